@@ -1,0 +1,444 @@
+"""Seeded synthetic workloads: meshes, partitions, element tangents and loads.
+
+This module only synthesises *inputs* to the solver: structured Q1/Q2 hexahedral
+box meshes (paper §2, "Space discretization": H1-conforming hexahedral elements of
+order 1 and 2), element-by-element tangent matrices of hyperelastic materials
+linearised at a given displacement (the Newton tangent of §2, eq. "tangent
+problem"), consistent body-force load vectors, homogeneous Dirichlet clamps and
+structured subdomain partitions (§3.2, non-overlapping decomposition).
+
+It holds none of the domain-decomposition arithmetic: no assembly of a global
+operator, no interface classification, no factorisation and no Krylov method.
+Both the solver library and the FP64 checker consume what it produces.
+
+Conventions
+-----------
+* Nodes of an ``nx x ny x nz`` element box of order ``p`` are numbered
+  lexicographically with x fastest: ``node(i, j, k) = i + Nx*(j + Ny*k)`` with
+  ``Nx = p*nx + 1``.
+* Element-local node ``(a, b, c)`` (each in ``0..p``) has local index
+  ``a + (p+1)*b + (p+1)**2*c``.
+* Degree of freedom ``3*node + comp`` (the strided block-size-3 layout of §4).
+* Element matrices are ``[n_el, 3*npe, 3*npe]`` in that local DOF order.
+* Boundary tag bits per node: 1:x=0, 2:x=Lx, 4:y=0, 8:y=Ly, 16:z=0, 32:z=Lz.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Optional
+
+import numpy as np
+
+HEX8 = 1
+HEX27 = 2
+
+
+# ----------------------------------------------------------------------------
+# reference element (tensor-product Lagrange on [0,1]^3) and Gauss rules
+# ----------------------------------------------------------------------------
+def _lagrange_1d(order: int, x: np.ndarray):
+    """Values and derivatives of the 1D Lagrange basis on equispaced points of [0,1]."""
+    x = np.asarray(x, dtype=np.float64)
+    if order == 1:
+        v = np.stack([1.0 - x, x])
+        d = np.stack([-np.ones_like(x), np.ones_like(x)])
+    elif order == 2:
+        v = np.stack([2.0 * (x - 0.5) * (x - 1.0), -4.0 * x * (x - 1.0), 2.0 * x * (x - 0.5)])
+        d = np.stack([4.0 * x - 3.0, -8.0 * x + 4.0, 4.0 * x - 1.0])
+    else:
+        raise ValueError("order must be 1 or 2")
+    return v, d  # [p+1, len(x)]
+
+
+def gauss_rule(npts: int):
+    """Tensor Gauss-Legendre rule on [0,1]^3: points [q,3], weights [q]."""
+    g, w = np.polynomial.legendre.leggauss(npts)
+    g = 0.5 * (g + 1.0)
+    w = 0.5 * w
+    pts, wts = [], []
+    for k in range(npts):
+        for j in range(npts):
+            for i in range(npts):
+                pts.append((g[i], g[j], g[k]))
+                wts.append(w[i] * w[j] * w[k])
+    return np.array(pts), np.array(wts)
+
+
+def shape_functions(order: int, pts: np.ndarray):
+    """N [q, npe] and dN/dxi [q, npe, 3] at reference points, lexicographic local order."""
+    p1 = order + 1
+    vx, dx = _lagrange_1d(order, pts[:, 0])
+    vy, dy = _lagrange_1d(order, pts[:, 1])
+    vz, dz = _lagrange_1d(order, pts[:, 2])
+    q = pts.shape[0]
+    N = np.empty((q, p1 ** 3))
+    dN = np.empty((q, p1 ** 3, 3))
+    for c in range(p1):
+        for b in range(p1):
+            for a in range(p1):
+                l = a + p1 * b + p1 * p1 * c
+                N[:, l] = vx[a] * vy[b] * vz[c]
+                dN[:, l, 0] = dx[a] * vy[b] * vz[c]
+                dN[:, l, 1] = vx[a] * dy[b] * vz[c]
+                dN[:, l, 2] = vx[a] * vy[b] * dz[c]
+    return N, dN
+
+
+# ----------------------------------------------------------------------------
+# meshes and partitions
+# ----------------------------------------------------------------------------
+@dataclasses.dataclass
+class Mesh:
+    coords: np.ndarray        # [n_nodes, 3] float64
+    elem_nodes: np.ndarray    # [n_el, npe] int32
+    order: int                # 1 (HEX8) or 2 (HEX27)
+    node_tags: np.ndarray     # [n_nodes] uint32 boundary-surface bitmask
+    shape: tuple = ()         # element counts per direction for boxes
+
+    @property
+    def elem_type(self) -> int:
+        return HEX8 if self.order == 1 else HEX27
+
+    @property
+    def n_nodes(self) -> int:
+        return self.coords.shape[0]
+
+    @property
+    def n_elems(self) -> int:
+        return self.elem_nodes.shape[0]
+
+    @property
+    def npe(self) -> int:
+        return self.elem_nodes.shape[1]
+
+
+def box_mesh(nx: int, ny: int, nz: int, order: int = 1, lengths=(1.0, 1.0, 1.0)) -> Mesh:
+    p = order
+    Nx, Ny, Nz = p * nx + 1, p * ny + 1, p * nz + 1
+    i = np.arange(Nx)
+    j = np.arange(Ny)
+    k = np.arange(Nz)
+    K, J, I = np.meshgrid(k, j, i, indexing="ij")
+    coords = np.stack([I.ravel() * lengths[0] / (p * nx),
+                       J.ravel() * lengths[1] / (p * ny),
+                       K.ravel() * lengths[2] / (p * nz)], axis=1)
+    I, J, K = I.ravel(), J.ravel(), K.ravel()
+    tags = ((I == 0) * 1 | (I == Nx - 1) * 2 | (J == 0) * 4 | (J == Ny - 1) * 8
+            | (K == 0) * 16 | (K == Nz - 1) * 32).astype(np.uint32)
+    ez, ey, ex = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    ex, ey, ez = ex.ravel(), ey.ravel(), ez.ravel()
+    p1 = p + 1
+    en = np.empty((nx * ny * nz, p1 ** 3), dtype=np.int64)
+    for c in range(p1):
+        for b in range(p1):
+            for a in range(p1):
+                en[:, a + p1 * b + p1 * p1 * c] = (p * ex + a) + Nx * ((p * ey + b) + Ny * (p * ez + c))
+    return Mesh(coords=coords, elem_nodes=en.astype(np.int32), order=order,
+                node_tags=tags, shape=(nx, ny, nz))
+
+
+def block_partition(mesh: Mesh, block) -> tuple[np.ndarray, int]:
+    """Element -> subdomain map for axis-aligned blocks of ``block`` elements per direction."""
+    nx, ny, nz = mesh.shape
+    bx, by, bz = (block, block, block) if np.isscalar(block) else block
+    sx, sy, sz = -(-nx // bx), -(-ny // by), -(-nz // bz)
+    e = np.arange(nx * ny * nz)
+    ex, ey, ez = e % nx, (e // nx) % ny, e // (nx * ny)
+    part = (ex // bx) + sx * ((ey // by) + sy * (ez // bz))
+    return part.astype(np.int32), sx * sy * sz
+
+
+def clamp_dofs(mesh: Mesh, tag_bit: int = 1) -> np.ndarray:
+    """All three DOFs of every node carrying ``tag_bit`` (default: face x=0)."""
+    nodes = np.nonzero(mesh.node_tags & tag_bit)[0]
+    return np.sort((3 * nodes[:, None] + np.arange(3)[None, :]).ravel()).astype(np.int32)
+
+
+# ----------------------------------------------------------------------------
+# seeded smooth fields
+# ----------------------------------------------------------------------------
+def smooth_field(X: np.ndarray, seed: int, amplitude: float, n_modes: int = 8) -> np.ndarray:
+    """u(X) = sum_m a_m sin(pi k_m.X + phi_m), k_m in {1,2}^3, a_m ~ N(0, I3),
+    phi_m ~ U[0, 2pi), rescaled so that max_nodes |u| = amplitude."""
+    rng = np.random.default_rng(seed)
+    kvec = rng.integers(1, 3, size=(n_modes, 3)).astype(np.float64)
+    amp = rng.standard_normal((n_modes, 3))
+    phase = rng.uniform(0.0, 2.0 * np.pi, size=n_modes)
+    arg = np.pi * X @ kvec.T + phase[None, :]          # [n, m]
+    u = np.sin(arg) @ amp                               # [n, 3]
+    mx = np.max(np.linalg.norm(u, axis=1))
+    return u * (amplitude / mx) if mx > 0 else u
+
+
+def isochoric_field(X: np.ndarray, seed: int, amplitude: float, n_modes: int = 8) -> np.ndarray:
+    """Divergence-free displacement u = curl(x^2 psi), psi the seeded 8-mode sine field,
+    rescaled to max_nodes |u| = amplitude. It vanishes on the clamped face x = 0 and keeps
+    J = 1 + O(|grad u|^2), the natural state of a nearly incompressible solid."""
+    rng = np.random.default_rng(seed)
+    kvec = rng.integers(1, 3, size=(n_modes, 3)).astype(np.float64)
+    amp = rng.standard_normal((n_modes, 3))
+    phase = rng.uniform(0.0, 2.0 * np.pi, size=n_modes)
+    arg = np.pi * X @ kvec.T + phase[None, :]
+    psi = np.sin(arg) @ amp                                             # [n, 3]
+    gpsi = np.einsum("nm,mj,mi->nji", np.cos(arg), amp, np.pi * kvec)   # d psi_j / d X_i
+    curl = np.stack([gpsi[:, 2, 1] - gpsi[:, 1, 2], gpsi[:, 0, 2] - gpsi[:, 2, 0],
+                     gpsi[:, 1, 0] - gpsi[:, 0, 1]], axis=1)
+    x = X[:, 0]
+    gx2 = np.zeros_like(X)
+    gx2[:, 0] = 2.0 * x
+    u = np.cross(gx2, psi) + (x * x)[:, None] * curl
+    mx = np.max(np.linalg.norm(u, axis=1))
+    return u * (amplitude / mx) if mx > 0 else u
+
+
+# ----------------------------------------------------------------------------
+# materials: second Piola-Kirchhoff stress S and material tangent C = dS/dE
+# (the Newton tangent of a hyperelastic potential, paper §2)
+# ----------------------------------------------------------------------------
+def _eye3():
+    return np.eye(3)
+
+
+def linear_elastic(E: float = 1.0, nu: float = 0.3):
+    lam = E * nu / ((1 + nu) * (1 - 2 * nu))
+    mu = E / (2 * (1 + nu))
+    return {"kind": "svk", "lam": lam, "mu": mu}
+
+
+def neo_hookean(mu: float = 1.0, kappa: float = 50.0):
+    return {"kind": "neo_hookean", "mu": mu, "lam": kappa - 2.0 * mu / 3.0}
+
+
+def _stress_tangent(mat, F):
+    """F [m,3,3] -> S [m,3,3], CC [m,3,3,3,3] (dS/dE, major-symmetric)."""
+    I = _eye3()
+    m = F.shape[0]
+    if mat["kind"] == "svk":
+        # Saint Venant-Kirchhoff: the linear-elastic law written on E.
+        lam, mu = mat["lam"], mat["mu"]
+        C = np.einsum("mki,mkj->mij", F, F)
+        E = 0.5 * (C - I)
+        trE = np.trace(E, axis1=1, axis2=2)
+        S = lam * trE[:, None, None] * I + 2 * mu * E
+        CC = (lam * np.einsum("ij,kl->ijkl", I, I)
+              + mu * (np.einsum("ik,jl->ijkl", I, I) + np.einsum("il,jk->ijkl", I, I)))
+        CC = np.broadcast_to(CC, (m, 3, 3, 3, 3)).copy()
+        return S, CC
+    if mat["kind"] == "neo_hookean":
+        # Psi = mu/2 (I1 - 3) - mu ln J + lam/2 (ln J)^2
+        lam, mu = mat["lam"], mat["mu"]
+        C = np.einsum("mki,mkj->mij", F, F)
+        J = np.linalg.det(F)
+        if np.any(J <= 0):
+            raise ValueError("non-positive Jacobian at a quadrature point")
+        Ci = np.linalg.inv(C)
+        lnJ = np.log(J)
+        S = mu * (I - Ci) + (lam * lnJ)[:, None, None] * Ci
+        CC = (lam * np.einsum("mij,mkl->mijkl", Ci, Ci)
+              + (mu - lam * lnJ)[:, None, None, None, None]
+              * (np.einsum("mik,mjl->mijkl", Ci, Ci) + np.einsum("mil,mjk->mijkl", Ci, Ci)))
+        return S, CC
+    if mat["kind"] == "guccione":
+        return _guccione(mat, F)
+    raise ValueError(mat["kind"])
+
+
+def guccione(C: float = 0.88, bf: float = 8.0, bt: float = 2.0, bfs: float = 2.0, B: float = 50.0):
+    return {"kind": "guccione", "C": C, "bf": bf, "bt": bt, "bfs": bfs, "B": B}
+
+
+def _guccione(mat, F):
+    """Guccione exponential law in the fibre frame plus B/2 (J-1) ln J (paper §2).
+    ``mat['frames']`` holds the per-point rotation Q [m,3,3] whose rows are f, s, n."""
+    I = _eye3()
+    Q = mat["frames"]
+    Cm, bf, bt, bfs, B = mat["C"], mat["bf"], mat["bt"], mat["bfs"], mat["B"]
+    Cg = np.einsum("mki,mkj->mij", F, F)
+    E = 0.5 * (Cg - I)
+    Ef = np.einsum("mai,mij,mbj->mab", Q, E, Q)           # E in the fibre frame
+    b = np.array([[bf, bfs, bfs], [bfs, bt, bt], [bfs, bt, bt]])
+    Qv = np.einsum("ab,mab->m", b, Ef * Ef)
+    eQ = np.exp(Qv)
+    # S_frame = C e^Q b.E_frame ; C_frame = C e^Q (2 (b.E)(b.E) + diag-b)
+    bE = b[None] * Ef
+    S_f = Cm * eQ[:, None, None] * bE
+    Cf = Cm * eQ[:, None, None, None, None] * (2.0 * np.einsum("mab,mcd->mabcd", bE, bE)
+                                              + 0.5 * (np.einsum("ab,ac,bd->abcd", b, I, I)
+                                                       + np.einsum("ab,ad,bc->abcd", b, I, I))[None])
+    S = np.einsum("mai,mab,mbj->mij", Q, S_f, Q)
+    CC = np.einsum("mai,mbj,mck,mdl,mabcd->mijkl", Q, Q, Q, Q, Cf)
+    # volumetric part W(J) = B/2 (J-1) ln J:  S_vol = J W'(J) C^-1
+    J = np.linalg.det(F)
+    if np.any(J <= 0):
+        raise ValueError("non-positive Jacobian at a quadrature point")
+    Ci = np.linalg.inv(Cg)
+    lnJ = np.log(J)
+    W1 = 0.5 * B * (lnJ + (J - 1.0) / J)
+    W2 = 0.5 * B * (1.0 / J + 1.0 / (J * J))
+    a1 = J * W1
+    a2 = J * W1 + J * J * W2
+    S = S + a1[:, None, None] * Ci
+    CC = CC + (a2[:, None, None, None, None] * np.einsum("mij,mkl->mijkl", Ci, Ci)
+               - a1[:, None, None, None, None]
+               * (np.einsum("mik,mjl->mijkl", Ci, Ci) + np.einsum("mil,mjk->mijkl", Ci, Ci)))
+    return S, CC
+
+
+# ----------------------------------------------------------------------------
+# element tangents / internal forces / loads (Gauss quadrature, isoparametric)
+# ----------------------------------------------------------------------------
+def _elem_geometry(mesh: Mesh, elems: np.ndarray, dNq: np.ndarray):
+    """For one quadrature point: dN/dX [e, npe, 3] and det J [e]."""
+    Xe = mesh.coords[mesh.elem_nodes[elems]]                 # [e, npe, 3]
+    Jm = np.einsum("eai,aj->eij", Xe, dNq)                   # dX/dxi
+    det = np.linalg.det(Jm)
+    if np.any(det <= 0):
+        raise ValueError("inverted element")
+    Jinv = np.linalg.inv(Jm)
+    dNX = np.einsum("aj,eji->eai", dNq, Jinv)
+    return dNX, det
+
+
+def element_tangents(mesh: Mesh, material, u: Optional[np.ndarray] = None,
+                     chunk: int = 4096, frames_fn=None) -> np.ndarray:
+    """K_e[(a,i),(b,k)] = sum_q w |J| dN_a/dX_J A_iJkL dN_b/dX_L with
+    A_iJkL = delta_ik S_JL + F_iI F_kK C_IJKL, for every element (float64)."""
+    order = mesh.order
+    pts, wts = gauss_rule(order + 1)
+    _, dN = shape_functions(order, pts)
+    npe = mesh.npe
+    nd = 3 * npe
+    out = np.zeros((mesh.n_elems, nd, nd))
+    I = _eye3()
+    for e0 in range(0, mesh.n_elems, chunk):
+        elems = np.arange(e0, min(mesh.n_elems, e0 + chunk))
+        ue = None if u is None else u[mesh.elem_nodes[elems]]   # [e, npe, 3]
+        Ke = np.zeros((len(elems), npe, 3, npe, 3))
+        for q in range(len(wts)):
+            dNX, det = _elem_geometry(mesh, elems, dN[q])
+            if ue is None:
+                F = np.broadcast_to(I, (len(elems), 3, 3)).copy()
+            else:
+                F = I + np.einsum("eai,eaJ->eiJ", ue, dNX)
+            mat = material
+            if frames_fn is not None:
+                mat = dict(material)
+                mat["frames"] = frames_fn(elems, q)
+            S, CC = _stress_tangent(mat, F)
+            A = (np.einsum("ik,mJL->miJkL", I, S)
+                 + np.einsum("miI,mkK,mIJKL->miJkL", F, F, CC, optimize=True))
+            wdet = wts[q] * det
+            Bm = np.einsum("eaJ,eiJkL->eaikL", dNX, A, optimize=True)
+            Ke += wdet[:, None, None, None, None] * np.einsum("eaikL,ebL->eaibk", Bm, dNX, optimize=True)
+        out[elems] = Ke.reshape(len(elems), nd, nd)
+    return out
+
+
+def element_internal_forces(mesh: Mesh, material, u: np.ndarray, frames_fn=None) -> np.ndarray:
+    """f_e[(a,i)] = sum_q w |J| P_iJ dN_a/dX_J with P = F S (used to check tangents)."""
+    order = mesh.order
+    pts, wts = gauss_rule(order + 1)
+    _, dN = shape_functions(order, pts)
+    elems = np.arange(mesh.n_elems)
+    ue = u[mesh.elem_nodes]
+    fe = np.zeros((mesh.n_elems, mesh.npe, 3))
+    for q in range(len(wts)):
+        dNX, det = _elem_geometry(mesh, elems, dN[q])
+        F = np.eye(3) + np.einsum("eai,eaJ->eiJ", ue, dNX)
+        mat = material
+        if frames_fn is not None:
+            mat = dict(material)
+            mat["frames"] = frames_fn(elems, q)
+        S, _ = _stress_tangent(mat, F)
+        P = np.einsum("miI,mIJ->miJ", F, S)
+        fe += (wts[q] * det)[:, None, None] * np.einsum("eiJ,eaJ->eai", P, dNX)
+    return fe.reshape(mesh.n_elems, 3 * mesh.npe)
+
+
+def body_force_load(mesh: Mesh, force_at_nodes: np.ndarray) -> np.ndarray:
+    """Consistent load b_(a,i) = sum_e sum_q w |J| N_a f_i(X_q), f interpolated from nodal
+    values [n_nodes, 3]; returned as a full DOF vector [3*n_nodes]."""
+    order = mesh.order
+    pts, wts = gauss_rule(order + 1)
+    N, dN = shape_functions(order, pts)
+    elems = np.arange(mesh.n_elems)
+    fnod = force_at_nodes[mesh.elem_nodes]                     # [e, npe, 3]
+    fe = np.zeros((mesh.n_elems, mesh.npe, 3))
+    for q in range(len(wts)):
+        _, det = _elem_geometry(mesh, elems, dN[q])
+        fq = np.einsum("a,eai->ei", N[q], fnod)
+        fe += (wts[q] * det)[:, None, None] * N[q][None, :, None] * fq[:, None, :]
+    b = np.zeros(3 * mesh.n_nodes)
+    np.add.at(b, (3 * mesh.elem_nodes[:, :, None] + np.arange(3)[None, None, :]).ravel(), fe.ravel())
+    return b
+
+
+# ----------------------------------------------------------------------------
+# complete problem instances
+# ----------------------------------------------------------------------------
+@dataclasses.dataclass
+class Problem:
+    """One tangent system: mesh, partition, clamps, element tangents and right-hand sides."""
+    name: str
+    mesh: Mesh
+    elem_part: np.ndarray     # [n_el] int32
+    n_sub: int
+    dirichlet: np.ndarray     # [n_dir] int32 DOF ids (homogeneous)
+    Ke: np.ndarray            # [n_el, 3npe, 3npe] float64
+    rhs: np.ndarray           # [nrhs, 3*n_nodes] float64, zero on Dirichlet DOFs
+    primal: int               # bitmask V=1, E=2, F=4
+    meta: dict = dataclasses.field(default_factory=dict)
+
+    @property
+    def n_dofs(self) -> int:
+        return 3 * self.mesh.n_nodes
+
+
+def _loads(mesh: Mesh, dirichlet: np.ndarray, nrhs: int, seed: int) -> np.ndarray:
+    f0 = np.zeros((mesh.n_nodes, 3))
+    f0[:, 2] = -1.0
+    out = [body_force_load(mesh, f0)]
+    for j in range(1, nrhs):
+        fj = smooth_field(mesh.coords, seed + j, 1.0)
+        out.append(body_force_load(mesh, fj))
+    rhs = np.stack(out)
+    rhs[:, dirichlet] = 0.0
+    return rhs
+
+
+def linear_box(n: int = 8, block: int = 4, order: int = 1, nrhs: int = 1, E: float = 1.0,
+               nu: float = 0.3, primal: int = 1, seed: int = 1, name: str = "linear_box") -> Problem:
+    """Linear elasticity on the unit cube, x=0 clamped, body force (0,0,-1)."""
+    mesh = box_mesh(n, n, n, order)
+    part, nsub = block_partition(mesh, block)
+    dirichlet = clamp_dofs(mesh, 1)
+    Ke = element_tangents(mesh, linear_elastic(E, nu))
+    rhs = _loads(mesh, dirichlet, nrhs, seed)
+    return Problem(name, mesh, part, nsub, dirichlet, Ke, rhs, primal,
+                   {"material": "linear", "E": E, "nu": nu, "n": n, "block": block, "order": order})
+
+
+def neo_hookean_box(n: int = 32, block: int = 4, order: int = 1, nrhs: int = 4, mu: float = 1.0,
+                    kappa: float = 50.0, amplitude: float = 0.05, field_seed: int = 0,
+                    rhs_seed: int = 1, primal: int = 3, name: str = "neo_hookean_box") -> Problem:
+    """Compressible neo-Hookean tangent linearised at a seeded isochoric 8-mode field."""
+    mesh = box_mesh(n, n, n, order)
+    part, nsub = block_partition(mesh, block)
+    dirichlet = clamp_dofs(mesh, 1)
+    u = isochoric_field(mesh.coords, field_seed, amplitude)
+    Ke = element_tangents(mesh, neo_hookean(mu, kappa), u)
+    rhs = _loads(mesh, dirichlet, nrhs, rhs_seed)
+    return Problem(name, mesh, part, nsub, dirichlet, Ke, rhs, primal,
+                   {"material": "neo_hookean", "mu": mu, "kappa": kappa, "n": n, "block": block,
+                    "order": order, "amplitude": amplitude, "field_seed": field_seed})
+
+
+def config_small() -> Problem:
+    """8^3 Q1 unit cube, linear elasticity E=1 nu=0.3, 2x2x2 subdomains of 4^3, primal V."""
+    return linear_box(8, 4, 1, nrhs=1, primal=1, name="linear_8cube_2x2x2_V")
+
+
+def config_nh32(nrhs: int = 4) -> Problem:
+    """32^3 Q1 neo-Hookean (mu=1, kappa=50) at the 8-mode field, 512 subdomains of 4^3, primal VE."""
+    return neo_hookean_box(32, 4, 1, nrhs=nrhs, primal=3, name="neo_hookean_32cube_512sub_VE")

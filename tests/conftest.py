@@ -1,0 +1,46 @@
+"""Shared fixtures. Tests marked ``gpu`` need an MI355X and the built HIP library."""
+import functools
+import os
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def pytest_configure(config):
+    config.addinivalue_line("markers", "gpu: needs an AMD MI355X GPU and the built HIP library")
+    config.addinivalue_line("markers", "slow: takes more than a few seconds on the CPU")
+
+
+@functools.lru_cache(maxsize=None)
+def problem(name: str):
+    """Seeded problems shared across test modules (built once per session)."""
+    from paper_2208_06191_amd import workloads as W
+    if name == "small":            # 8^3 Q1 linear elasticity, 2x2x2 subdomains, primal V
+        return W.config_small()
+    if name == "small_ve":
+        return W.linear_box(8, 4, 1, nrhs=2, primal=3, name="small_ve")
+    if name == "tiny":             # 6^3 Q1, 2x2x2 subdomains of 3^3
+        return W.linear_box(6, 3, 1, nrhs=1, primal=1, name="tiny")
+    if name == "tiny_nh":          # neo-Hookean tangent on 8^3, 2x2x2 subdomains, VE
+        return W.neo_hookean_box(8, 4, 1, nrhs=2, amplitude=0.02, primal=3, name="tiny_nh")
+    if name == "tiny_q2":          # Q2 on 4^3 elements, 2x2x2 subdomains of 2^3
+        return W.linear_box(4, 2, 2, nrhs=1, primal=3, name="tiny_q2")
+    if name == "ragged":           # 6x5x7 Q1 box, blocks of 4 -> uneven subdomains
+        from paper_2208_06191_amd.workloads import Problem
+        mesh = W.box_mesh(6, 5, 7, 1)
+        part, nsub = W.block_partition(mesh, 4)
+        dirichlet = W.clamp_dofs(mesh, 1)
+        u = W.isochoric_field(mesh.coords, 3, 0.02)
+        Ke = W.element_tangents(mesh, W.neo_hookean(1.0, 50.0), u)
+        rhs = W._loads(mesh, dirichlet, 2, 5)
+        return Problem("ragged", mesh, part, nsub, dirichlet, Ke, rhs, 3, {})
+    raise KeyError(name)
+
+
+@pytest.fixture
+def get_problem():
+    return problem

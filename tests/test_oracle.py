@@ -1,0 +1,360 @@
+"""Pins for the FP64 oracle (paper §3.2), against facts fixed by the mathematics.
+
+* glob counts on structured box partitions equal closed forms (derived below)
+  and a brute-force geometric classification of subdomain corners/edges/faces;
+* one subdomain, or every interface DOF primal, makes BDDC an exact inverse;
+* lambda_min(M^-1 A) >= 1 on SPD problems (the BDDC lower bound);
+* M^-1 is symmetric when A is;
+* the Lagrange-multiplier form equals the paper's explicit-primal formula
+  (R_GammaDelta, R_GammaPi, Phi, S_PiPi as printed in §3.2) for vertex primals;
+* the coarse basis satisfies C Phi = I, A Phi = -C^T Lambda, Phi^T A Phi = -Lambda,
+  and is energy-minimal;
+* floating subdomains carry exactly the six rigid motions in their kernel;
+* constraint-row scaling leaves the preconditioner unchanged;
+* three levels with a single level-2 subdomain reduce to two levels;
+* GMRES with M = I follows scipy's restarted GMRES, and BDDC-GMRES solutions
+  match a direct solve.
+"""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+import scipy.sparse.linalg as spla
+
+from paper_2208_06191_amd import workloads as W
+from oracle import bddc, fem, gmres
+from tests.conftest import problem
+
+
+def decomp(P, primal=None, **kw):
+    return bddc.Decomposition(P.mesh.elem_nodes, P.mesh.n_nodes, P.elem_part, P.n_sub, P.dirichlet,
+                              P.mesh.node_tags, primal=P.primal if primal is None else primal, **kw)
+
+
+# --------------------------------------------------------------------------------------------
+# glob classification
+# --------------------------------------------------------------------------------------------
+def closed_form_counts(S):
+    """S x S x S box subdomains, face x=0 clamped (all three components).
+
+    Subdomain corner coordinates take S+1 values per axis, S-1 of them internal.
+    * vertices: corners off the clamped face (x in 1..S) with at least one internal
+      coordinate: S (S+1)^2 minus the 4 corners with x = S and y, z on the boundary;
+    * edges: segments between consecutive corners along one axis whose two fixed
+      coordinates include an internal one; segments lying in the clamped face drop out;
+      along x: S ((S+1)^2 - 4); along y or z: S (S (S+1) - 2) each;
+    * faces: internal planes cut into S x S patches: 3 (S-1) S^2."""
+    V = S * (S + 1) ** 2 - 4
+    E = S * ((S + 1) ** 2 - 4) + 2 * S * (S * (S + 1) - 2)
+    F = 3 * (S - 1) * S * S
+    return V, E, F
+
+
+@pytest.mark.parametrize("S,block", [(2, 4), (2, 3), (3, 3), (4, 3)])
+def test_glob_counts_closed_form(S, block):
+    P = W.linear_box(S * block, block, 1, nrhs=1, primal=7)
+    dec = decomp(P)
+    V, E, F = closed_form_counts(S)
+    assert dec.glob_counts() == (V, E, F)
+    for mask, n in ((1, V), (3, V + E), (7, V + E + F), (6, E + F)):
+        assert decomp(P, mask).n_coarse == 3 * n
+
+
+def test_one_node_edges_and_faces_become_vertices():
+    # blocks of 2 Q1 elements: every edge segment and face patch holds a single node
+    V, E, F = closed_form_counts(2)
+    P = W.linear_box(4, 2, 1, nrhs=1, primal=7)
+    assert decomp(P).glob_counts() == (V + E + F, 0, 0)
+
+
+def test_glob_counts_paper_scale_box():
+    # 32^3 mesh, 8^3 subdomains: the sizes of the 512-subdomain neo-Hookean workload
+    mesh = W.box_mesh(32, 32, 32, 1)
+    part, nsub = W.block_partition(mesh, 4)
+    dec = bddc.Decomposition(mesh.elem_nodes, mesh.n_nodes, part, nsub, W.clamp_dofs(mesh),
+                             mesh.node_tags, primal=3)
+    assert dec.glob_counts() == closed_form_counts(8) == (644, 1736, 1344)
+    assert dec.n_coarse == 7140
+
+
+@pytest.mark.parametrize("S,block,order", [(2, 4, 1), (3, 3, 1), (2, 2, 2)])
+def test_globs_equal_geometric_classification(S, block, order):
+    """Brute force: on a box partition a glob is a corner, the open segment between two
+    corners, or an open face patch; classify each interface node by how many of its
+    coordinates sit on a block boundary plane and by which segment/patch it is in."""
+    n = S * block
+    P = W.linear_box(n, block, order, nrhs=1, primal=7)
+    dec = decomp(P)
+    p = order
+    geo = {}
+    Nx = p * n + 1
+    for nd in range(P.mesh.n_nodes):
+        if not dec.interface_node[nd]:
+            continue
+        ijk = (nd % Nx, (nd // Nx) % Nx, nd // (Nx * Nx))
+        on = [c % (p * block) == 0 for c in ijk]
+        blk = [c // (p * block) for c in ijk]
+        key = tuple(("c", c) if o else ("b", b) for c, o, b in zip(ijk, on, blk))
+        geo.setdefault(key, []).append(nd)
+    kinds = {3: bddc.VERTEX, 2: bddc.EDGE, 1: bddc.FACE}
+    expect = sorted((kinds[sum(k[0] == "c" for k in key)], tuple(v)) for key, v in geo.items())
+    got = sorted((g[0], tuple(g[1])) for g in dec.globs)
+    assert got == expect
+
+
+# --------------------------------------------------------------------------------------------
+# coarse basis and local problems
+# --------------------------------------------------------------------------------------------
+def test_coarse_basis_properties():
+    P = problem("small_ve")
+    dec = decomp(P)
+    B = bddc.BDDC(dec, P.mesh.elem_nodes, P.Ke)
+    rng = np.random.default_rng(0)
+    for sd, L in zip(dec.subdomains, B.L1.loc):
+        K, Phi, Lam, C = L["K"], L["Phi"], L["Lam"], sd.C
+        assert np.abs(C @ Phi - np.eye(C.shape[0])).max() < 1e-12
+        assert np.abs(K @ Phi + C.T @ Lam).max() < 1e-10 * np.abs(K).max()
+        assert np.abs(Phi.T @ K @ Phi + Lam).max() < 1e-10 * np.abs(Lam).max()
+        # energy minimality: any perturbation that keeps C v = I raises the energy
+        Z = sla.null_space(C)
+        for _ in range(3):
+            D = Z @ rng.standard_normal((Z.shape[1], C.shape[0])) * 1e-2
+            assert np.trace((Phi + D).T @ K @ (Phi + D)) > np.trace(Phi.T @ K @ Phi)
+    ev = np.linalg.eigvalsh(B.Kc)
+    assert ev.min() > 0 and np.abs(B.Kc - B.Kc.T).max() < 1e-12 * np.abs(B.Kc).max()
+
+
+def test_floating_subdomain_kernel_is_rigid_motions():
+    P = problem("small")
+    dec = decomp(P)
+    Ks = bddc.local_matrices(dec, P.mesh.elem_nodes, P.Ke)
+    floating = [i for i, el in enumerate(dec.sub_elems)
+                if not np.any(P.mesh.node_tags[P.mesh.elem_nodes[el]] & 1)]
+    assert floating, "expected subdomains away from the clamp"
+    R = fem.rigid_body_modes(P.mesh.coords)
+    for i in floating:
+        K = Ks[i]
+        Ri = R[dec.local_dofs[i]]
+        assert np.abs(K @ Ri).max() < 1e-12 * np.abs(K).max()
+        ev = np.linalg.eigvalsh(K)
+        assert np.sum(np.abs(ev) < 1e-10 * ev.max()) == 6
+        sd = dec.subdomains[i]
+        nc = sd.C.shape[0]
+        N = np.block([[K, sd.C.T], [sd.C, np.zeros((nc, nc))]])
+        assert np.linalg.matrix_rank(N) == N.shape[0]
+
+
+# --------------------------------------------------------------------------------------------
+# exactness pins
+# --------------------------------------------------------------------------------------------
+def skew_perturbed(P, eps=0.05, seed=3):
+    """Make the tangent nonsymmetric (as follower loads do) to expose transposed operands."""
+    rng = np.random.default_rng(seed)
+    S = rng.standard_normal(P.Ke.shape)
+    S = S - np.transpose(S, (0, 2, 1))
+    return P.Ke + eps * np.abs(P.Ke).max() * S
+
+
+@pytest.mark.parametrize("nonsym", [False, True])
+def test_one_subdomain_is_exact(nonsym):
+    P = problem("tiny")
+    part = np.zeros_like(P.elem_part)
+    Ke = skew_perturbed(P) if nonsym else P.Ke
+    dec = bddc.Decomposition(P.mesh.elem_nodes, P.mesh.n_nodes, part, 1, P.dirichlet, P.mesh.node_tags, 1)
+    B = bddc.BDDC(dec, P.mesh.elem_nodes, Ke)
+    b = P.rhs[0][dec.free]
+    z = B.apply(b)
+    x = spla.spsolve(B.A.tocsc(), b)
+    assert np.linalg.norm(z - x) < 1e-12 * np.linalg.norm(x)
+    r = gmres.gmres(lambda v: B.A @ v, B.apply, b, 1e-8, 30, 10)
+    assert r.iterations == 1 and r.converged
+
+
+@pytest.mark.parametrize("nonsym", [False, True])
+@pytest.mark.parametrize("name", ["tiny", "tiny_q2"])
+def test_all_interface_primal_is_exact(name, nonsym):
+    P = problem(name)
+    Ke = skew_perturbed(P) if nonsym else P.Ke
+    dec = decomp(P, all_interface_vertices=True)
+    B = bddc.BDDC(dec, P.mesh.elem_nodes, Ke)
+    rng = np.random.default_rng(1)
+    r = rng.standard_normal(len(dec.free))
+    z = B.apply(r)
+    x = spla.spsolve(B.A.tocsc(), r)
+    assert np.linalg.norm(z - x) < 1e-11 * np.linalg.norm(x)
+
+
+def dense_precond(B, n):
+    return np.stack([B.apply(e) for e in np.eye(n)], axis=1)
+
+
+@pytest.mark.parametrize("name,primal", [("tiny", 1), ("tiny", 3), ("tiny_q2", 1), ("tiny_q2", 7)])
+def test_bddc_lower_bound_and_symmetry(name, primal):
+    P = problem(name)
+    dec = decomp(P, primal)
+    B = bddc.BDDC(dec, P.mesh.elem_nodes, P.Ke)
+    n = len(dec.free)
+    M = dense_precond(B, n)
+    assert np.abs(M - M.T).max() < 1e-10 * np.abs(M).max()
+    ev = np.linalg.eigvals(M @ B.A.toarray())
+    assert np.abs(ev.imag).max() < 1e-8
+    assert ev.real.min() > 1 - 1e-10
+    assert ev.real.max() > 1.5           # a genuine (inexact) preconditioner
+
+
+def test_nonsymmetric_lower_bound_not_needed_but_solution_exact():
+    P = problem("tiny")
+    Ke = skew_perturbed(P, 0.02)
+    dec = decomp(P, 3)
+    B = bddc.BDDC(dec, P.mesh.elem_nodes, Ke)
+    b = P.rhs[0][dec.free]
+    res = gmres.gmres(lambda v: B.A @ v, B.apply, b, 1e-10, 30, 200)
+    x = spla.spsolve(B.A.tocsc(), b)
+    assert res.converged and np.linalg.norm(res.x - x) < 1e-8 * np.linalg.norm(x)
+
+
+def test_constraint_row_scaling_invariance():
+    P = problem("small_ve")
+    dec = decomp(P)
+    B1 = bddc.BDDC(dec, P.mesh.elem_nodes, P.Ke)
+    rng = np.random.default_rng(4)
+    scale = rng.uniform(0.1, 10.0, size=dec.n_coarse)      # one factor per coarse DOF
+    for sd in dec.subdomains:
+        sd.C = sd.C * scale[sd.coarse][:, None]
+    B2 = bddc.BDDC(dec, P.mesh.elem_nodes, P.Ke)
+    r = rng.standard_normal(len(dec.free))
+    z1, z2 = B1.apply(r), B2.apply(r)
+    assert np.linalg.norm(z1 - z2) < 1e-11 * np.linalg.norm(z1)
+
+
+def test_paper_explicit_primal_formula_equals_lagrange_form():
+    """For vertex primals the primal DOFs are ordinary DOFs, so the §3.2 formulas apply as
+    printed: M^-1 = R_{D,Gamma}^T S~^-1 R_{D,Gamma} on the space V_Delta (+) V^_Pi."""
+    P = problem("tiny")
+    dec = decomp(P, 1)
+    B = bddc.BDDC(dec, P.mesh.elem_nodes, P.Ke)
+    Ks = bddc.local_matrices(dec, P.mesh.elem_nodes, P.Ke)
+    G = B.L1.G                                # free-vector positions of the interface
+    gpos = {int(g): k for k, g in enumerate(G)}
+    prim = sorted({int(dec.free_pos[3 * dec.globs[gi][1][0] + c]) for gi, c in dec.coarse})
+    ppos = {g: k for k, g in enumerate(prim)}
+    nG, nP = len(G), len(prim)
+    # dual copies: (subdomain, dual DOF)
+    duals = []
+    for i, sd in enumerate(dec.subdomains):
+        for k in range(sd.n_interior, len(sd.dofs)):
+            if int(sd.dofs[k]) not in ppos:
+                duals.append((i, int(sd.dofs[k])))
+    dpos = {d: k for k, d in enumerate(duals)}
+    nD = len(duals)
+    RGD = np.zeros((nD, nG))                  # R_GammaDelta: V^_Gamma -> V_Delta (0/1)
+    RDD = np.zeros((nD, nG))                  # weighted: delta^dagger on the dual part
+    for (i, g), k in dpos.items():
+        RGD[k, gpos[g]] = 1.0
+        RDD[k, gpos[g]] = 1.0 / len(dec.node_subs[dec.free[g] // 3])
+    RGP = np.zeros((nP, nG))                  # R_GammaPi (unweighted)
+    for g, k in ppos.items():
+        RGP[k, gpos[g]] = 1.0
+    Sinv = np.zeros((nD + nP, nD + nP))
+    Phi = np.zeros((nD + nP, nP))
+    Phi[nD:, :] = np.eye(nP)                  # R_GammaPi^T part of Phi
+    SPP = np.zeros((nP, nP))
+    for i, (sd, K) in enumerate(zip(dec.subdomains, Ks)):
+        loc = [int(d) for d in sd.dofs]
+        I = list(range(sd.n_interior))
+        D = [k for k in range(sd.n_interior, len(loc)) if loc[k] not in ppos]
+        Pi = [k for k in range(sd.n_interior, len(loc)) if loc[k] in ppos]
+        ID = I + D
+        Kr = K[np.ix_(ID, ID)]
+        Kinv = np.linalg.inv(Kr)
+        KrP = K[np.ix_(ID, Pi)]
+        RD = np.zeros((len(D), nD))           # R_Delta^(i)
+        for a, k in enumerate(D):
+            RD[a, dpos[(i, loc[k])]] = 1.0
+        RP = np.zeros((len(Pi), nP))          # R_Pi^(i)
+        for a, k in enumerate(Pi):
+            RP[a, ppos[loc[k]]] = 1.0
+        E = np.zeros((len(ID), len(D)))       # [0; R_Delta^T] selector of the Delta block
+        E[len(I):, :] = np.eye(len(D))
+        Sinv[:nD, :nD] += RD.T @ E.T @ Kinv @ E @ RD
+        Phi[:nD, :] -= RD.T @ E.T @ Kinv @ KrP @ RP
+        SPP += RP.T @ (K[np.ix_(Pi, Pi)] - K[np.ix_(Pi, ID)] @ Kinv @ KrP) @ RP
+    Sinv += Phi @ np.linalg.inv(SPP) @ Phi.T
+    RD_G = np.vstack([RDD, RGP])              # R_{D,Gamma}
+    M_paper = RD_G.T @ Sinv @ RD_G
+    M_orc = np.stack([B.L1.interface_precond(_unit(len(dec.free), G[k]))[G] for k in range(nG)], axis=1)
+    assert np.abs(M_paper - M_orc).max() < 1e-10 * np.abs(M_orc).max()
+
+
+def _unit(n, k):
+    e = np.zeros(n)
+    e[k] = 1.0
+    return e
+
+
+def test_three_levels_with_one_group_equal_two_levels():
+    P = problem("small_ve")
+    dec = decomp(P)
+    B2 = bddc.BDDC(dec, P.mesh.elem_nodes, P.Ke, levels=2)
+    B3 = bddc.BDDC(dec, P.mesh.elem_nodes, P.Ke, levels=3, coarse_group=8)
+    r = np.random.default_rng(5).standard_normal(len(dec.free))
+    z2, z3 = B2.apply(r), B3.apply(r)
+    assert np.linalg.norm(z2 - z3) < 1e-11 * np.linalg.norm(z2)
+
+
+# --------------------------------------------------------------------------------------------
+# Krylov method and end-to-end
+# --------------------------------------------------------------------------------------------
+def test_gmres_identity_preconditioner_matches_scipy():
+    P = problem("tiny")
+    dec = decomp(P)
+    A = fem.reduce_to_free(fem.assemble(P.mesh.elem_nodes, P.Ke, dec.n_dofs), dec.free)
+    b = P.rhs[0][dec.free]
+    mine = gmres.gmres(lambda v: A @ v, lambda v: v, b, 1e-8, 30, 2000)
+    count = [0]
+
+    def cb(_):
+        count[0] += 1
+    x, info = spla.gmres(A, b, rtol=1e-8, restart=30, maxiter=200, callback=cb,
+                         callback_type="pr_norm")
+    assert info == 0
+    assert abs(mine.iterations - count[0]) <= 1
+    assert np.linalg.norm(mine.x - x) < 1e-6 * np.linalg.norm(x)
+
+
+def test_small_config_matches_direct_solve():
+    P = problem("small")
+    dec = decomp(P)
+    B = bddc.BDDC(dec, P.mesh.elem_nodes, P.Ke)
+    b = P.rhs[0][dec.free]
+    res = gmres.gmres(lambda v: B.A @ v, B.apply, b, 1e-8, 30, 1000)
+    x = np.linalg.solve(B.A.toarray(), b)
+    assert res.converged and res.rel_res_true <= 1e-8
+    assert np.linalg.norm(res.x - x) < 1e-7 * np.linalg.norm(x)
+    assert 5 <= res.iterations <= 40
+
+
+def test_richer_primal_spaces_need_fewer_iterations():
+    """Paper §6.2: iterations decrease from V to VE to VEF."""
+    P = problem("small")
+    its = []
+    for primal in (1, 3, 7):
+        dec = decomp(P, primal)
+        B = bddc.BDDC(dec, P.mesh.elem_nodes, P.Ke)
+        b = P.rhs[0][dec.free]
+        its.append(gmres.gmres(lambda v: B.A @ v, B.apply, b, 1e-8, 30, 1000).iterations)
+    assert its[0] >= its[1] >= its[2]
+
+
+@pytest.mark.slow
+def test_three_levels_need_more_iterations_than_two():
+    """Paper §7: the multilevel variant trades iterations for a cheaper coarse problem."""
+    P = W.linear_box(16, 4, 1, nrhs=1, primal=7)
+    dec = decomp(P, 7)
+    b = P.rhs[0][dec.free]
+    out = []
+    for lv in (2, 3):
+        B = bddc.BDDC(dec, P.mesh.elem_nodes, P.Ke, levels=lv, coarse_group=8)
+        r = gmres.gmres(lambda v: B.A @ v, B.apply, b, 1e-8, 30, 1000)
+        assert r.converged
+        out.append(r.iterations)
+    assert out[1] >= out[0]

@@ -1,0 +1,118 @@
+"""Pins for the seeded input generators (element tangents, loads, meshes).
+
+These check the generator against facts fixed by continuum mechanics and the
+finite-element method, independent of any solver code:
+* rigid motions are in the kernel of the unconstrained elastic stiffness;
+* the consistent body-force load integrates to the body force times volume;
+* the neo-Hookean tangent at zero displacement is the linear-elastic one with
+  lambda = kappa - 2 mu / 3;
+* every tangent is the derivative of its internal force (central differences);
+* hyperelastic element tangents are symmetric.
+"""
+import numpy as np
+import pytest
+
+from paper_2208_06191_amd import workloads as W
+from oracle import fem
+
+
+@pytest.mark.parametrize("order", [1, 2])
+def test_partition_of_unity_and_volume(order):
+    pts, wts = W.gauss_rule(order + 1)
+    N, dN = W.shape_functions(order, pts)
+    assert np.allclose(N.sum(axis=1), 1.0, atol=1e-14)
+    assert np.allclose(dN.sum(axis=1), 0.0, atol=1e-13)
+    assert abs(wts.sum() - 1.0) < 1e-14
+    mesh = W.box_mesh(2, 3, 2, order, lengths=(2.0, 1.5, 1.0))
+    b = W.body_force_load(mesh, np.tile([0.0, 0.0, -1.0], (mesh.n_nodes, 1)))
+    assert abs(b[2::3].sum() + 3.0) < 1e-12        # body force x volume (2 * 1.5 * 1)
+    assert abs(b[0::3].sum()) < 1e-14
+
+
+@pytest.mark.parametrize("order", [1, 2])
+def test_rigid_motions_in_kernel(order):
+    mesh = W.box_mesh(3, 2, 2, order)
+    Ke = W.element_tangents(mesh, W.linear_elastic(1.0, 0.3))
+    K = fem.assemble(mesh.elem_nodes, Ke, 3 * mesh.n_nodes)
+    R = fem.rigid_body_modes(mesh.coords)
+    scale = abs(K).max() * np.abs(R).max()
+    assert np.abs(K @ R).max() < 1e-12 * scale
+    # and nothing else: exactly 6 zero eigenvalues
+    ev = np.linalg.eigvalsh(K.toarray())
+    assert np.sum(np.abs(ev) < 1e-10 * ev.max()) == 6
+
+
+def test_translations_in_kernel_of_prestressed_tangent():
+    mesh = W.box_mesh(3, 3, 2, 1)
+    u = W.isochoric_field(mesh.coords, 7, 0.05)
+    Ke = W.element_tangents(mesh, W.neo_hookean(1.0, 50.0), u)
+    K = fem.assemble(mesh.elem_nodes, Ke, 3 * mesh.n_nodes)
+    T = fem.rigid_body_modes(mesh.coords)[:, :3]
+    assert np.abs(K @ T).max() < 1e-11 * abs(K).max()
+    assert np.abs(Ke - np.transpose(Ke, (0, 2, 1))).max() < 1e-12 * np.abs(Ke).max()
+
+
+def test_neo_hookean_at_rest_is_linear_elasticity():
+    mesh = W.box_mesh(2, 2, 2, 1)
+    mu, kappa = 1.3, 50.0
+    lam = kappa - 2 * mu / 3
+    E = mu * (3 * lam + 2 * mu) / (lam + mu)
+    nu = lam / (2 * (lam + mu))
+    K1 = W.element_tangents(mesh, W.neo_hookean(mu, kappa))
+    K2 = W.element_tangents(mesh, W.linear_elastic(E, nu))
+    assert np.abs(K1 - K2).max() < 1e-12 * np.abs(K2).max()
+
+
+def test_isochoric_field_is_divergence_free_and_clamped():
+    mesh = W.box_mesh(4, 4, 4, 2)
+    u = W.isochoric_field(mesh.coords, 0, 0.05)
+    assert abs(np.linalg.norm(u, axis=1).max() - 0.05) < 1e-15
+    assert np.abs(u[mesh.node_tags & 1 == 1]).max() == 0.0
+    # analytic divergence by central differences at random interior points (one call, so
+    # the max-norm rescaling is shared by every evaluation point)
+    rng = np.random.default_rng(0)
+    X0 = rng.uniform(0.1, 0.9, size=(50, 3))
+    h = 1e-5
+    pts = [X0]
+    for i in range(3):
+        e = np.zeros(3)
+        e[i] = h
+        pts += [X0 + e, X0 - e]
+    U = W.isochoric_field(np.concatenate(pts), 0, 1.0).reshape(7, 50, 3)
+    div = sum((U[1 + 2 * i, :, i] - U[2 + 2 * i, :, i]) / (2 * h) for i in range(3))
+    grad = np.abs(U[1] - U[2]).max() / (2 * h)
+    assert np.abs(div).max() < 1e-8 * grad
+
+
+def _fd_check(mesh, material, u, frames_fn=None, h=1e-6):
+    rng = np.random.default_rng(11)
+    d = rng.standard_normal(u.shape) * 1e-2
+    Ke = W.element_tangents(mesh, material, u, frames_fn=frames_fn)
+    fp = W.element_internal_forces(mesh, material, u + h * d, frames_fn=frames_fn)
+    fm = W.element_internal_forces(mesh, material, u - h * d, frames_fn=frames_fn)
+    de = d[mesh.elem_nodes].reshape(mesh.n_elems, -1)
+    lin = np.einsum("eij,ej->ei", Ke, de)
+    fd = (fp - fm) / (2 * h)
+    return np.abs(lin - fd).max() / np.abs(lin).max()
+
+
+@pytest.mark.parametrize("order", [1, 2])
+def test_neo_hookean_tangent_is_derivative_of_internal_force(order):
+    mesh = W.box_mesh(2, 2, 1, order)
+    u = W.smooth_field(mesh.coords, 3, 0.05)
+    assert _fd_check(mesh, W.neo_hookean(1.0, 50.0), u) < 1e-7
+
+
+def test_guccione_tangent_is_derivative_of_internal_force():
+    mesh = W.box_mesh(2, 1, 2, 1)
+    u = W.smooth_field(mesh.coords, 4, 0.05)
+    rng = np.random.default_rng(2)
+    Qs = {}
+
+    def frames(elems, q):
+        key = (len(elems), q)
+        if key not in Qs:
+            A = rng.standard_normal((len(elems), 3, 3))
+            Qs[key] = np.linalg.qr(A)[0].transpose(0, 2, 1)
+        return Qs[key]
+    assert _fd_check(mesh, W.guccione(), u, frames_fn=frames) < 1e-7
