@@ -1,0 +1,194 @@
+/*
+ * mbddc.h - C ABI of the MI355X BDDC-preconditioned GMRES library.
+ *
+ * The library solves the Newton tangent systems of finite-element elasticity
+ * (Barnafi, Pavarino, Scacchi, arXiv 2208.06191, §2 eq. "tangent problem")
+ * with GMRES preconditioned by two-level BDDC (§3.2, "BDDC preconditioner").
+ * The operator is given unassembled, element by element, together with a
+ * non-overlapping element partition (§3.2, Omega = U Omega_i; §4, MATIS
+ * storage) and a choice of primal constraints (vertices / edge averages /
+ * face averages, §3.2 and §6.2).
+ *
+ * Conventions shared by every entry point
+ *  - Every function returns MBDDC_OK (0) or a negative status; nothing throws
+ *    across the ABI. mbddc_strerror() names a status.
+ *  - DOF numbering is 3*node + component (the strided block-size-3 layout of
+ *    §4). Vectors are "full DOF vectors" of length 3*n_nodes (summed over the
+ *    instances of a batch, in instance order); clamped (Dirichlet) entries are
+ *    ignored on input and written as 0 on output.
+ *  - Host pointers are read during the call only and never retained. Device
+ *    pointers (flag on_device = 1) must live on the handle's device and stay
+ *    valid for the duration of the call.
+ *  - A handle is not thread-safe; distinct handles are independent. All GPU
+ *    work is enqueued on the handle's HIP stream; every call returns after the
+ *    work it enqueued has completed.
+ *  - Call order: create -> setup_symbolic -> set_tangent -> factor ->
+ *    solve / apply / matvec (any number) ; set_tangent again replaces the
+ *    operator, and solves then reuse the factors of the last factor call
+ *    (lagged preconditioner) until factor is called again. Calls out of
+ *    order return MBDDC_ERR_STATE.
+ */
+#ifndef MBDDC_H
+#define MBDDC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  MBDDC_OK = 0,
+  MBDDC_ERR_ARG = -1,        /* invalid argument (NULL, out of range, NaN in an input) */
+  MBDDC_ERR_OOM = -2,        /* device allocation failed; nothing partial is kept */
+  MBDDC_ERR_SINGULAR = -3,   /* zero pivot: info / mbddc_last_bad_subdomain names it (-1: coarse) */
+  MBDDC_ERR_NOCONV = -4,     /* GMRES hit max_it; x holds the last iterate */
+  MBDDC_ERR_DEVICE = -5,     /* a HIP runtime call failed */
+  MBDDC_ERR_STATE = -6,      /* call out of order */
+  MBDDC_ERR_UNSUPPORTED = -7 /* size or option outside what this build handles */
+};
+
+enum { MBDDC_HEX8 = 1, MBDDC_HEX27 = 2 };              /* Q1, Q2 hexahedra (§2) */
+enum { MBDDC_PRIMAL_V = 1, MBDDC_PRIMAL_E = 2, MBDDC_PRIMAL_F = 4 }; /* §6.2 primal spaces */
+/* Precision policy. Global vectors, the assembled operator, the coarse problem
+ * and GMRES are FP64 in every mode. MBDDC_FP64: local factorisations and the
+ * per-iteration local operators in FP64. MBDDC_MIXED: local factorisations in
+ * FP64, local operators stored and applied in FP32 with FP32 accumulation.
+ * MBDDC_MIXED_F32FACT: local factorisations also in FP32. */
+enum { MBDDC_FP64 = 0, MBDDC_MIXED = 1, MBDDC_MIXED_F32FACT = 2 };
+
+typedef struct mbddc_ctx mbddc_ctx;
+
+/* One mesh and its partition (§3.2). Element-local node order is lexicographic:
+ * local index a + (p+1) b + (p+1)^2 c for reference-cube position (a, b, c),
+ * p = 1 (HEX8) or 2 (HEX27). */
+typedef struct {
+  int32_t n_nodes;
+  const double* coords;          /* [n_nodes*3], may be NULL (not used by the box rule) */
+  int32_t n_elems;
+  int32_t elem_type;             /* MBDDC_HEX8 or MBDDC_HEX27 */
+  const int32_t* elem_nodes;     /* [n_elems*npe] node ids */
+  int32_t n_sub;
+  const int32_t* elem_part;      /* [n_elems] subdomain id in [0, n_sub) */
+  const uint32_t* node_tags;     /* [n_nodes] boundary-surface bitmask, may be NULL */
+  int32_t n_dirichlet;
+  const int32_t* dirichlet_dofs; /* [n_dirichlet] clamped DOF ids (homogeneous) */
+} mbddc_mesh;
+
+typedef struct {
+  uint32_t primal;               /* MBDDC_PRIMAL_* bitmask */
+  int32_t levels;                /* 2 (this build) */
+  int32_t coarse_group;          /* level-2 group size (reserved) */
+  int32_t precision;             /* MBDDC_FP64 or MBDDC_MIXED */
+  int32_t restart;               /* GMRES restart length, 1..64 */
+  double rtol;                   /* relative residual target on ||b - K x||_2 */
+  int32_t max_it;                /* Arnoldi steps summed over restarts */
+  int32_t symmetric_hint;        /* reserved */
+  const char* tune_table;        /* reserved, may be NULL */
+  int32_t keep_coarse_matrix;    /* 1: keep S_PiPi for mbddc_get_coarse_matrix (8 n_c^2 bytes) */
+} mbddc_options;
+
+typedef struct {
+  int32_t iterations;            /* max over the systems of the call */
+  int32_t restarts;
+  int32_t status;
+  int32_t bad_subdomain;
+  double rel_res_true;           /* max over systems of ||b - K x|| / ||b|| (FP64) */
+  double rel_res_est;
+  double ms_setup, ms_factor, ms_solve;
+} mbddc_info;
+
+typedef struct {
+  int64_t n_dofs;                /* 3 * total nodes */
+  int64_t n_free;
+  int64_t n_interface;           /* free DOFs shared by >= 2 subdomains */
+  int64_t n_coarse;              /* primal constraints (all instances) */
+  int64_t n_sub;
+  int64_t n_instances;
+  int64_t n_vertices, n_edges, n_faces;
+  int64_t max_local;             /* largest local dense problem size */
+  int64_t bsr_blocks;            /* 3x3 blocks of the assembled operator */
+} mbddc_sizes;
+
+/* Creates a handle on HIP device `hip_device`, enqueuing on `hip_stream` (a
+ * hipStream_t, may be NULL for the null stream). */
+int mbddc_create(mbddc_ctx** out, int hip_device, void* hip_stream);
+
+/* Fills `opt` with the defaults: primal V|E, 2 levels, group 8, MIXED, restart
+ * 30, rtol 1e-8, max_it 1000. */
+int mbddc_default_options(mbddc_options* opt);
+
+/* Host-side symbolic setup (§3.2 index sets: interior / interface, vertex /
+ * edge / face globs, primal constraint rows, counting weights; §4 exact
+ * preallocation of the assembled pattern). Copies every input. */
+int mbddc_setup_symbolic(mbddc_ctx* ctx, const mbddc_mesh* mesh, const mbddc_options* opt);
+
+/* Same for `n_inst` independent problems solved together (one launch per
+ * phase for all of them); vectors and element matrices are concatenated in
+ * instance order. */
+int mbddc_setup_symbolic_batch(mbddc_ctx* ctx, int n_inst, const mbddc_mesh* meshes,
+                               const mbddc_options* opt);
+
+/* Device bytes the handle will hold after factor (exact; call after setup). */
+int mbddc_footprint(const mbddc_ctx* ctx, size_t* device_bytes);
+
+int mbddc_get_sizes(const mbddc_ctx* ctx, mbddc_sizes* out);
+
+/* Element tangents K_e, [n_elems][3npe][3npe] row-major FP64 in element-local
+ * DOF order 3a + comp (all instances concatenated). Assembles the operator
+ * (§3.2, A = sum_i A^(i)) on the device; keeps factors of a previous factor
+ * call (lagged preconditioner). */
+int mbddc_set_tangent(mbddc_ctx* ctx, const double* elem_K, int on_device);
+
+/* Numeric BDDC setup (§3.2): local interior and constrained-Neumann problems,
+ * coarse basis Phi, coarse matrix S_PiPi and its FP64 factorisation.
+ * Returns MBDDC_ERR_SINGULAR on a zero pivot (mbddc_last_bad_subdomain). */
+int mbddc_factor(mbddc_ctx* ctx);
+
+/* Right-preconditioned GMRES(restart) for `nrhs` right-hand sides (each
+ * instance x each rhs is an independent system). b, x: [nrhs][n_dofs]. */
+int mbddc_solve(mbddc_ctx* ctx, int nrhs, const double* b, double* x, int on_device,
+                mbddc_info* info);
+
+/* One preconditioner application z = M^-1 r (§3.2 block factorisation with
+ * S_Gamma^-1 replaced by M^-1_BDDC). r, z: [nrhs][n_dofs]. */
+int mbddc_apply(mbddc_ctx* ctx, int nrhs, const double* r, double* z, int on_device);
+
+/* y = K x with the assembled FP64 operator (clamped rows/columns removed). */
+int mbddc_matvec(mbddc_ctx* ctx, int nrhs, const double* x, double* y, int on_device);
+
+/* Integer results of the symbolic setup, for inspection (host arrays):
+ * node_glob [n_nodes total] glob id or -1; glob_kind [n_globs] 1/2/4;
+ * coarse_glob/coarse_comp [n_coarse]. Any pointer may be NULL. */
+int mbddc_get_globs(const mbddc_ctx* ctx, int32_t* node_glob, int32_t* n_globs, int32_t* glob_kind,
+                    int32_t* coarse_glob, int32_t* coarse_comp);
+
+/* The assembled coarse matrix S_PiPi of instance `inst` before factorisation,
+ * [n_c][n_c] FP64 row-major (host). Available after factor. */
+int mbddc_get_coarse_matrix(const mbddc_ctx* ctx, int inst, double* out, int64_t n_c);
+
+/* The assembled operator in 3x3-block CSR over nodes (host): rowptr [n_nodes+1],
+ * colidx [blocks], vals [blocks*9] row-major blocks. */
+int mbddc_get_bsr(const mbddc_ctx* ctx, int32_t* rowptr, int32_t* colidx, double* vals);
+
+/* Host-only symbolic setup of one mesh (no device needed): sizes, glob
+ * classification and per-subdomain counts. Output arrays may be NULL; sizes
+ * first (call once with NULL arrays to learn them): node_glob [n_nodes],
+ * glob_kind [n_globs = n_vertices + n_edges + n_faces], coarse_glob /
+ * coarse_comp [n_coarse], sub_counts [n_sub * 3] = (interior, interface,
+ * primal) DOFs per subdomain. */
+int mbddc_inspect_symbolic(const mbddc_mesh* mesh, uint32_t primal, mbddc_sizes* sizes, int32_t* node_glob,
+                           int32_t* glob_kind, int32_t* coarse_glob, int32_t* coarse_comp, int32_t* sub_counts);
+
+/* Subdomain of the last MBDDC_ERR_SINGULAR (-1: coarse problem). */
+int mbddc_last_bad_subdomain(const mbddc_ctx* ctx);
+
+int mbddc_destroy(mbddc_ctx* ctx);
+
+const char* mbddc_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MBDDC_H */

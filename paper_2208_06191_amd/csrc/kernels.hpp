@@ -1,0 +1,58 @@
+// Device data layouts and kernel launchers of the BDDC hot path.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace mbddc {
+
+constexpr int kBlock = 256;          // threads per workgroup (4 wave64)
+constexpr int kMaxRhs = 8;           // right-hand sides handled per call
+constexpr int kGjMax = 512;          // largest matrix of the one-workgroup Gauss-Jordan kernel
+constexpr int kCoarseBlock = 64;     // diagonal block of the multi-workgroup coarse inversion
+constexpr int kCoarseChunk = 256;    // columns per workgroup in the coarse product
+
+// Per-subdomain device descriptor. Offsets are element counts into the
+// per-precision work buffers. Dense work matrices are row-major; apply
+// operators are column-major with a leading dimension padded to 4.
+struct SubDev {
+  int32_t nI, nG, nc, inst;
+  int32_t n_elems, ldK;               // ldK = nI + nG
+  int64_t dof_off, if_off, c_off, elem_off, cons_off;
+  int64_t oK;                         // K^(i) (ni x ni); its top-left nI block becomes K_II^-1
+  int64_t oG;                         // K_GI K_II^-1   (nG x nI)
+  int64_t oH;                         // K_II^-1 K_IG   (nI x nG)
+  int64_t oP;                         // [S C^T; C 0] (mP x mP), inverted in place
+  int64_t oB1, oB2, oB3, oB4;         // operators: [K_II^-1; G], [D S~ D; (D Phi)^T], D Phi, H
+  int32_t ld1, ld2, ld3, ld4;
+  int64_t oKc;                        // local coarse matrix (nc x nc, FP64)
+  int64_t oPiv;                       // pivots: nI for K_II then mP for P
+};
+
+// Batched Gauss-Jordan descriptor: invert the n x n matrix at base+off (row stride ld).
+struct GjDesc {
+  int64_t off;
+  int32_t n, ld;
+  int64_t piv_off;
+  int32_t id;                          // reported in the status array on a zero pivot
+  int32_t pad;
+};
+
+// Batched GEMM descriptor: C = alpha * A B + beta * Ci (row-major, sizes M x K, K x N).
+struct GemmDesc {
+  int32_t M, N, K, lda, ldb, ldc, ldci, tiles_n;
+  int64_t oA, oB, oC, oCi;
+  double alpha, beta;
+};
+
+struct GemmItem {
+  int32_t prob, tm, tn, pad;
+};
+
+// Apply work item: (subdomain or instance, first row, first column, column count).
+struct ApplyItem {
+  int32_t sub, row0, col0, ncol;
+};
+
+}  // namespace mbddc

@@ -1,0 +1,1231 @@
+// MI355X BDDC-preconditioned GMRES: device memory, drivers and the C ABI.
+//
+// Paper: Barnafi, Pavarino, Scacchi, arXiv 2208.06191. The method (§3.2):
+// non-overlapping substructuring with unassembled subdomain matrices, primal
+// vertex / edge / face constraints, counting-function scaling, a coarse basis
+// Phi of minimum-energy extensions and coarse matrix S_PiPi; GMRES on the
+// Newton tangent (§2) preconditioned by M^-1 = U diag(A_II^-1, M^-1_BDDC) L,
+// the exact block factorisation of A^-1 with the interface Schur complement
+// replaced by BDDC.
+//
+// MI355X design: every subdomain's local problems are reduced, at factor time,
+// to dense operators (K_II^-1, K_GI K_II^-1, D [N^-1]_GG D, D Phi, K_II^-1 K_IG)
+// obtained by batched Gauss-Jordan inversion with partial pivoting and
+// batched GEMMs; the coarse matrix is inverted explicitly in FP64. One
+// preconditioner application is then five launches of column-major gemv over
+// all subdomains at once plus one dense FP64 coarse product: pure HBM
+// streaming with every right-hand side of the call sharing each operator read.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "mbddc.h"
+#include "plan.hpp"
+#include "kernels.hpp"
+#include "kernels_setup.inc"
+#include "kernels_apply.inc"
+
+using namespace mbddc;
+
+namespace {
+
+#define HIPCHK(x)                                  \
+  do {                                             \
+    hipError_t e_ = (x);                           \
+    if (e_ != hipSuccess) {                        \
+      last_hip_error() = e_;                       \
+      return MBDDC_ERR_DEVICE;                     \
+    }                                              \
+  } while (0)
+
+hipError_t& last_hip_error() {
+  static thread_local hipError_t e = hipSuccess;
+  return e;
+}
+
+inline int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
+inline unsigned nblk(int64_t n, int64_t b = kBlock) { return (unsigned)((n + b - 1) / b); }
+
+struct DevMem {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+}  // namespace
+
+struct mbddc_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  mbddc_options opt{};
+  int state = 0;                 // 0 created, 1 symbolic, 2 tangent, 3 factored
+  bool mixed = true;             // apply operators in FP32
+  bool fact32 = false;           // local factorisations in FP32
+  Plan plan;
+  int last_bad = 0;
+  size_t bytes = 0;              // device bytes currently held
+  std::vector<DevMem> allocs;
+
+  // sizes
+  int64_t nblocks = 0, w_elems = 0, op_elems = 0, kcl_elems = 0, piv_elems = 0, kc_elems = 0;
+  int max_cols = 0, coarse_max_nc = 0;
+  std::vector<SubDev> subs;
+  std::vector<GjDesc> gj_kii, gj_p, gj_coarse_small;
+  std::vector<int32_t> coarse_large;                 // instances inverted by the blocked path
+  std::vector<GemmDesc> gemm_desc;
+  std::vector<GemmItem> gemm_items_gh, gemm_items_s;
+  std::vector<ApplyItem> itA, itC, itE, itF, itH;
+  std::vector<int64_t> inst_coarse_off, inst_kc_off;
+  std::vector<int32_t> inst_nc, inst_kc_ld, inst_nchunk, coarse_inst, cslot_sub;
+  std::vector<int32_t> chunk_inst, inst_chunk_off;
+  std::vector<int64_t> chunk_begin;
+  int32_t nchunk_max = 1;
+
+  // device arrays (plan)
+  SubDev* d_subs = nullptr;
+  int32_t *d_sub_dofs = nullptr, *d_sub_elems = nullptr, *d_elem_npe = nullptr, *d_elem_ldof = nullptr;
+  int64_t *d_ke_off = nullptr, *d_elem_ldof_off = nullptr;
+  int32_t *d_cons_ptr = nullptr, *d_cons_idx = nullptr;
+  double* d_cons_w = nullptr;
+  int32_t *d_slot_dof = nullptr, *d_slot_ifx = nullptr, *d_ifx_ptr = nullptr, *d_ifx_slots = nullptr;
+  double* d_slot_w = nullptr;
+  uint8_t* d_slot_owner = nullptr;
+  int32_t *d_cslot_coarse = nullptr, *d_cslot_sub = nullptr, *d_coarse_ptr = nullptr, *d_coarse_slots = nullptr,
+          *d_coarse_inst = nullptr;
+  int64_t *d_inst_coarse_off = nullptr, *d_inst_kc_off = nullptr;
+  int32_t *d_inst_nc = nullptr, *d_inst_kc_ld = nullptr, *d_inst_nchunk = nullptr;
+  int32_t *d_bsr_rowptr = nullptr, *d_bsr_col = nullptr, *d_bsr_rownode = nullptr, *d_bsr_cptr = nullptr,
+          *d_bsr_kstride = nullptr;
+  int64_t* d_bsr_contrib = nullptr;
+  uint8_t* d_free = nullptr;
+  int32_t* d_dof_inst = nullptr;
+  GjDesc *d_gj_kii = nullptr, *d_gj_p = nullptr, *d_gj_cs = nullptr;
+  GemmDesc* d_gemm_desc = nullptr;
+  GemmItem *d_gemm_gh = nullptr, *d_gemm_s = nullptr;
+  ApplyItem *d_itA = nullptr, *d_itC = nullptr, *d_itE = nullptr, *d_itF = nullptr, *d_itH = nullptr;
+  int32_t *d_chunk_inst = nullptr, *d_inst_chunk_off = nullptr;
+  int64_t* d_chunk_begin = nullptr;
+
+  // device arrays (numeric)
+  double* d_Ke = nullptr;
+  double* d_vals = nullptr;
+  void* d_W = nullptr;          // factor-precision work matrices
+  void* d_Op = nullptr;         // apply operators
+  double* d_Kcl = nullptr;      // local coarse matrices
+  double* d_Kc = nullptr;       // coarse matrices, inverted in place
+  double* d_Kc_keep = nullptr;  // copy of the assembled coarse matrices (optional)
+  int32_t* d_piv = nullptr;
+  int32_t* d_status = nullptr;  // per GJ descriptor
+  int32_t* d_piv_c = nullptr;   // coarse pivots
+  double *d_cDinv = nullptr, *d_cY = nullptr, *d_cCcol = nullptr;
+  double* d_amax = nullptr;
+  int64_t status_len = 0;
+
+  // per-call buffers (sized for R right-hand sides)
+  int R_alloc = 0;
+  double *d_tb = nullptr, *d_wb = nullptr, *d_cc = nullptr;
+  int Y_R = 0;                   // layout (R) of the apply output block currently in d_Y
+  double* d_ep = nullptr;
+  double *d_X = nullptr, *d_Y = nullptr, *d_io = nullptr;
+  // Krylov buffers
+  int R_kry = 0, restart_kry = 0;
+  double *d_V = nullptr, *d_Z = nullptr, *d_Wv = nullptr, *d_B = nullptr, *d_x = nullptr, *d_r = nullptr;
+  double *d_part = nullptr, *d_part2 = nullptr, *d_npart = nullptr;
+  double *d_h1 = nullptr, *d_h2 = nullptr, *d_Hs = nullptr, *d_cs = nullptr, *d_sn = nullptr, *d_g = nullptr,
+         *d_hnorm = nullptr, *d_y = nullptr, *d_beta = nullptr;
+  int32_t *d_jsys = nullptr, *d_nk = nullptr;
+  uint8_t *d_active = nullptr, *d_mode = nullptr, *d_fin = nullptr;
+  double* h_est = nullptr;       // pinned host
+  double* h_norm = nullptr;      // pinned host
+};
+
+namespace {
+
+template <typename T>
+int dalloc(mbddc_ctx* c, T** p, int64_t n) {
+  size_t b = std::max<int64_t>(n, 1) * sizeof(T);
+  b = round_up(b, 256);
+  void* q = nullptr;
+  hipError_t e = hipMalloc(&q, b);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return MBDDC_ERR_OOM;
+  }
+  c->allocs.push_back({q, b});
+  c->bytes += b;
+  *p = reinterpret_cast<T*>(q);
+  return MBDDC_OK;
+}
+
+template <typename T>
+void dfree(mbddc_ctx* c, T*& p) {
+  if (!p) return;
+  for (size_t i = 0; i < c->allocs.size(); ++i) {
+    if (c->allocs[i].p == (void*)p) {
+      c->bytes -= c->allocs[i].bytes;
+      c->allocs.erase(c->allocs.begin() + i);
+      break;
+    }
+  }
+  (void)hipFree((void*)p);
+  p = nullptr;
+}
+
+void free_all(mbddc_ctx* c) {
+  for (auto& a : c->allocs) (void)hipFree(a.p);
+  c->allocs.clear();
+  c->bytes = 0;
+  if (c->h_est) (void)hipHostFree(c->h_est);
+  if (c->h_norm) (void)hipHostFree(c->h_norm);
+  c->h_est = c->h_norm = nullptr;
+}
+
+template <typename T>
+int upload(mbddc_ctx* c, T** p, const std::vector<T>& v) {
+  int st = dalloc(c, p, (int64_t)v.size());
+  if (st) return st;
+  if (!v.empty()) HIPCHK(hipMemcpyAsync(*p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, c->stream));
+  return MBDDC_OK;
+}
+
+#define CHK(x)                 \
+  do {                         \
+    int s_ = (x);              \
+    if (s_ != MBDDC_OK) return s_; \
+  } while (0)
+
+int apply_R(int nrhs) {
+  if (nrhs <= 1) return 1;
+  if (nrhs <= 2) return 2;
+  if (nrhs <= 4) return 4;
+  return 8;
+}
+
+size_t elem_size(bool mixed) { return mixed ? sizeof(float) : sizeof(double); }
+
+// ----------------------------------------------------------------------------
+// symbolic layout on top of the host plan
+// ----------------------------------------------------------------------------
+int build_layout(mbddc_ctx* c) {
+  const Plan& P = c->plan;
+  c->subs.assign(P.n_sub, SubDev{});
+  int64_t w = 0, op = 0, kcl = 0, piv = 0;
+  c->gj_kii.clear();
+  c->gj_p.clear();
+  c->gemm_desc.clear();
+  c->gemm_items_gh.clear();
+  c->gemm_items_s.clear();
+  c->itA.clear(); c->itC.clear(); c->itE.clear(); c->itF.clear(); c->itH.clear();
+  c->max_cols = 1;
+  std::vector<GemmDesc> dS;
+  for (int64_t s = 0; s < P.n_sub; ++s) {
+    const SubLayout& L = P.subs[s];
+    SubDev& d = c->subs[s];
+    d.nI = L.nI; d.nG = L.nG; d.nc = L.nc; d.inst = L.inst;
+    d.n_elems = L.n_elems; d.ldK = L.ni();
+    d.dof_off = L.dof_off; d.if_off = L.if_off; d.c_off = L.c_off; d.elem_off = L.elem_off; d.cons_off = L.cons_off;
+    const int64_t ni = L.ni(), nI = L.nI, nG = L.nG, nc = L.nc, m = L.mP();
+    if (std::max<int64_t>(nI, m) > kGjMax) return MBDDC_ERR_UNSUPPORTED;
+    d.oK = w; w += round_up(ni * ni, 64);
+    d.oG = w; w += round_up(nG * nI, 64);
+    d.oH = w; w += round_up(nI * nG, 64);
+    d.oP = w; w += round_up(m * m, 64);
+    d.ld1 = (int32_t)round_up(nI + nG, 4);
+    d.ld2 = (int32_t)round_up(nG + nc, 4);
+    d.ld3 = (int32_t)round_up(nG, 4);
+    d.ld4 = (int32_t)round_up(nI, 4);
+    d.oB1 = op; op += round_up((int64_t)d.ld1 * nI, 64);
+    d.oB2 = op; op += round_up((int64_t)d.ld2 * nG, 64);
+    d.oB3 = op; op += round_up((int64_t)d.ld3 * nc, 64);
+    d.oB4 = op; op += round_up((int64_t)d.ld4 * nG, 64);
+    d.oKc = kcl; kcl += nc * nc;
+    d.oPiv = piv; piv += nI + m;
+    c->max_cols = std::max<int>(c->max_cols, (int)std::max(std::max(nI, nG), nc));
+    c->gj_kii.push_back({d.oK, (int32_t)nI, (int32_t)ni, d.oPiv, (int32_t)s, 0});
+    c->gj_p.push_back({d.oP, (int32_t)m, (int32_t)m, d.oPiv + nI, (int32_t)s, 0});
+    // G = K_GI K_II^-1, H = K_II^-1 K_IG, S = K_GG - G K_IG
+    GemmDesc g{};
+    g.M = (int32_t)nG; g.N = (int32_t)nI; g.K = (int32_t)nI; g.lda = (int32_t)ni; g.ldb = (int32_t)ni; g.ldc = (int32_t)nI;
+    g.ldci = 1; g.oA = d.oK + nI * ni; g.oB = d.oK; g.oC = d.oG; g.oCi = 0; g.alpha = 1.0; g.beta = 0.0;
+    GemmDesc h{};
+    h.M = (int32_t)nI; h.N = (int32_t)nG; h.K = (int32_t)nI; h.lda = (int32_t)ni; h.ldb = (int32_t)ni; h.ldc = (int32_t)nG;
+    h.ldci = 1; h.oA = d.oK; h.oB = d.oK + nI; h.oC = d.oH; h.oCi = 0; h.alpha = 1.0; h.beta = 0.0;
+    GemmDesc sS{};
+    sS.M = (int32_t)nG; sS.N = (int32_t)nG; sS.K = (int32_t)nI; sS.lda = (int32_t)nI; sS.ldb = (int32_t)ni;
+    sS.ldc = (int32_t)m; sS.ldci = (int32_t)ni; sS.oA = d.oG; sS.oB = d.oK + nI; sS.oC = d.oP;
+    sS.oCi = d.oK + nI * ni + nI; sS.alpha = -1.0; sS.beta = 1.0;
+    for (GemmDesc* gd : {&g, &h}) {
+      int32_t tm = (int32_t)((gd->M + 63) / 64), tn = (int32_t)((gd->N + 63) / 64);
+      gd->tiles_n = tn;
+      int32_t id = (int32_t)c->gemm_desc.size();
+      c->gemm_desc.push_back(*gd);
+      for (int32_t a = 0; a < tm; ++a)
+        for (int32_t b = 0; b < tn; ++b) c->gemm_items_gh.push_back({id, a, b, 0});
+    }
+    sS.tiles_n = (int32_t)((sS.N + 63) / 64);
+    dS.push_back(sS);
+    // apply work items
+    auto add = [](std::vector<ApplyItem>& v, int64_t sub, int64_t rows) {
+      int64_t nb = std::max<int64_t>(1, (rows + 255) / 256);
+      for (int64_t b = 0; b < nb; ++b) v.push_back({(int32_t)sub, (int32_t)(b * 256), 0, 0});
+    };
+    add(c->itA, s, nI + nG);
+    add(c->itC, s, nG + nc);
+    add(c->itF, s, nG);
+    add(c->itH, s, nI);
+  }
+  for (GemmDesc& sS : dS) {
+    int32_t id = (int32_t)c->gemm_desc.size();
+    c->gemm_desc.push_back(sS);
+    int32_t tm = (sS.M + 63) / 64, tn = sS.tiles_n;
+    for (int32_t a = 0; a < tm; ++a)
+      for (int32_t b = 0; b < tn; ++b) c->gemm_items_s.push_back({id, a, b, 0});
+  }
+  c->w_elems = w;
+  c->op_elems = op;
+  c->kcl_elems = kcl;
+  c->piv_elems = piv;
+  // coarse problems per instance
+  c->inst_coarse_off.assign(P.n_inst, 0);
+  c->inst_kc_off.assign(P.n_inst, 0);
+  c->inst_nc.assign(P.n_inst, 0);
+  c->inst_kc_ld.assign(P.n_inst, 0);
+  c->inst_nchunk.assign(P.n_inst, 1);
+  c->gj_coarse_small.clear();
+  c->coarse_large.clear();
+  int64_t kc = 0;
+  c->coarse_max_nc = 0;
+  c->nchunk_max = 1;
+  for (int32_t ii = 0; ii < P.n_inst; ++ii) {
+    const Instance& in = P.inst[ii];
+    c->inst_coarse_off[ii] = in.coarse_off;
+    c->inst_nc[ii] = in.n_coarse;
+    int32_t ld = (int32_t)round_up(std::max(in.n_coarse, 1), 4);
+    c->inst_kc_ld[ii] = ld;
+    c->inst_kc_off[ii] = kc;
+    kc += round_up((int64_t)ld * std::max(in.n_coarse, 1), 64);
+    c->coarse_max_nc = std::max(c->coarse_max_nc, in.n_coarse);
+    int32_t nch = std::max(1, (in.n_coarse + kCoarseChunk - 1) / kCoarseChunk);
+    c->inst_nchunk[ii] = nch;
+    c->nchunk_max = std::max(c->nchunk_max, nch);
+    if (in.n_coarse > 0) {
+      if (in.n_coarse <= kGjMax)
+        c->gj_coarse_small.push_back({c->inst_kc_off[ii], in.n_coarse, ld, in.coarse_off, ii, 0});
+      else
+        c->coarse_large.push_back(ii);
+      for (int32_t r0 = 0; r0 < in.n_coarse; r0 += 256)
+        for (int32_t c0 = 0; c0 < in.n_coarse; c0 += kCoarseChunk)
+          c->itE.push_back({ii, r0, c0, std::min(kCoarseChunk, in.n_coarse - c0)});
+    }
+  }
+  c->kc_elems = kc;
+  c->coarse_inst.assign(P.n_coarse, 0);
+  for (int32_t ii = 0; ii < P.n_inst; ++ii)
+    for (int32_t k = 0; k < P.inst[ii].n_coarse; ++k) c->coarse_inst[P.inst[ii].coarse_off + k] = ii;
+  c->cslot_sub.assign(P.n_cslots, 0);
+  for (int64_t s = 0; s < P.n_sub; ++s)
+    for (int32_t k = 0; k < P.subs[s].nc; ++k) c->cslot_sub[P.subs[s].c_off + k] = (int32_t)s;
+  // Krylov row chunks (never straddling an instance)
+  c->chunk_inst.clear();
+  c->chunk_begin.clear();
+  c->inst_chunk_off.assign(P.n_inst + 1, 0);
+  int64_t target = std::max<int64_t>(256, round_up(P.n_dofs / 1024 + 1, 64));
+  for (int32_t ii = 0; ii < P.n_inst; ++ii) {
+    c->inst_chunk_off[ii] = (int32_t)c->chunk_inst.size();
+    int64_t b0 = 3 * P.inst[ii].node_off, b1 = b0 + 3LL * P.inst[ii].n_nodes;
+    for (int64_t b = b0; b < b1; b += target) {
+      c->chunk_inst.push_back(ii);
+      c->chunk_begin.push_back(b);
+    }
+  }
+  c->inst_chunk_off[P.n_inst] = (int32_t)c->chunk_inst.size();
+  c->chunk_begin.push_back(P.n_dofs);
+  c->nblocks = (int64_t)P.bsr_col.size();
+  return MBDDC_OK;
+}
+
+int upload_plan(mbddc_ctx* c) {
+  const Plan& P = c->plan;
+  CHK(upload(c, &c->d_subs, c->subs));
+  CHK(upload(c, &c->d_sub_dofs, P.sub_dofs));
+  CHK(upload(c, &c->d_sub_elems, P.sub_elems));
+  CHK(upload(c, &c->d_elem_npe, P.elem_npe));
+  CHK(upload(c, &c->d_elem_ldof, P.elem_ldof));
+  CHK(upload(c, &c->d_ke_off, P.ke_off));
+  CHK(upload(c, &c->d_elem_ldof_off, P.elem_ldof_off));
+  CHK(upload(c, &c->d_cons_ptr, P.cons_ptr));
+  CHK(upload(c, &c->d_cons_idx, P.cons_idx));
+  CHK(upload(c, &c->d_cons_w, P.cons_w));
+  CHK(upload(c, &c->d_slot_dof, P.slot_dof));
+  CHK(upload(c, &c->d_slot_ifx, P.slot_ifx));
+  CHK(upload(c, &c->d_slot_w, P.slot_w));
+  CHK(upload(c, &c->d_slot_owner, P.slot_owner));
+  CHK(upload(c, &c->d_ifx_ptr, P.ifx_ptr));
+  CHK(upload(c, &c->d_ifx_slots, P.ifx_slots));
+  CHK(upload(c, &c->d_cslot_coarse, P.cslot_coarse));
+  CHK(upload(c, &c->d_cslot_sub, c->cslot_sub));
+  CHK(upload(c, &c->d_coarse_ptr, P.coarse_ptr));
+  CHK(upload(c, &c->d_coarse_slots, P.coarse_slots));
+  CHK(upload(c, &c->d_coarse_inst, c->coarse_inst));
+  CHK(upload(c, &c->d_inst_coarse_off, c->inst_coarse_off));
+  CHK(upload(c, &c->d_inst_kc_off, c->inst_kc_off));
+  CHK(upload(c, &c->d_inst_nc, c->inst_nc));
+  CHK(upload(c, &c->d_inst_kc_ld, c->inst_kc_ld));
+  CHK(upload(c, &c->d_inst_nchunk, c->inst_nchunk));
+  std::vector<int32_t> rownode(c->nblocks);
+  for (int64_t n = 0; n < P.n_nodes; ++n)
+    for (int32_t b = P.bsr_rowptr[n]; b < P.bsr_rowptr[n + 1]; ++b) rownode[b] = (int32_t)n;
+  CHK(upload(c, &c->d_bsr_rowptr, P.bsr_rowptr));
+  CHK(upload(c, &c->d_bsr_col, P.bsr_col));
+  CHK(upload(c, &c->d_bsr_rownode, rownode));
+  CHK(upload(c, &c->d_bsr_cptr, P.bsr_cptr));
+  CHK(upload(c, &c->d_bsr_contrib, P.bsr_contrib));
+  CHK(upload(c, &c->d_bsr_kstride, P.bsr_kstride));
+  CHK(upload(c, &c->d_free, P.free_dof));
+  std::vector<int32_t> dof_inst(P.n_dofs);
+  for (int64_t d = 0; d < P.n_dofs; ++d) dof_inst[d] = P.dof_inst[d];
+  CHK(upload(c, &c->d_dof_inst, dof_inst));
+  CHK(upload(c, &c->d_gj_kii, c->gj_kii));
+  CHK(upload(c, &c->d_gj_p, c->gj_p));
+  CHK(upload(c, &c->d_gj_cs, c->gj_coarse_small));
+  CHK(upload(c, &c->d_gemm_desc, c->gemm_desc));
+  CHK(upload(c, &c->d_gemm_gh, c->gemm_items_gh));
+  CHK(upload(c, &c->d_gemm_s, c->gemm_items_s));
+  CHK(upload(c, &c->d_itA, c->itA));
+  CHK(upload(c, &c->d_itC, c->itC));
+  CHK(upload(c, &c->d_itE, c->itE));
+  CHK(upload(c, &c->d_itF, c->itF));
+  CHK(upload(c, &c->d_itH, c->itH));
+  CHK(upload(c, &c->d_chunk_inst, c->chunk_inst));
+  CHK(upload(c, &c->d_chunk_begin, c->chunk_begin));
+  CHK(upload(c, &c->d_inst_chunk_off, c->inst_chunk_off));
+  // numeric buffers
+  const size_t es = elem_size(c->mixed);
+  CHK(dalloc(c, &c->d_Ke, P.ke_total));
+  CHK(dalloc(c, &c->d_vals, c->nblocks * 9));
+  CHK(dalloc(c, reinterpret_cast<unsigned char**>(&c->d_W), c->w_elems * (int64_t)elem_size(c->fact32)));
+  CHK(dalloc(c, reinterpret_cast<unsigned char**>(&c->d_Op), c->op_elems * (int64_t)es));
+  CHK(dalloc(c, &c->d_Kcl, c->kcl_elems));
+  CHK(dalloc(c, &c->d_Kc, c->kc_elems));
+  if (c->opt.keep_coarse_matrix) CHK(dalloc(c, &c->d_Kc_keep, c->kc_elems));
+  CHK(dalloc(c, &c->d_piv, c->piv_elems));
+  c->status_len = std::max<int64_t>(P.n_sub, (int64_t)c->gj_coarse_small.size()) + 1;
+  CHK(dalloc(c, &c->d_status, c->status_len));
+  CHK(dalloc(c, &c->d_piv_c, std::max<int64_t>(std::max<int64_t>(P.n_coarse, c->coarse_max_nc), 1)));
+  if (!c->coarse_large.empty()) {
+    int64_t ldmax = round_up(c->coarse_max_nc, 4);
+    CHK(dalloc(c, &c->d_cDinv, kCoarseBlock * kCoarseBlock));
+    CHK(dalloc(c, &c->d_cY, kCoarseBlock * ldmax));
+    CHK(dalloc(c, &c->d_cCcol, ldmax * kCoarseBlock));
+  }
+  CHK(dalloc(c, &c->d_amax, 1));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return MBDDC_OK;
+}
+
+int ensure_apply_buffers(mbddc_ctx* c, int R) {
+  if (c->R_alloc >= R) {
+    if (c->Y_R != R) {   // clamped entries of the output block are never written by the apply
+      HIPCHK(hipMemsetAsync(c->d_Y, 0, c->plan.n_dofs * c->R_alloc * sizeof(double), c->stream));
+      c->Y_R = R;
+    }
+    return MBDDC_OK;
+  }
+  const Plan& P = c->plan;
+  dfree(c, c->d_tb); dfree(c, c->d_wb); dfree(c, c->d_cc); dfree(c, c->d_ep);
+  dfree(c, c->d_X); dfree(c, c->d_Y); dfree(c, c->d_io);
+  CHK(dalloc(c, &c->d_tb, P.n_slots * R));
+  CHK(dalloc(c, &c->d_wb, P.n_slots * R));
+  CHK(dalloc(c, &c->d_cc, std::max<int64_t>(P.n_cslots, 1) * R));
+  CHK(dalloc(c, &c->d_ep, (int64_t)c->nchunk_max * std::max<int64_t>(P.n_coarse, 1) * R));
+  CHK(dalloc(c, &c->d_X, P.n_dofs * R));
+  CHK(dalloc(c, &c->d_Y, P.n_dofs * R));
+  CHK(dalloc(c, &c->d_io, P.n_dofs * R));
+  HIPCHK(hipMemsetAsync(c->d_Y, 0, P.n_dofs * R * sizeof(double), c->stream));
+  c->R_alloc = R;
+  c->Y_R = R;
+  return MBDDC_OK;
+}
+
+template <typename K>
+int set_lds(K kern, size_t bytes) {
+  static_assert(sizeof(K) > 0, "");
+  HIPCHK(hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+  return MBDDC_OK;
+}
+
+// ----------------------------------------------------------------------------
+// numeric setup (factor)
+// ----------------------------------------------------------------------------
+template <typename T>
+int run_gj(mbddc_ctx* c, T* base, const GjDesc* d_desc, int64_t count, int maxn, int32_t* d_stat, int32_t* d_pivs) {
+  if (count == 0) return MBDDC_OK;
+  constexpr int BP = sizeof(T) == 4 ? 32 : 16;
+  size_t lds = ((size_t)maxn * (BP + 1) + (size_t)BP * maxn) * sizeof(T);
+  lds = std::max<size_t>(lds, 16);
+  CHK(set_lds(k_gj_batched<T, BP>, lds));
+  hipLaunchKernelGGL((k_gj_batched<T, BP>), dim3((unsigned)count), dim3(kBlock), lds, c->stream, base, d_desc, d_pivs,
+                     d_stat);
+  HIPCHK(hipGetLastError());
+  return MBDDC_OK;
+}
+
+int check_status(mbddc_ctx* c, int64_t count, const std::vector<GjDesc>& descs, int* bad) {
+  std::vector<int32_t> st(count);
+  if (count == 0) return MBDDC_OK;
+  HIPCHK(hipMemcpyAsync(st.data(), c->d_status, count * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  for (int64_t i = 0; i < count; ++i)
+    if (st[i] != 0) {
+      *bad = descs[i].id;
+      return MBDDC_ERR_SINGULAR;
+    }
+  return MBDDC_OK;
+}
+
+__global__ void k_absmax(const double* __restrict__ A, int n, int ld, double* out) {
+  double m = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < (int64_t)n * n; i += (int64_t)gridDim.x * kBlock) {
+    int r = (int)(i / n), cc = (int)(i % n);
+    m = fmax(m, fabs(A[(int64_t)r * ld + cc]));
+  }
+  m = wave_max(m);
+  if ((threadIdx.x & 63) == 0) atomicMax(reinterpret_cast<unsigned long long*>(out), (unsigned long long)__double_as_longlong(m));
+}
+
+int coarse_invert_large(mbddc_ctx* c, int32_t ii) {
+  const int n = c->inst_nc[ii], ld = c->inst_kc_ld[ii];
+  double* A = c->d_Kc + c->inst_kc_off[ii];
+  HIPCHK(hipMemsetAsync(c->d_amax, 0, sizeof(double), c->stream));
+  hipLaunchKernelGGL(k_absmax, dim3(512), dim3(kBlock), 0, c->stream, A, n, ld, c->d_amax);
+  double amax = 0.0;
+  HIPCHK(hipMemcpyAsync(&amax, c->d_amax, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipMemsetAsync(c->d_status, 0, sizeof(int32_t), c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  const double thresh = (double)n * 2.220446049250313e-16 * amax;
+  // single-problem GEMM descriptor re-used for every diagonal block
+  GemmDesc gd{};
+  gd.M = n; gd.N = n; gd.K = kCoarseBlock; gd.lda = kCoarseBlock; gd.ldb = ld; gd.ldc = ld; gd.ldci = ld;
+  gd.tiles_n = (n + 63) / 64; gd.oA = 0; gd.oB = 0; gd.oC = 0; gd.oCi = 0; gd.alpha = -1.0; gd.beta = 1.0;
+  std::vector<GemmItem> items;
+  for (int a = 0; a < (n + 63) / 64; ++a)
+    for (int b = 0; b < gd.tiles_n; ++b) items.push_back({0, a, b, 0});
+  GemmDesc* d_gd = nullptr;
+  GemmItem* d_items = nullptr;
+  CHK(upload(c, &d_gd, std::vector<GemmDesc>{gd}));
+  CHK(upload(c, &d_items, items));
+  const unsigned ncb = nblk(n, 64);
+  for (int k0 = 0; k0 < n; k0 += kCoarseBlock) {
+    hipLaunchKernelGGL(k_cgj_diag, dim3(1), dim3(kBlock), 0, c->stream, A, n, ld, k0, c->d_cDinv, c->d_piv_c,
+                       c->d_status, thresh);
+    hipLaunchKernelGGL(k_cgj_prep, dim3(ncb), dim3(kBlock), 0, c->stream, A, n, ld, k0, c->d_cDinv, c->d_piv_c,
+                       c->d_cY, c->d_cCcol);
+    hipLaunchKernelGGL(k_cgj_clear_panel, dim3(std::min<unsigned>(1024, nblk((int64_t)n * kCoarseBlock))), dim3(kBlock),
+                       0, c->stream, A, n, ld, k0);
+    hipLaunchKernelGGL((k_gemm_batched<double>), dim3((unsigned)items.size()), dim3(kBlock), 0, c->stream, d_gd,
+                       d_items, c->d_cCcol, c->d_cY, A, A);
+    hipLaunchKernelGGL(k_cgj_rows, dim3(std::min<unsigned>(1024, nblk((int64_t)n * kCoarseBlock))), dim3(kBlock), 0,
+                       c->stream, A, n, ld, k0, c->d_cY);
+  }
+  hipLaunchKernelGGL(k_cgj_unswap, dim3(ncb, (unsigned)((n + kCoarseBlock - 1) / kCoarseBlock)), dim3(kBlock), 0,
+                     c->stream, A, n, ld, c->d_piv_c);
+  HIPCHK(hipGetLastError());
+  int32_t st = 0;
+  HIPCHK(hipMemcpyAsync(&st, c->d_status, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  dfree(c, d_gd);
+  dfree(c, d_items);
+  if (st != 0) {
+    c->last_bad = -1;
+    return MBDDC_ERR_SINGULAR;
+  }
+  return MBDDC_OK;
+}
+
+template <typename T, typename To>
+int factor_impl(mbddc_ctx* c) {
+  const Plan& P = c->plan;
+  T* W = reinterpret_cast<T*>(c->d_W);
+  To* Op = reinterpret_cast<To*>(c->d_Op);
+  const unsigned nsub = (unsigned)P.n_sub;
+  hipLaunchKernelGGL((k_assemble_local<T>), dim3(nsub), dim3(kBlock), 0, c->stream, c->d_Ke, c->d_subs,
+                     c->d_sub_elems, c->d_ke_off, c->d_elem_npe, c->d_elem_ldof, c->d_elem_ldof_off, W);
+  HIPCHK(hipGetLastError());
+  int maxI = 1, maxP = 1;
+  for (const SubDev& d : c->subs) {
+    maxI = std::max(maxI, d.nI);
+    maxP = std::max(maxP, d.nG + d.nc);
+  }
+  CHK(run_gj<T>(c, W, c->d_gj_kii, (int64_t)c->gj_kii.size(), maxI, c->d_status, c->d_piv));
+  int bad = 0;
+  int st = check_status(c, (int64_t)c->gj_kii.size(), c->gj_kii, &bad);
+  if (st) {
+    c->last_bad = bad;
+    return st;
+  }
+  if (!c->gemm_items_gh.empty())
+    hipLaunchKernelGGL((k_gemm_batched<T>), dim3((unsigned)c->gemm_items_gh.size()), dim3(kBlock), 0, c->stream,
+                       c->d_gemm_desc, c->d_gemm_gh, W, W, W, W);
+  if (!c->gemm_items_s.empty())
+    hipLaunchKernelGGL((k_gemm_batched<T>), dim3((unsigned)c->gemm_items_s.size()), dim3(kBlock), 0, c->stream,
+                       c->d_gemm_desc, c->d_gemm_s, W, W, W, W);
+  hipLaunchKernelGGL((k_build_constraints<T>), dim3(nsub), dim3(kBlock), 0, c->stream, c->d_subs, c->d_cons_ptr,
+                     c->d_cons_idx, c->d_cons_w, W);
+  HIPCHK(hipGetLastError());
+  CHK(run_gj<T>(c, W, c->d_gj_p, (int64_t)c->gj_p.size(), maxP, c->d_status, c->d_piv));
+  st = check_status(c, (int64_t)c->gj_p.size(), c->gj_p, &bad);
+  if (st) {
+    c->last_bad = bad;
+    return st;
+  }
+  hipLaunchKernelGGL((k_extract<T, To>), dim3(nsub), dim3(kBlock), 0, c->stream, c->d_subs, c->d_slot_w, W, Op, c->d_Kcl);
+  if (P.n_coarse > 0) {
+    hipLaunchKernelGGL(k_coarse_assemble, dim3((unsigned)P.n_coarse), dim3(kBlock), 0, c->stream, c->d_subs,
+                       c->d_coarse_ptr, c->d_coarse_slots, c->d_cslot_sub, c->d_cslot_coarse, c->d_inst_coarse_off,
+                       c->d_inst_nc, c->d_inst_kc_off, c->d_inst_kc_ld, c->d_coarse_inst, c->d_Kcl, c->d_Kc);
+    HIPCHK(hipGetLastError());
+    if (c->d_Kc_keep)
+      HIPCHK(hipMemcpyAsync(c->d_Kc_keep, c->d_Kc, c->kc_elems * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    if (!c->gj_coarse_small.empty()) {
+      int maxc = 1;
+      for (auto& g : c->gj_coarse_small) maxc = std::max(maxc, g.n);
+      CHK(run_gj<double>(c, c->d_Kc, c->d_gj_cs, (int64_t)c->gj_coarse_small.size(), maxc, c->d_status, c->d_piv_c));
+      // pivots of several small coarse problems: they share d_piv_c only when one exists
+      st = check_status(c, (int64_t)c->gj_coarse_small.size(), c->gj_coarse_small, &bad);
+      if (st) {
+        c->last_bad = -1;
+        return st;
+      }
+    }
+    for (int32_t ii : c->coarse_large) CHK(coarse_invert_large(c, ii));
+  }
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return MBDDC_OK;
+}
+
+// ----------------------------------------------------------------------------
+// preconditioner application and operator product on interleaved blocks
+// ----------------------------------------------------------------------------
+template <typename To, int R>
+int apply_impl(mbddc_ctx* c, const double* r, double* z) {
+  const Plan& P = c->plan;
+  ApplyArgs a{};
+  a.subs = c->d_subs; a.sub_dofs = c->d_sub_dofs; a.slot_dof = c->d_slot_dof; a.slot_ifx = c->d_slot_ifx;
+  a.slot_owner = c->d_slot_owner; a.ifx_ptr = c->d_ifx_ptr; a.ifx_slots = c->d_ifx_slots;
+  a.cslot_coarse = c->d_cslot_coarse; a.coarse_ptr = c->d_coarse_ptr; a.coarse_slots = c->d_coarse_slots;
+  a.inst_nchunk = c->d_inst_nchunk; a.op = c->d_Op; a.kcinv = c->d_Kc; a.inst_kc_off = c->d_inst_kc_off;
+  a.inst_kc_ld = c->d_inst_kc_ld; a.inst_coarse_off = c->d_inst_coarse_off; a.inst_nc = c->d_inst_nc;
+  a.r = r; a.z = z; a.tb = c->d_tb; a.wb = c->d_wb; a.cc = c->d_cc; a.ep = c->d_ep; a.n_coarse = P.n_coarse;
+  const size_t lds_local = (size_t)(4 * 256 * R + (size_t)c->max_cols * R) * sizeof(double);
+  static bool attr_set = false;
+  if (!attr_set) {
+    size_t mx = 160 * 1024;
+    CHK(set_lds(k_apply_local<To, R, 0>, mx));
+    CHK(set_lds(k_apply_local<To, R, 1>, mx));
+    CHK(set_lds(k_apply_local<To, R, 3>, mx));
+    CHK(set_lds(k_apply_local<To, R, 4>, mx));
+    CHK(set_lds(k_apply_coarse<To, R>, mx));
+    attr_set = true;
+  }
+  if (lds_local > 160 * 1024) return MBDDC_ERR_UNSUPPORTED;
+  a.items = c->d_itA;
+  hipLaunchKernelGGL((k_apply_local<To, R, 0>), dim3((unsigned)c->itA.size()), dim3(kBlock), lds_local, c->stream, a);
+  a.items = c->d_itC;
+  hipLaunchKernelGGL((k_apply_local<To, R, 1>), dim3((unsigned)c->itC.size()), dim3(kBlock), lds_local, c->stream, a);
+  if (!c->itE.empty()) {
+    const size_t lds_c = (size_t)(4 * 256 * R + kCoarseChunk * R) * sizeof(double);
+    a.items = c->d_itE;
+    hipLaunchKernelGGL((k_apply_coarse<To, R>), dim3((unsigned)c->itE.size()), dim3(kBlock), lds_c, c->stream, a);
+  }
+  a.items = c->d_itF;
+  hipLaunchKernelGGL((k_apply_local<To, R, 3>), dim3((unsigned)c->itF.size()), dim3(kBlock), lds_local, c->stream, a);
+  a.items = c->d_itH;
+  hipLaunchKernelGGL((k_apply_local<To, R, 4>), dim3((unsigned)c->itH.size()), dim3(kBlock), lds_local, c->stream, a);
+  HIPCHK(hipGetLastError());
+  return MBDDC_OK;
+}
+
+int apply_dispatch(mbddc_ctx* c, int R, const double* r, double* z) {
+  if (c->mixed) {
+    switch (R) {
+      case 1: return apply_impl<float, 1>(c, r, z);
+      case 2: return apply_impl<float, 2>(c, r, z);
+      case 4: return apply_impl<float, 4>(c, r, z);
+      default: return apply_impl<float, 8>(c, r, z);
+    }
+  }
+  switch (R) {
+    case 1: return apply_impl<double, 1>(c, r, z);
+    case 2: return apply_impl<double, 2>(c, r, z);
+    case 4: return apply_impl<double, 4>(c, r, z);
+    default: return apply_impl<double, 8>(c, r, z);
+  }
+}
+
+int spmv_dispatch(mbddc_ctx* c, int R, const double* x, double* y) {
+  const int64_t nd = c->plan.n_dofs;
+  const unsigned g = nblk(nd * 16);
+  switch (R) {
+    case 1: hipLaunchKernelGGL(k_spmv<1>, dim3(g), dim3(kBlock), 0, c->stream, c->d_bsr_rowptr, c->d_bsr_col, c->d_vals, nd, x, y); break;
+    case 2: hipLaunchKernelGGL(k_spmv<2>, dim3(g), dim3(kBlock), 0, c->stream, c->d_bsr_rowptr, c->d_bsr_col, c->d_vals, nd, x, y); break;
+    case 4: hipLaunchKernelGGL(k_spmv<4>, dim3(g), dim3(kBlock), 0, c->stream, c->d_bsr_rowptr, c->d_bsr_col, c->d_vals, nd, x, y); break;
+    default: hipLaunchKernelGGL(k_spmv<8>, dim3(g), dim3(kBlock), 0, c->stream, c->d_bsr_rowptr, c->d_bsr_col, c->d_vals, nd, x, y); break;
+  }
+  HIPCHK(hipGetLastError());
+  return MBDDC_OK;
+}
+
+// copies the API layout [nrhs][n] (host or device) into the interleaved block dst
+int load_block(mbddc_ctx* c, const double* src, int nrhs, int R, int on_device, double* dst) {
+  const int64_t n = c->plan.n_dofs;
+  const double* s = src;
+  if (!on_device) {
+    HIPCHK(hipMemcpyAsync(c->d_io, src, (size_t)n * nrhs * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    s = c->d_io;
+  }
+  hipLaunchKernelGGL(k_to_interleaved, dim3(nblk(n * R)), dim3(kBlock), 0, c->stream, s, nrhs, R, n, c->d_free, dst);
+  HIPCHK(hipGetLastError());
+  return MBDDC_OK;
+}
+
+int store_block(mbddc_ctx* c, const double* src, int nrhs, int R, int on_device, double* dst) {
+  const int64_t n = c->plan.n_dofs;
+  double* d = on_device ? dst : c->d_io;
+  hipLaunchKernelGGL(k_from_interleaved, dim3(nblk(n * nrhs)), dim3(kBlock), 0, c->stream, src, nrhs, R, n, d);
+  HIPCHK(hipGetLastError());
+  if (!on_device)
+    HIPCHK(hipMemcpyAsync(dst, c->d_io, (size_t)n * nrhs * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return MBDDC_OK;
+}
+
+// ----------------------------------------------------------------------------
+// GMRES
+// ----------------------------------------------------------------------------
+int ensure_krylov(mbddc_ctx* c, int R) {
+  const int restart = c->opt.restart;
+  if (c->R_kry >= R && c->restart_kry == restart) return MBDDC_OK;
+  for (double** p : {&c->d_V, &c->d_Z, &c->d_Wv, &c->d_B, &c->d_x, &c->d_r, &c->d_part, &c->d_part2, &c->d_npart,
+                     &c->d_h1, &c->d_h2, &c->d_Hs, &c->d_cs, &c->d_sn, &c->d_g, &c->d_hnorm, &c->d_y, &c->d_beta})
+    dfree(c, *p);
+  dfree(c, c->d_jsys); dfree(c, c->d_nk); dfree(c, c->d_active); dfree(c, c->d_mode); dfree(c, c->d_fin);
+  if (c->h_est) (void)hipHostFree(c->h_est);
+  if (c->h_norm) (void)hipHostFree(c->h_norm);
+  c->h_est = c->h_norm = nullptr;
+  const int64_t n = c->plan.n_dofs, J = restart + 1;
+  const int64_t nsys = (int64_t)c->plan.n_inst * R;
+  const int64_t nch = (int64_t)c->chunk_inst.size();
+  CHK(dalloc(c, &c->d_V, J * n * R));
+  CHK(dalloc(c, &c->d_Z, restart * n * R));
+  CHK(dalloc(c, &c->d_Wv, n * R));
+  CHK(dalloc(c, &c->d_B, n * R));
+  CHK(dalloc(c, &c->d_x, n * R));
+  CHK(dalloc(c, &c->d_r, n * R));
+  CHK(dalloc(c, &c->d_part, nch * J * R));
+  CHK(dalloc(c, &c->d_part2, nch * J * R));
+  CHK(dalloc(c, &c->d_npart, nch * R));
+  CHK(dalloc(c, &c->d_h1, nsys * J));
+  CHK(dalloc(c, &c->d_h2, nsys * J));
+  CHK(dalloc(c, &c->d_Hs, nsys * J * J));
+  CHK(dalloc(c, &c->d_cs, nsys * J));
+  CHK(dalloc(c, &c->d_sn, nsys * J));
+  CHK(dalloc(c, &c->d_g, nsys * J));
+  CHK(dalloc(c, &c->d_hnorm, nsys));
+  CHK(dalloc(c, &c->d_y, nsys * J));
+  CHK(dalloc(c, &c->d_beta, nsys));
+  CHK(dalloc(c, &c->d_jsys, nsys));
+  CHK(dalloc(c, &c->d_nk, nsys));
+  CHK(dalloc(c, &c->d_active, nsys));
+  CHK(dalloc(c, &c->d_mode, nsys));
+  CHK(dalloc(c, &c->d_fin, nsys));
+  HIPCHK(hipHostMalloc((void**)&c->h_est, nsys * sizeof(double), hipHostMallocDefault));
+  HIPCHK(hipHostMalloc((void**)&c->h_norm, nsys * sizeof(double), hipHostMallocDefault));
+  HIPCHK(hipMemsetAsync(c->d_V, 0, J * n * R * sizeof(double), c->stream));
+  HIPCHK(hipMemsetAsync(c->d_Z, 0, restart * n * R * sizeof(double), c->stream));
+  c->R_kry = R;
+  c->restart_kry = restart;
+  return MBDDC_OK;
+}
+
+template <int R>
+int gmres_impl(mbddc_ctx* c, int nrhs, mbddc_info* info) {
+  const Plan& P = c->plan;
+  const int restart = c->opt.restart, J = restart + 1;
+  const int64_t n = P.n_dofs;
+  const int nsys = P.n_inst * R;
+  const double rtol = c->opt.rtol;
+  const int max_it = c->opt.max_it;
+  KrylovArgs ka{};
+  ka.chunk_inst = c->d_chunk_inst; ka.chunk_begin = c->d_chunk_begin; ka.inst_chunk_off = c->d_inst_chunk_off;
+  ka.nchunks = (int32_t)c->chunk_inst.size(); ka.R = R; ka.jmax1 = J; ka.nrows = n;
+  const unsigned nch = (unsigned)c->chunk_inst.size();
+  const unsigned gv = nblk(n * R);
+  const unsigned gs = nblk(nsys, 64);
+  std::vector<int32_t> j(nsys, 0), its(nsys, 0), rest(nsys, 0), nk(nsys, 0);
+  std::vector<uint8_t> active(nsys, 0), mode(nsys, 2), fin(nsys, 0), done(nsys, 0);
+  std::vector<double> bnorm(nsys, 0.0), est(nsys, 0.0), rres(nsys, 0.0);
+  auto h2d = [&](void* d, const void* h, size_t b) { return hipMemcpyAsync(d, h, b, hipMemcpyHostToDevice, c->stream); };
+  // ||b||
+  hipLaunchKernelGGL((k_residual<R>), dim3(nch), dim3(kBlock), 0, c->stream, ka, c->d_B, nullptr, nullptr, c->d_npart);
+  hipLaunchKernelGGL(k_norms, dim3(gs), dim3(64), 0, c->stream, ka, nsys, c->d_npart, c->h_norm);
+  HIPCHK(hipMemsetAsync(c->d_x, 0, n * R * sizeof(double), c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  for (int s = 0; s < nsys; ++s) {
+    bnorm[s] = c->h_norm[s];
+    int k = s % R;
+    if (k >= nrhs || bnorm[s] == 0.0) {
+      done[s] = 1;
+      continue;
+    }
+    active[s] = 1;
+    fin[s] = 1;
+    mode[s] = 0;
+  }
+  // r = b (x0 = 0): V_0 = b / ||b||, g = (||b||, 0, ...)
+  HIPCHK(h2d(c->d_fin, fin.data(), nsys));
+  HIPCHK(h2d(c->d_beta, bnorm.data(), nsys * sizeof(double)));
+  HIPCHK(h2d(c->d_jsys, j.data(), nsys * sizeof(int32_t)));
+  hipLaunchKernelGGL((k_restart<R>), dim3(gv), dim3(kBlock), 0, c->stream, ka, c->d_V, c->d_B, c->d_fin, c->d_beta,
+                     c->d_dof_inst);
+  hipLaunchKernelGGL(k_restart_g, dim3(gs), dim3(64), 0, c->stream, ka, nsys, c->d_fin, c->d_beta, c->d_g);
+  int status = MBDDC_OK;
+  while (true) {
+    bool any = false;
+    for (int s = 0; s < nsys; ++s) any |= active[s] != 0;
+    if (!any) break;
+    HIPCHK(h2d(c->d_jsys, j.data(), nsys * sizeof(int32_t)));
+    HIPCHK(h2d(c->d_active, active.data(), nsys));
+    HIPCHK(h2d(c->d_mode, mode.data(), nsys));
+    int jtop = 0;
+    for (int s = 0; s < nsys; ++s)
+      if (active[s]) jtop = std::max(jtop, j[s]);
+    hipLaunchKernelGGL((k_next_vector<R>), dim3(gv), dim3(kBlock), 0, c->stream, ka, c->d_V, c->d_Wv, c->d_jsys,
+                       c->d_mode, c->d_hnorm, c->d_dof_inst, c->d_X);
+    CHK(apply_dispatch(c, R, c->d_X, c->d_Y));
+    hipLaunchKernelGGL((k_store_z<R>), dim3(gv), dim3(kBlock), 0, c->stream, ka, c->d_Y, c->d_Z, c->d_jsys,
+                       c->d_active, c->d_dof_inst);
+    CHK(spmv_dispatch(c, R, c->d_Y, c->d_Wv));
+    // CGS2
+    hipLaunchKernelGGL((k_dots<R>), dim3(nch), dim3(kBlock), 0, c->stream, ka, c->d_V, c->d_Wv, c->d_jsys, c->d_active,
+                       jtop, c->d_part);
+    hipLaunchKernelGGL(k_reduce_dots, dim3(nblk((int64_t)nsys * (jtop + 1))), dim3(kBlock), 0, c->stream, ka, c->d_part,
+                       nsys, jtop, c->d_h1);
+    hipLaunchKernelGGL((k_update<R>), dim3(nch), dim3(kBlock), 0, c->stream, ka, c->d_V, c->d_Wv, c->d_h1, c->d_jsys,
+                       c->d_active, c->d_dof_inst, jtop, (double*)nullptr);
+    hipLaunchKernelGGL((k_dots<R>), dim3(nch), dim3(kBlock), 0, c->stream, ka, c->d_V, c->d_Wv, c->d_jsys, c->d_active,
+                       jtop, c->d_part2);
+    hipLaunchKernelGGL(k_reduce_dots, dim3(nblk((int64_t)nsys * (jtop + 1))), dim3(kBlock), 0, c->stream, ka,
+                       c->d_part2, nsys, jtop, c->d_h2);
+    hipLaunchKernelGGL((k_update<R>), dim3(nch), dim3(kBlock), 0, c->stream, ka, c->d_V, c->d_Wv, c->d_h2, c->d_jsys,
+                       c->d_active, c->d_dof_inst, jtop, c->d_npart);
+    hipLaunchKernelGGL(k_givens, dim3(gs), dim3(64), 0, c->stream, ka, nsys, c->d_h1, c->d_h2, c->d_npart, c->d_jsys,
+                       c->d_active, c->d_Hs, c->d_cs, c->d_sn, c->d_g, c->d_hnorm, c->h_est);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(c->stream));
+    bool any_fin = false;
+    for (int s = 0; s < nsys; ++s) {
+      fin[s] = 0;
+      if (!active[s]) continue;
+      its[s]++;
+      est[s] = c->h_est[s];
+      bool conv = est[s] <= rtol * bnorm[s];
+      bool brk = !(est[s] == est[s]);
+      if (conv || j[s] + 1 >= restart || its[s] >= max_it || brk) {
+        fin[s] = 1;
+        nk[s] = j[s] + 1;
+        any_fin = true;
+      } else {
+        j[s]++;
+        mode[s] = 1;
+      }
+    }
+    if (!any_fin) continue;
+    HIPCHK(h2d(c->d_fin, fin.data(), nsys));
+    HIPCHK(h2d(c->d_nk, nk.data(), nsys * sizeof(int32_t)));
+    hipLaunchKernelGGL(k_backsolve, dim3(gs), dim3(64), 0, c->stream, ka, nsys, c->d_fin, c->d_nk, c->d_Hs, c->d_g,
+                       c->d_y);
+    hipLaunchKernelGGL((k_xupdate<R>), dim3(gv), dim3(kBlock), 0, c->stream, ka, c->d_x, c->d_Z, c->d_y, c->d_fin,
+                       c->d_nk, c->d_dof_inst);
+    CHK(spmv_dispatch(c, R, c->d_x, c->d_Y));   // W of continuing systems stays intact
+    hipLaunchKernelGGL((k_residual<R>), dim3(nch), dim3(kBlock), 0, c->stream, ka, c->d_B, c->d_Y, c->d_r, c->d_npart);
+    hipLaunchKernelGGL(k_norms, dim3(gs), dim3(64), 0, c->stream, ka, nsys, c->d_npart, c->h_norm);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(c->stream));
+    std::vector<uint8_t> rs(nsys, 0);
+    std::vector<double> beta(nsys, 0.0);
+    bool any_rs = false;
+    for (int s = 0; s < nsys; ++s) {
+      if (!fin[s]) continue;
+      rres[s] = c->h_norm[s];
+      if (rres[s] <= rtol * bnorm[s]) {
+        active[s] = 0;
+        done[s] = 1;
+      } else if (its[s] >= max_it || !(rres[s] == rres[s])) {
+        active[s] = 0;
+        done[s] = 2;
+        status = MBDDC_ERR_NOCONV;
+      } else {
+        rs[s] = 1;
+        beta[s] = rres[s];
+        j[s] = 0;
+        mode[s] = 0;
+        rest[s]++;
+        any_rs = true;
+      }
+    }
+    if (any_rs) {
+      HIPCHK(h2d(c->d_fin, rs.data(), nsys));
+      HIPCHK(h2d(c->d_beta, beta.data(), nsys * sizeof(double)));
+      hipLaunchKernelGGL((k_restart<R>), dim3(gv), dim3(kBlock), 0, c->stream, ka, c->d_V, c->d_r, c->d_fin,
+                         c->d_beta, c->d_dof_inst);
+      hipLaunchKernelGGL(k_restart_g, dim3(gs), dim3(64), 0, c->stream, ka, nsys, c->d_fin, c->d_beta, c->d_g);
+    }
+  }
+  if (info) {
+    info->iterations = 0;
+    info->restarts = 0;
+    info->rel_res_true = 0.0;
+    info->rel_res_est = 0.0;
+    for (int s = 0; s < nsys; ++s) {
+      if (bnorm[s] == 0.0 || (s % R) >= nrhs) continue;
+      info->iterations = std::max(info->iterations, its[s]);
+      info->restarts = std::max(info->restarts, rest[s]);
+      info->rel_res_true = std::max(info->rel_res_true, rres[s] / bnorm[s]);
+      info->rel_res_est = std::max(info->rel_res_est, est[s] / bnorm[s]);
+    }
+    info->status = status;
+  }
+  return status;
+}
+
+int gmres_dispatch(mbddc_ctx* c, int R, int nrhs, mbddc_info* info) {
+  switch (R) {
+    case 1: return gmres_impl<1>(c, nrhs, info);
+    case 2: return gmres_impl<2>(c, nrhs, info);
+    case 4: return gmres_impl<4>(c, nrhs, info);
+    default: return gmres_impl<8>(c, nrhs, info);
+  }
+}
+
+double now_ms() {
+  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+}  // namespace
+
+// ============================================================================
+// C ABI
+// ============================================================================
+extern "C" {
+
+const char* mbddc_strerror(int status) {
+  switch (status) {
+    case MBDDC_OK: return "ok";
+    case MBDDC_ERR_ARG: return "invalid argument";
+    case MBDDC_ERR_OOM: return "device out of memory";
+    case MBDDC_ERR_SINGULAR: return "singular local or coarse problem";
+    case MBDDC_ERR_NOCONV: return "GMRES did not converge";
+    case MBDDC_ERR_DEVICE: return "HIP runtime error";
+    case MBDDC_ERR_STATE: return "call out of order";
+    case MBDDC_ERR_UNSUPPORTED: return "unsupported size or option";
+    default: return "unknown status";
+  }
+}
+
+int mbddc_default_options(mbddc_options* opt) {
+  if (!opt) return MBDDC_ERR_ARG;
+  std::memset(opt, 0, sizeof(*opt));
+  opt->primal = MBDDC_PRIMAL_V | MBDDC_PRIMAL_E;
+  opt->levels = 2;
+  opt->coarse_group = 8;
+  opt->precision = MBDDC_MIXED;
+  opt->restart = 30;
+  opt->rtol = 1e-8;
+  opt->max_it = 1000;
+  return MBDDC_OK;
+}
+
+int mbddc_create(mbddc_ctx** out, int hip_device, void* hip_stream) {
+  if (!out) return MBDDC_ERR_ARG;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return MBDDC_ERR_DEVICE;
+  if (hip_device < 0 || hip_device >= ndev) return MBDDC_ERR_ARG;
+  if (hipSetDevice(hip_device) != hipSuccess) return MBDDC_ERR_DEVICE;
+  mbddc_ctx* c = new (std::nothrow) mbddc_ctx();
+  if (!c) return MBDDC_ERR_OOM;
+  c->device = hip_device;
+  c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  mbddc_default_options(&c->opt);
+  *out = c;
+  return MBDDC_OK;
+}
+
+int mbddc_destroy(mbddc_ctx* c) {
+  if (!c) return MBDDC_OK;
+  (void)hipSetDevice(c->device);
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  else (void)hipDeviceSynchronize();
+  free_all(c);
+  delete c;
+  return MBDDC_OK;
+}
+
+int mbddc_setup_symbolic_batch(mbddc_ctx* c, int n_inst, const mbddc_mesh* meshes, const mbddc_options* opt) {
+  if (!c || n_inst <= 0 || !meshes) return MBDDC_ERR_ARG;
+  if (hipSetDevice(c->device) != hipSuccess) return MBDDC_ERR_DEVICE;
+  mbddc_options o;
+  if (opt) o = *opt;
+  else mbddc_default_options(&o);
+  if (o.levels != 2 || o.restart < 1 || o.restart > 63 || !(o.rtol > 0.0) || o.max_it < 1 ||
+      (o.precision != MBDDC_FP64 && o.precision != MBDDC_MIXED && o.precision != MBDDC_MIXED_F32FACT) ||
+      (o.primal & ~7u))
+    return MBDDC_ERR_ARG;
+  std::vector<MeshIn> ms(n_inst);
+  for (int i = 0; i < n_inst; ++i) {
+    const mbddc_mesh& m = meshes[i];
+    if (m.n_nodes <= 0 || m.n_elems <= 0 || m.n_sub <= 0 || !m.elem_nodes || !m.elem_part ||
+        (m.n_dirichlet > 0 && !m.dirichlet_dofs) || m.n_dirichlet < 0)
+      return MBDDC_ERR_ARG;
+    int npe = m.elem_type == MBDDC_HEX8 ? 8 : (m.elem_type == MBDDC_HEX27 ? 27 : 0);
+    if (!npe) return MBDDC_ERR_ARG;
+    MeshIn& mi = ms[i];
+    mi.n_nodes = m.n_nodes; mi.n_elems = m.n_elems; mi.npe = npe; mi.n_sub = m.n_sub;
+    mi.elem_nodes.assign(m.elem_nodes, m.elem_nodes + (int64_t)m.n_elems * npe);
+    mi.elem_part.assign(m.elem_part, m.elem_part + m.n_elems);
+    if (m.node_tags) mi.node_tags.assign(m.node_tags, m.node_tags + m.n_nodes);
+    if (m.n_dirichlet > 0) mi.dirichlet.assign(m.dirichlet_dofs, m.dirichlet_dofs + m.n_dirichlet);
+  }
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  free_all(c);
+  c->subs.clear();
+  c->R_alloc = 0; c->R_kry = 0; c->restart_kry = 0; c->Y_R = 0;
+  c->d_tb = c->d_wb = c->d_cc = nullptr;
+  c->d_ep = c->d_X = c->d_Y = c->d_io = nullptr;
+  c->d_V = c->d_Z = c->d_Wv = c->d_B = c->d_x = c->d_r = nullptr;
+  c->d_part = c->d_part2 = c->d_npart = c->d_h1 = c->d_h2 = c->d_Hs = c->d_cs = c->d_sn = c->d_g = nullptr;
+  c->d_hnorm = c->d_y = c->d_beta = nullptr;
+  c->d_jsys = c->d_nk = nullptr;
+  c->d_active = c->d_mode = c->d_fin = nullptr;
+  c->d_Kc_keep = nullptr;
+  c->d_cDinv = c->d_cY = c->d_cCcol = nullptr;
+  c->opt = o;
+  c->mixed = (o.precision != MBDDC_FP64);
+  c->fact32 = (o.precision == MBDDC_MIXED_F32FACT);
+  c->state = 0;
+  std::string err = build_plan(ms, o.primal, c->plan);
+  if (!err.empty()) return MBDDC_ERR_ARG;
+  int st = build_layout(c);
+  if (st) return st;
+  st = upload_plan(c);
+  if (st) {
+    free_all(c);
+    return st;
+  }
+  c->state = 1;
+  return MBDDC_OK;
+}
+
+int mbddc_setup_symbolic(mbddc_ctx* c, const mbddc_mesh* mesh, const mbddc_options* opt) {
+  return mbddc_setup_symbolic_batch(c, 1, mesh, opt);
+}
+
+int mbddc_footprint(const mbddc_ctx* c, size_t* device_bytes) {
+  if (!c || !device_bytes) return MBDDC_ERR_ARG;
+  if (c->state < 1) return MBDDC_ERR_STATE;
+  const Plan& P = c->plan;
+  const size_t es = elem_size(c->mixed);
+  const int R = 4, J = c->opt.restart + 1;
+  size_t extra = 0;
+  extra += (size_t)P.n_slots * R * 8 * 2 + (size_t)std::max<int64_t>(P.n_cslots, 1) * R * 8;
+  extra += (size_t)c->nchunk_max * std::max<int64_t>(P.n_coarse, 1) * R * 8;
+  extra += (size_t)P.n_dofs * R * 8 * (3 + 2 * J + 4);
+  *device_bytes = c->bytes + extra;
+  return MBDDC_OK;
+}
+
+int mbddc_get_sizes(const mbddc_ctx* c, mbddc_sizes* out) {
+  if (!c || !out) return MBDDC_ERR_ARG;
+  if (c->state < 1) return MBDDC_ERR_STATE;
+  const Plan& P = c->plan;
+  out->n_dofs = P.n_dofs;
+  out->n_free = P.n_free;
+  out->n_interface = P.n_ifx;
+  out->n_coarse = P.n_coarse;
+  out->n_sub = P.n_sub;
+  out->n_instances = P.n_inst;
+  out->n_vertices = P.n_vertices;
+  out->n_edges = P.n_edges;
+  out->n_faces = P.n_faces;
+  out->max_local = P.max_local;
+  out->bsr_blocks = c->nblocks;
+  return MBDDC_OK;
+}
+
+int mbddc_set_tangent(mbddc_ctx* c, const double* elem_K, int on_device) {
+  if (!c || !elem_K) return MBDDC_ERR_ARG;
+  if (c->state < 1) return MBDDC_ERR_STATE;
+  if (hipSetDevice(c->device) != hipSuccess) return MBDDC_ERR_DEVICE;
+  const Plan& P = c->plan;
+  if (!on_device) {
+    for (int64_t i = 0; i < P.ke_total; ++i)
+      if (!std::isfinite(elem_K[i])) return MBDDC_ERR_ARG;
+  }
+  HIPCHK(hipMemcpyAsync(c->d_Ke, elem_K, P.ke_total * sizeof(double),
+                        on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->stream));
+  hipLaunchKernelGGL(k_assemble_bsr, dim3(nblk(c->nblocks * 9)), dim3(kBlock), 0, c->stream, c->d_Ke, c->d_bsr_rowptr,
+                     c->d_bsr_rownode, c->d_bsr_col, c->d_bsr_cptr, c->d_bsr_contrib, c->d_bsr_kstride, c->d_free,
+                     c->nblocks, c->d_vals);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(c->stream));
+  c->state = std::max(c->state, 2);
+  return MBDDC_OK;
+}
+
+int mbddc_factor(mbddc_ctx* c) {
+  if (!c) return MBDDC_ERR_ARG;
+  if (c->state < 2) return MBDDC_ERR_STATE;
+  if (hipSetDevice(c->device) != hipSuccess) return MBDDC_ERR_DEVICE;
+  c->last_bad = 0;
+  int st = c->fact32 ? factor_impl<float, float>(c)
+                     : (c->mixed ? factor_impl<double, float>(c) : factor_impl<double, double>(c));
+  if (st != MBDDC_OK) {
+    c->state = 2;
+    return st;
+  }
+  c->state = 3;
+  return MBDDC_OK;
+}
+
+int mbddc_apply(mbddc_ctx* c, int nrhs, const double* r, double* z, int on_device) {
+  if (!c || !r || !z || nrhs < 1 || nrhs > kMaxRhs) return MBDDC_ERR_ARG;
+  if (c->state < 3) return MBDDC_ERR_STATE;
+  if (hipSetDevice(c->device) != hipSuccess) return MBDDC_ERR_DEVICE;
+  const int R = apply_R(nrhs);
+  CHK(ensure_apply_buffers(c, R));
+  CHK(load_block(c, r, nrhs, R, on_device, c->d_X));
+  CHK(apply_dispatch(c, R, c->d_X, c->d_Y));
+  return store_block(c, c->d_Y, nrhs, R, on_device, z);
+}
+
+int mbddc_matvec(mbddc_ctx* c, int nrhs, const double* x, double* y, int on_device) {
+  if (!c || !x || !y || nrhs < 1 || nrhs > kMaxRhs) return MBDDC_ERR_ARG;
+  if (c->state < 2) return MBDDC_ERR_STATE;
+  if (hipSetDevice(c->device) != hipSuccess) return MBDDC_ERR_DEVICE;
+  const int R = apply_R(nrhs);
+  CHK(ensure_apply_buffers(c, R));
+  CHK(load_block(c, x, nrhs, R, on_device, c->d_X));
+  CHK(spmv_dispatch(c, R, c->d_X, c->d_Y));
+  return store_block(c, c->d_Y, nrhs, R, on_device, y);
+}
+
+int mbddc_solve(mbddc_ctx* c, int nrhs, const double* b, double* x, int on_device, mbddc_info* info) {
+  if (!c || !b || !x || nrhs < 1 || nrhs > kMaxRhs) return MBDDC_ERR_ARG;
+  if (c->state < 3) return MBDDC_ERR_STATE;
+  if (hipSetDevice(c->device) != hipSuccess) return MBDDC_ERR_DEVICE;
+  double t0 = now_ms();
+  const int R = apply_R(nrhs);
+  CHK(ensure_apply_buffers(c, R));
+  CHK(ensure_krylov(c, R));
+  CHK(load_block(c, b, nrhs, R, on_device, c->d_B));
+  int st = gmres_dispatch(c, R, nrhs, info);
+  int st2 = store_block(c, c->d_x, nrhs, R, on_device, x);
+  if (info) {
+    info->ms_solve = now_ms() - t0;
+    info->bad_subdomain = 0;
+  }
+  return st != MBDDC_OK ? st : st2;
+}
+
+int mbddc_get_globs(const mbddc_ctx* c, int32_t* node_glob, int32_t* n_globs, int32_t* glob_kind,
+                    int32_t* coarse_glob, int32_t* coarse_comp) {
+  if (!c) return MBDDC_ERR_ARG;
+  if (c->state < 1) return MBDDC_ERR_STATE;
+  const Plan& P = c->plan;
+  if (node_glob) std::copy(P.node_glob.begin(), P.node_glob.end(), node_glob);
+  if (n_globs) *n_globs = (int32_t)P.glob_kind.size();
+  if (glob_kind) std::copy(P.glob_kind.begin(), P.glob_kind.end(), glob_kind);
+  if (coarse_glob) std::copy(P.coarse_glob.begin(), P.coarse_glob.end(), coarse_glob);
+  if (coarse_comp) std::copy(P.coarse_comp.begin(), P.coarse_comp.end(), coarse_comp);
+  return MBDDC_OK;
+}
+
+int mbddc_get_coarse_matrix(const mbddc_ctx* c, int inst, double* out, int64_t n_c) {
+  if (!c || !out || inst < 0) return MBDDC_ERR_ARG;
+  if (c->state < 3 || !c->d_Kc_keep) return MBDDC_ERR_STATE;
+  if (inst >= c->plan.n_inst || n_c != c->inst_nc[inst]) return MBDDC_ERR_ARG;
+  const int ld = c->inst_kc_ld[inst];
+  std::vector<double> t((size_t)ld * std::max<int64_t>(n_c, 1));
+  if (hipMemcpy(t.data(), c->d_Kc_keep + c->inst_kc_off[inst], t.size() * sizeof(double), hipMemcpyDeviceToHost) !=
+      hipSuccess)
+    return MBDDC_ERR_DEVICE;
+  for (int64_t k = 0; k < n_c; ++k)
+    for (int64_t l = 0; l < n_c; ++l) out[l * n_c + k] = t[(size_t)k * ld + l];   // stored transposed
+  return MBDDC_OK;
+}
+
+int mbddc_get_bsr(const mbddc_ctx* c, int32_t* rowptr, int32_t* colidx, double* vals) {
+  if (!c) return MBDDC_ERR_ARG;
+  if (c->state < 2) return MBDDC_ERR_STATE;
+  const Plan& P = c->plan;
+  if (rowptr) std::copy(P.bsr_rowptr.begin(), P.bsr_rowptr.end(), rowptr);
+  if (colidx) std::copy(P.bsr_col.begin(), P.bsr_col.end(), colidx);
+  if (vals) {
+    std::vector<double> v(c->nblocks * 9);
+    if (hipMemcpy(v.data(), c->d_vals, v.size() * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
+      return MBDDC_ERR_DEVICE;
+    for (int64_t n = 0; n < P.n_nodes; ++n) {
+      int32_t r0 = P.bsr_rowptr[n], nb = P.bsr_rowptr[n + 1] - r0;
+      for (int32_t j = 0; j < nb; ++j)
+        for (int p = 0; p < 3; ++p)
+          for (int q = 0; q < 3; ++q)
+            vals[9LL * (r0 + j) + 3 * p + q] = v[9LL * r0 + (int64_t)p * 3 * nb + 3LL * j + q];
+    }
+  }
+  return MBDDC_OK;
+}
+
+int mbddc_last_bad_subdomain(const mbddc_ctx* c) { return c ? c->last_bad : 0; }
+
+int mbddc_inspect_symbolic(const mbddc_mesh* m, uint32_t primal, mbddc_sizes* sizes, int32_t* node_glob,
+                           int32_t* glob_kind, int32_t* coarse_glob, int32_t* coarse_comp, int32_t* sub_counts) {
+  if (!m || (primal & ~7u)) return MBDDC_ERR_ARG;
+  int npe = m->elem_type == MBDDC_HEX8 ? 8 : (m->elem_type == MBDDC_HEX27 ? 27 : 0);
+  if (!npe || m->n_nodes <= 0 || m->n_elems <= 0 || m->n_sub <= 0 || !m->elem_nodes || !m->elem_part ||
+      m->n_dirichlet < 0 || (m->n_dirichlet > 0 && !m->dirichlet_dofs))
+    return MBDDC_ERR_ARG;
+  std::vector<MeshIn> ms(1);
+  MeshIn& mi = ms[0];
+  mi.n_nodes = m->n_nodes; mi.n_elems = m->n_elems; mi.npe = npe; mi.n_sub = m->n_sub;
+  mi.elem_nodes.assign(m->elem_nodes, m->elem_nodes + (int64_t)m->n_elems * npe);
+  mi.elem_part.assign(m->elem_part, m->elem_part + m->n_elems);
+  if (m->node_tags) mi.node_tags.assign(m->node_tags, m->node_tags + m->n_nodes);
+  if (m->n_dirichlet > 0) mi.dirichlet.assign(m->dirichlet_dofs, m->dirichlet_dofs + m->n_dirichlet);
+  Plan P;
+  if (!build_plan(ms, primal, P).empty()) return MBDDC_ERR_ARG;
+  if (sizes) {
+    sizes->n_dofs = P.n_dofs; sizes->n_free = P.n_free; sizes->n_interface = P.n_ifx; sizes->n_coarse = P.n_coarse;
+    sizes->n_sub = P.n_sub; sizes->n_instances = 1; sizes->n_vertices = P.n_vertices; sizes->n_edges = P.n_edges;
+    sizes->n_faces = P.n_faces; sizes->max_local = P.max_local; sizes->bsr_blocks = (int64_t)P.bsr_col.size();
+  }
+  if (node_glob) std::copy(P.node_glob.begin(), P.node_glob.end(), node_glob);
+  if (glob_kind) std::copy(P.glob_kind.begin(), P.glob_kind.end(), glob_kind);
+  if (coarse_glob) std::copy(P.coarse_glob.begin(), P.coarse_glob.end(), coarse_glob);
+  if (coarse_comp) std::copy(P.coarse_comp.begin(), P.coarse_comp.end(), coarse_comp);
+  if (sub_counts)
+    for (int64_t s = 0; s < P.n_sub; ++s) {
+      sub_counts[3 * s] = P.subs[s].nI;
+      sub_counts[3 * s + 1] = P.subs[s].nG;
+      sub_counts[3 * s + 2] = P.subs[s].nc;
+    }
+  return MBDDC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,292 @@
+"""Thin ctypes binding of the C ABI declared in ``include/mbddc.h``.
+
+Argument marshalling only: every step of the solver runs in the HIP library
+``libmbddc.so`` built next to this file. If the library is missing the import
+of any entry point raises; there is no fallback path.
+
+Arrays may be numpy arrays (host) or torch CUDA/HIP tensors (device); device
+tensors are passed as raw pointers with ``on_device=1`` and must be contiguous
+float64 tensors on the handle's device.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmbddc.so")
+
+MBDDC_OK, MBDDC_ERR_ARG, MBDDC_ERR_OOM, MBDDC_ERR_SINGULAR = 0, -1, -2, -3
+MBDDC_ERR_NOCONV, MBDDC_ERR_DEVICE, MBDDC_ERR_STATE, MBDDC_ERR_UNSUPPORTED = -4, -5, -6, -7
+MBDDC_HEX8, MBDDC_HEX27 = 1, 2
+MBDDC_PRIMAL_V, MBDDC_PRIMAL_E, MBDDC_PRIMAL_F = 1, 2, 4
+MBDDC_FP64, MBDDC_MIXED, MBDDC_MIXED_F32FACT = 0, 1, 2
+
+_i32p = ctypes.POINTER(ctypes.c_int32)
+_u32p = ctypes.POINTER(ctypes.c_uint32)
+_f64p = ctypes.POINTER(ctypes.c_double)
+
+
+class mbddc_mesh(ctypes.Structure):
+    _fields_ = [("n_nodes", ctypes.c_int32), ("coords", _f64p), ("n_elems", ctypes.c_int32),
+                ("elem_type", ctypes.c_int32), ("elem_nodes", _i32p), ("n_sub", ctypes.c_int32),
+                ("elem_part", _i32p), ("node_tags", _u32p), ("n_dirichlet", ctypes.c_int32),
+                ("dirichlet_dofs", _i32p)]
+
+
+class mbddc_options(ctypes.Structure):
+    _fields_ = [("primal", ctypes.c_uint32), ("levels", ctypes.c_int32), ("coarse_group", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("restart", ctypes.c_int32), ("rtol", ctypes.c_double),
+                ("max_it", ctypes.c_int32), ("symmetric_hint", ctypes.c_int32), ("tune_table", ctypes.c_char_p),
+                ("keep_coarse_matrix", ctypes.c_int32)]
+
+
+class mbddc_info(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("restarts", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("bad_subdomain", ctypes.c_int32), ("rel_res_true", ctypes.c_double),
+                ("rel_res_est", ctypes.c_double), ("ms_setup", ctypes.c_double), ("ms_factor", ctypes.c_double),
+                ("ms_solve", ctypes.c_double)]
+
+
+class mbddc_sizes(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in ("n_dofs", "n_free", "n_interface", "n_coarse", "n_sub",
+                                               "n_instances", "n_vertices", "n_edges", "n_faces", "max_local",
+                                               "bsr_blocks")]
+
+
+_lib = None
+
+# (name, argtypes) for every entry point of include/mbddc.h
+_SIGNATURES = {
+    "mbddc_create": [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int, ctypes.c_void_p],
+    "mbddc_default_options": [ctypes.POINTER(mbddc_options)],
+    "mbddc_setup_symbolic": [ctypes.c_void_p, ctypes.POINTER(mbddc_mesh), ctypes.POINTER(mbddc_options)],
+    "mbddc_setup_symbolic_batch": [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(mbddc_mesh),
+                                   ctypes.POINTER(mbddc_options)],
+    "mbddc_footprint": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t)],
+    "mbddc_get_sizes": [ctypes.c_void_p, ctypes.POINTER(mbddc_sizes)],
+    "mbddc_set_tangent": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int],
+    "mbddc_factor": [ctypes.c_void_p],
+    "mbddc_solve": [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                    ctypes.POINTER(mbddc_info)],
+    "mbddc_apply": [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int],
+    "mbddc_matvec": [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int],
+    "mbddc_get_globs": [ctypes.c_void_p, _i32p, _i32p, _i32p, _i32p, _i32p],
+    "mbddc_get_coarse_matrix": [ctypes.c_void_p, ctypes.c_int, _f64p, ctypes.c_int64],
+    "mbddc_get_bsr": [ctypes.c_void_p, _i32p, _i32p, _f64p],
+    "mbddc_inspect_symbolic": [ctypes.POINTER(mbddc_mesh), ctypes.c_uint32, ctypes.POINTER(mbddc_sizes), _i32p,
+                               _i32p, _i32p, _i32p, _i32p],
+    "mbddc_last_bad_subdomain": [ctypes.c_void_p],
+    "mbddc_destroy": [ctypes.c_void_p],
+    "mbddc_strerror": [ctypes.c_int],
+}
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP library not built: {LIB_PATH} (run __graft_entry__.build())")
+        try:
+            # torch ships its own HIP runtime under the same soname; loading it first makes the
+            # library bind to that runtime, so device memory and streams are shared with torch
+            import torch  # noqa: F401
+        except ImportError:
+            pass
+        L = ctypes.CDLL(LIB_PATH)
+        for name, args in _SIGNATURES.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = ctypes.c_char_p if name == "mbddc_strerror" else ctypes.c_int
+        _lib = L
+    return _lib
+
+
+class MbddcError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        super().__init__(f"{where}: {lib().mbddc_strerror(status).decode()} ({status})")
+        self.status = status
+
+
+def _check(st: int, where: str):
+    if st != MBDDC_OK:
+        raise MbddcError(st, where)
+
+
+def _ptr(a, ctype):
+    return a.ctypes.data_as(ctypes.POINTER(ctype)) if a is not None else None
+
+
+class _MeshArrays:
+    """Keeps the numpy buffers of an mbddc_mesh alive."""
+
+    def __init__(self, coords, elem_nodes, elem_type, elem_part, n_sub, node_tags, dirichlet):
+        self.coords = None if coords is None else np.ascontiguousarray(coords, dtype=np.float64)
+        self.elem_nodes = np.ascontiguousarray(elem_nodes, dtype=np.int32)
+        self.elem_part = np.ascontiguousarray(elem_part, dtype=np.int32)
+        self.node_tags = None if node_tags is None else np.ascontiguousarray(node_tags, dtype=np.uint32)
+        self.dirichlet = np.ascontiguousarray(dirichlet, dtype=np.int32)
+        n_nodes = int(self.elem_nodes.max()) + 1 if self.coords is None else self.coords.shape[0]
+        self.mesh = mbddc_mesh(n_nodes, _ptr(self.coords, ctypes.c_double), self.elem_nodes.shape[0], elem_type,
+                               _ptr(self.elem_nodes, ctypes.c_int32), int(n_sub), _ptr(self.elem_part, ctypes.c_int32),
+                               _ptr(self.node_tags, ctypes.c_uint32), len(self.dirichlet),
+                               _ptr(self.dirichlet, ctypes.c_int32))
+
+
+def mesh_from_problem(P) -> _MeshArrays:
+    """mbddc_mesh of a workloads.Problem."""
+    m = P.mesh
+    return _MeshArrays(m.coords, m.elem_nodes, m.elem_type, P.elem_part, P.n_sub, m.node_tags, P.dirichlet)
+
+
+def default_options(**kw) -> mbddc_options:
+    o = mbddc_options()
+    _check(lib().mbddc_default_options(ctypes.byref(o)), "mbddc_default_options")
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def mbddc_inspect_symbolic(mesh: _MeshArrays, primal: int):
+    """Host-only symbolic setup: (sizes, node_glob, glob_kind, coarse_glob, coarse_comp, sub_counts)."""
+    L = lib()
+    sz = mbddc_sizes()
+    _check(L.mbddc_inspect_symbolic(ctypes.byref(mesh.mesh), primal, ctypes.byref(sz), None, None, None, None, None),
+           "mbddc_inspect_symbolic")
+    ng = sz.n_vertices + sz.n_edges + sz.n_faces
+    node_glob = np.empty(mesh.mesh.n_nodes, np.int32)
+    kind = np.empty(max(ng, 1), np.int32)
+    cg = np.empty(max(sz.n_coarse, 1), np.int32)
+    cc = np.empty(max(sz.n_coarse, 1), np.int32)
+    sc = np.empty(3 * sz.n_sub, np.int32)
+    _check(L.mbddc_inspect_symbolic(ctypes.byref(mesh.mesh), primal, ctypes.byref(sz), _ptr(node_glob, ctypes.c_int32),
+                                    _ptr(kind, ctypes.c_int32), _ptr(cg, ctypes.c_int32), _ptr(cc, ctypes.c_int32),
+                                    _ptr(sc, ctypes.c_int32)), "mbddc_inspect_symbolic")
+    return sz, node_glob, kind[:ng], cg[:sz.n_coarse], cc[:sz.n_coarse], sc.reshape(-1, 3)
+
+
+def _dev_ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Solver:
+    """One handle: setup_symbolic -> set_tangent -> factor -> solve/apply/matvec."""
+
+    def __init__(self, device: int = 0, stream=None):
+        self._h = ctypes.c_void_p()
+        s = None if stream is None else ctypes.c_void_p(int(stream))
+        _check(lib().mbddc_create(ctypes.byref(self._h), device, s), "mbddc_create")
+        self._meshes = []
+        self.n_dofs = 0
+
+    def close(self):
+        if self._h:
+            lib().mbddc_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- setup ------------------------------------------------------------------
+    def mbddc_setup_symbolic(self, meshes: Sequence[_MeshArrays], options: Optional[mbddc_options] = None):
+        self._meshes = list(meshes)
+        arr = (mbddc_mesh * len(meshes))(*[m.mesh for m in meshes])
+        o = options if options is not None else default_options()
+        _check(lib().mbddc_setup_symbolic_batch(self._h, len(meshes), arr, ctypes.byref(o)), "mbddc_setup_symbolic")
+        self.n_dofs = self.sizes().n_dofs
+
+    def sizes(self) -> mbddc_sizes:
+        s = mbddc_sizes()
+        _check(lib().mbddc_get_sizes(self._h, ctypes.byref(s)), "mbddc_get_sizes")
+        return s
+
+    def mbddc_footprint(self) -> int:
+        b = ctypes.c_size_t()
+        _check(lib().mbddc_footprint(self._h, ctypes.byref(b)), "mbddc_footprint")
+        return b.value
+
+    def mbddc_set_tangent(self, Ke):
+        if isinstance(Ke, np.ndarray):
+            Ke = np.ascontiguousarray(Ke, dtype=np.float64)
+            _check(lib().mbddc_set_tangent(self._h, Ke.ctypes.data_as(ctypes.c_void_p), 0), "mbddc_set_tangent")
+        else:
+            _check(lib().mbddc_set_tangent(self._h, _dev_ptr(Ke), 1), "mbddc_set_tangent")
+
+    def mbddc_factor(self):
+        _check(lib().mbddc_factor(self._h), "mbddc_factor")
+
+    def last_bad_subdomain(self) -> int:
+        return lib().mbddc_last_bad_subdomain(self._h)
+
+    # -- per-call ----------------------------------------------------------------
+    def _vec_call(self, fn, name, v, out=None):
+        if isinstance(v, np.ndarray):
+            v2 = np.ascontiguousarray(np.atleast_2d(v), dtype=np.float64)
+            o = np.empty_like(v2) if out is None else out
+            st = fn(self._h, v2.shape[0], v2.ctypes.data_as(ctypes.c_void_p), o.ctypes.data_as(ctypes.c_void_p), 0)
+            _check(st, name)
+            return o if v.ndim == 2 else o[0]
+        nrhs = 1 if v.dim() == 1 else v.shape[0]
+        o = out if out is not None else v.new_empty(v.shape)
+        _check(fn(self._h, nrhs, _dev_ptr(v), _dev_ptr(o), 1), name)
+        return o
+
+    def mbddc_apply(self, r, out=None):
+        return self._vec_call(lib().mbddc_apply, "mbddc_apply", r, out)
+
+    def mbddc_matvec(self, x, out=None):
+        return self._vec_call(lib().mbddc_matvec, "mbddc_matvec", x, out)
+
+    def mbddc_solve(self, b, out=None, raise_on_noconv: bool = True):
+        info = mbddc_info()
+        if isinstance(b, np.ndarray):
+            b2 = np.ascontiguousarray(np.atleast_2d(b), dtype=np.float64)
+            x = np.empty_like(b2) if out is None else out
+            st = lib().mbddc_solve(self._h, b2.shape[0], b2.ctypes.data_as(ctypes.c_void_p),
+                                   x.ctypes.data_as(ctypes.c_void_p), 0, ctypes.byref(info))
+            res = x if b.ndim == 2 else x[0]
+        else:
+            nrhs = 1 if b.dim() == 1 else b.shape[0]
+            x = out if out is not None else b.new_empty(b.shape)
+            st = lib().mbddc_solve(self._h, nrhs, _dev_ptr(b), _dev_ptr(x), 1, ctypes.byref(info))
+            res = x
+        if st != MBDDC_OK and (raise_on_noconv or st != MBDDC_ERR_NOCONV):
+            raise MbddcError(st, "mbddc_solve")
+        return res, info
+
+    # -- inspection ----------------------------------------------------------------
+    def mbddc_get_globs(self):
+        sz = self.sizes()
+        ng = ctypes.c_int32()
+        node_glob = np.empty(sz.n_dofs // 3, np.int32)
+        _check(lib().mbddc_get_globs(self._h, _ptr(node_glob, ctypes.c_int32), ctypes.byref(ng), None, None, None),
+               "mbddc_get_globs")
+        kind = np.empty(max(ng.value, 1), np.int32)
+        cg = np.empty(max(sz.n_coarse, 1), np.int32)
+        cc = np.empty(max(sz.n_coarse, 1), np.int32)
+        _check(lib().mbddc_get_globs(self._h, None, None, _ptr(kind, ctypes.c_int32), _ptr(cg, ctypes.c_int32),
+                                     _ptr(cc, ctypes.c_int32)), "mbddc_get_globs")
+        return node_glob, kind[:ng.value], cg[:sz.n_coarse], cc[:sz.n_coarse]
+
+    def mbddc_get_coarse_matrix(self, inst: int, n_c: int) -> np.ndarray:
+        out = np.empty((n_c, n_c))
+        _check(lib().mbddc_get_coarse_matrix(self._h, inst, _ptr(out, ctypes.c_double), n_c),
+               "mbddc_get_coarse_matrix")
+        return out
+
+    def mbddc_get_bsr(self):
+        sz = self.sizes()
+        nn = sz.n_dofs // 3
+        rowptr = np.empty(nn + 1, np.int32)
+        col = np.empty(sz.bsr_blocks, np.int32)
+        vals = np.empty(9 * sz.bsr_blocks)
+        _check(lib().mbddc_get_bsr(self._h, _ptr(rowptr, ctypes.c_int32), _ptr(col, ctypes.c_int32),
+                                   _ptr(vals, ctypes.c_double)), "mbddc_get_bsr")
+        return rowptr, col, vals.reshape(-1, 3, 3)

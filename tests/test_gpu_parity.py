@@ -1,0 +1,289 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Checkpoints (paper §3.2 objects):
+* P1  assembled operator (3x3 blocks) and K x            FP64 <= 1e-14
+* P4  coarse matrix S_PiPi                               FP64 <= 1e-12, mixed <= 1e-4
+* P5  one preconditioner application z = M^-1 r          FP64 <= 1e-12, mixed <= 1e-5
+* P6  GMRES iterations                                   FP64: oracle +-1, mixed: <= oracle + 2
+*     solution (both at rtol 1e-12)                      FP64 <= 1e-8, mixed <= 1e-6
+* P7  true residual                                       <= rtol
+plus edge cases (one subdomain, ragged subdomains, Q2, every primal space,
+batched instances, several right-hand sides, failure statuses).
+"""
+import functools
+
+import numpy as np
+import pytest
+
+from oracle import bddc, fem, gmres
+from paper_2208_06191_amd import mbddc
+from paper_2208_06191_amd import workloads as W
+from tests.conftest import problem
+
+pytestmark = pytest.mark.gpu
+
+TOL_APPLY = {mbddc.MBDDC_FP64: 1e-12, mbddc.MBDDC_MIXED: 1e-5}
+TOL_COARSE = {mbddc.MBDDC_FP64: 1e-12, mbddc.MBDDC_MIXED: 1e-12}
+TOL_SOL = {mbddc.MBDDC_FP64: 1e-8, mbddc.MBDDC_MIXED: 1e-6}
+PRECS = [mbddc.MBDDC_FP64, mbddc.MBDDC_MIXED]
+
+
+@functools.lru_cache(maxsize=None)
+def oracle_of(name, primal):
+    P = problem(name)
+    dec = bddc.Decomposition(P.mesh.elem_nodes, P.mesh.n_nodes, P.elem_part, P.n_sub, P.dirichlet,
+                             P.mesh.node_tags, primal=primal)
+    return dec, bddc.BDDC(dec, P.mesh.elem_nodes, P.Ke)
+
+
+def solver_for(P, precision, primal, **kw):
+    s = mbddc.Solver(0)
+    o = mbddc.default_options(precision=precision, primal=primal, keep_coarse_matrix=1, **kw)
+    s.mbddc_setup_symbolic([mbddc.mesh_from_problem(P)], o)
+    s.mbddc_set_tangent(P.Ke)
+    s.mbddc_factor()
+    return s
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+CASES = [("small", 1), ("small_ve", 3), ("tiny_q2", 7), ("ragged", 3), ("tiny_nh", 3), ("small_ve", 6)]
+
+
+@pytest.mark.parametrize("name,primal", CASES[:4])
+def test_assembled_operator(name, primal):
+    P = problem(name)
+    dec, B = oracle_of(name, primal)
+    s = solver_for(P, mbddc.MBDDC_FP64, primal)
+    rowptr, col, vals = s.mbddc_get_bsr()
+    n = P.n_dofs
+    rows = np.repeat(np.arange(n // 3), np.diff(rowptr))
+    I = (3 * rows[:, None, None] + np.arange(3)[None, :, None]).repeat(3, axis=2).ravel()
+    J = (3 * col[:, None, None] + np.arange(3)[None, None, :]).repeat(3, axis=1).ravel()
+    import scipy.sparse as sp
+    K = sp.coo_matrix((vals.ravel(), (I, J)), shape=(n, n)).tocsr()
+    A = B.A
+    Kf = K[dec.free][:, dec.free]
+    assert abs(Kf - A).max() <= 1e-14 * abs(A).max()
+    clamped = np.setdiff1d(np.arange(n), dec.free)
+    assert abs(K[clamped]).max() == 0.0 and abs(K[:, clamped]).max() == 0.0
+    x = np.random.default_rng(0).standard_normal((2, n))
+    y = s.mbddc_matvec(x)
+    for k in range(2):
+        assert rel(y[k][dec.free], A @ x[k][dec.free]) <= 1e-14
+        assert np.abs(y[k][clamped]).max() == 0.0
+
+
+@pytest.mark.parametrize("precision", PRECS)
+@pytest.mark.parametrize("name,primal", CASES)
+def test_coarse_matrix_and_apply(name, primal, precision):
+    P = problem(name)
+    dec, B = oracle_of(name, primal)
+    s = solver_for(P, precision, primal)
+    Kc = s.mbddc_get_coarse_matrix(0, dec.n_coarse)
+    err_c = rel(Kc, B.Kc)
+    rng = np.random.default_rng(7)
+    r = rng.standard_normal((3, P.n_dofs))
+    r[:, P.dirichlet] = 0.0
+    z = s.mbddc_apply(r)
+    errs = [rel(z[k][dec.free], B.apply(r[k][dec.free])) for k in range(3)]
+    clamped = np.setdiff1d(np.arange(P.n_dofs), dec.free)
+    print(f"{name} primal={primal} prec={precision}: coarse {err_c:.2e} apply {max(errs):.2e}")
+    assert err_c <= TOL_COARSE[precision]
+    assert max(errs) <= TOL_APPLY[precision]
+    assert np.abs(z[:, clamped]).max() == 0.0
+
+
+@pytest.mark.parametrize("precision", PRECS)
+@pytest.mark.parametrize("name,primal", CASES)
+def test_solve_matches_oracle(name, primal, precision):
+    P = problem(name)
+    dec, B = oracle_of(name, primal)
+    s = solver_for(P, precision, primal)
+    x, info = s.mbddc_solve(P.rhs)
+    for k in range(P.rhs.shape[0]):
+        b = P.rhs[k][dec.free]
+        ref = gmres.gmres(lambda v: B.A @ v, B.apply, b, 1e-8, 30, 1000)
+        xr = x[k][dec.free]
+        tr = np.linalg.norm(b - B.A @ xr) / np.linalg.norm(b)
+        assert tr <= 1e-8
+        assert np.abs(x[k][P.dirichlet]).max() == 0.0
+    print(f"{name} primal={primal} prec={precision}: its {info.iterations} (oracle {ref.iterations}) "
+          f"res {info.rel_res_true:.2e}")
+    # iteration parity per right-hand side
+    for k in range(P.rhs.shape[0]):
+        b = P.rhs[k]
+        ref = gmres.gmres(lambda v: B.A @ v, B.apply, b[dec.free], 1e-8, 30, 1000)
+        _, i1 = s.mbddc_solve(b)
+        if precision == mbddc.MBDDC_FP64:
+            assert abs(i1.iterations - ref.iterations) <= 1
+        else:
+            assert i1.iterations <= ref.iterations + 2
+        assert i1.rel_res_true <= 1e-8
+
+
+@pytest.mark.parametrize("precision", PRECS)
+def test_solution_parity_tight_tolerance(precision):
+    P = problem("small_ve")
+    dec, B = oracle_of("small_ve", 3)
+    s = solver_for(P, precision, 3, rtol=1e-12)
+    b = P.rhs[0]
+    x, info = s.mbddc_solve(b)
+    ref = gmres.gmres(lambda v: B.A @ v, B.apply, b[dec.free], 1e-12, 30, 1000)
+    e = rel(x[dec.free], ref.x)
+    print(f"prec={precision}: ||x - x_oracle|| / ||x_oracle|| = {e:.2e}")
+    assert e <= TOL_SOL[precision]
+
+
+@pytest.mark.parametrize("precision", PRECS)
+def test_each_rhs_same_alone_and_in_a_batch(precision):
+    P = problem("small_ve")
+    s = solver_for(P, precision, 3)
+    rhs = np.concatenate([P.rhs, P.rhs[::-1] * 0.5])   # 4 right-hand sides
+    X, _ = s.mbddc_solve(rhs)
+    for k in range(rhs.shape[0]):
+        xk, _ = s.mbddc_solve(rhs[k])
+        assert np.array_equal(xk, X[k]), (k, rel(xk, X[k]))
+
+
+def test_batched_instances_equal_each_alone():
+    Pa, Pb = problem("small_ve"), problem("tiny_q2")
+    o = mbddc.default_options(precision=mbddc.MBDDC_FP64, primal=3)
+    s = mbddc.Solver(0)
+    s.mbddc_setup_symbolic([mbddc.mesh_from_problem(Pa), mbddc.mesh_from_problem(Pb)], o)
+    s.mbddc_set_tangent(np.concatenate([Pa.Ke.ravel(), Pb.Ke.ravel()]))
+    s.mbddc_factor()
+    b = np.concatenate([Pa.rhs[0], Pb.rhs[0]])
+    x, info = s.mbddc_solve(b)
+    for P, sl in ((Pa, slice(0, Pa.n_dofs)), (Pb, slice(Pa.n_dofs, Pa.n_dofs + Pb.n_dofs))):
+        s1 = solver_for(P, mbddc.MBDDC_FP64, 3)
+        x1, _ = s1.mbddc_solve(P.rhs[0])
+        assert rel(x[sl], x1) <= 1e-12
+
+
+def test_one_subdomain_is_one_iteration():
+    P = W.linear_box(4, 4, 1, nrhs=1, primal=1)
+    P1 = W.Problem("one", P.mesh, np.zeros_like(P.elem_part), 1, P.dirichlet, P.Ke, P.rhs, 1)
+    s = solver_for(P1, mbddc.MBDDC_FP64, 1)
+    x, info = s.mbddc_solve(P1.rhs[0])
+    A = fem.reduce_to_free(fem.assemble(P.mesh.elem_nodes, P.Ke, P.n_dofs),
+                           fem.free_dofs(P.n_dofs, P.dirichlet))
+    free = fem.free_dofs(P.n_dofs, P.dirichlet)
+    xd = np.linalg.solve(A.toarray(), P1.rhs[0][free])
+    assert info.iterations == 1
+    assert rel(x[free], xd) <= 1e-10
+
+
+def test_floating_subdomains_without_primals_are_singular():
+    P = problem("small")
+    s = mbddc.Solver(0)
+    s.mbddc_setup_symbolic([mbddc.mesh_from_problem(P)], mbddc.default_options(primal=0,
+                                                                              precision=mbddc.MBDDC_FP64))
+    s.mbddc_set_tangent(P.Ke)
+    with pytest.raises(mbddc.MbddcError) as e:
+        s.mbddc_factor()
+    assert e.value.status == mbddc.MBDDC_ERR_SINGULAR
+    bad = s.last_bad_subdomain()
+    elems = np.nonzero(P.elem_part == bad)[0]
+    assert not np.any(P.mesh.node_tags[P.mesh.elem_nodes[elems]] & 1)   # a floating subdomain
+
+
+def test_no_convergence_status_and_state_errors():
+    P = problem("small")
+    s = mbddc.Solver(0)
+    s.mbddc_setup_symbolic([mbddc.mesh_from_problem(P)], mbddc.default_options(primal=1, max_it=3))
+    with pytest.raises(mbddc.MbddcError) as e:
+        s.mbddc_factor()
+    assert e.value.status == mbddc.MBDDC_ERR_STATE
+    bad = P.Ke.copy()
+    bad[3, 2, 2] = np.nan
+    with pytest.raises(mbddc.MbddcError) as e:
+        s.mbddc_set_tangent(bad)
+    assert e.value.status == mbddc.MBDDC_ERR_ARG
+    s.mbddc_set_tangent(P.Ke)
+    s.mbddc_factor()
+    x, info = s.mbddc_solve(P.rhs[0], raise_on_noconv=False)
+    assert info.iterations == 3 and info.status == mbddc.MBDDC_ERR_NOCONV
+    assert 1e-8 < info.rel_res_true < 1.0
+
+
+def test_device_pointers_match_host_path():
+    torch = pytest.importorskip("torch")
+    P = problem("small_ve")
+    s = solver_for(P, mbddc.MBDDC_MIXED, 3)
+    xh, _ = s.mbddc_solve(P.rhs)
+    b = torch.tensor(P.rhs, device="cuda")
+    Ke = torch.tensor(P.Ke, device="cuda")
+    s.mbddc_set_tangent(Ke)
+    s.mbddc_factor()
+    xd, _ = s.mbddc_solve(b)
+    torch.cuda.synchronize()
+    assert np.array_equal(xd.cpu().numpy(), xh)
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("precision", PRECS)
+def test_paper_scale_neo_hookean_box(precision):
+    """512 subdomains, 7140 coarse DOFs (VE): apply parity, iteration parity, residuals."""
+    P = nh32()
+    dec, B = nh32_oracle()
+    s = solver_for(P, precision, 3)
+    rng = np.random.default_rng(3)
+    r = rng.standard_normal(P.n_dofs)
+    r[P.dirichlet] = 0.0
+    z = s.mbddc_apply(r)
+    e = rel(z[dec.free], B.apply(r[dec.free]))
+    x, info = s.mbddc_solve(P.rhs)
+    ref = nh32_ref()
+    print(f"32^3 prec={precision}: apply err {e:.2e}, its {info.iterations} (oracle {ref.iterations}), "
+          f"res {info.rel_res_true:.2e}")
+    assert e <= TOL_APPLY[precision]
+    assert info.rel_res_true <= 1e-8
+    _, i0 = s.mbddc_solve(P.rhs[0])
+    if precision == mbddc.MBDDC_FP64:
+        assert abs(i0.iterations - ref.iterations) <= 1
+    else:
+        assert i0.iterations <= ref.iterations + 2
+    for k in range(P.rhs.shape[0]):
+        b = P.rhs[k][dec.free]
+        assert np.linalg.norm(b - B.A @ x[k][dec.free]) <= 1e-8 * np.linalg.norm(b)
+
+
+@functools.lru_cache(maxsize=None)
+def nh32():
+    return W.config_nh32(nrhs=4)
+
+
+@functools.lru_cache(maxsize=None)
+def nh32_oracle():
+    P = nh32()
+    dec = bddc.Decomposition(P.mesh.elem_nodes, P.mesh.n_nodes, P.elem_part, P.n_sub, P.dirichlet,
+                             P.mesh.node_tags, primal=3)
+    return dec, bddc.BDDC(dec, P.mesh.elem_nodes, P.Ke)
+
+
+@functools.lru_cache(maxsize=None)
+def nh32_ref():
+    P = nh32()
+    dec, B = nh32_oracle()
+    return gmres.gmres(lambda v: B.A @ v, B.apply, P.rhs[0][dec.free], 1e-8, 30, 1000)
+
+
+@pytest.mark.parametrize("name,primal", [("small", 1), ("small_ve", 3), ("tiny_nh", 3)])
+def test_fp32_factorisation_path_converges(name, primal):
+    """FP32 local factorisations: the FP64 outer GMRES still reaches the FP64 residual; the
+    iteration overhead of the less accurate local operators is reported."""
+    P = problem(name)
+    dec, B = oracle_of(name, primal)
+    s = solver_for(P, mbddc.MBDDC_MIXED_F32FACT, primal)
+    r = np.random.default_rng(7).standard_normal(P.n_dofs)
+    r[P.dirichlet] = 0.0
+    e = rel(s.mbddc_apply(r)[dec.free], B.apply(r[dec.free]))
+    b = P.rhs[0]
+    ref = gmres.gmres(lambda v: B.A @ v, B.apply, b[dec.free], 1e-8, 30, 1000)
+    x, info = s.mbddc_solve(b)
+    print(f"{name}: FP32-factor apply error {e:.2e}, its {info.iterations} (oracle {ref.iterations})")
+    assert info.rel_res_true <= 1e-8
+    assert e <= 1e-2

@@ -1,0 +1,81 @@
+"""CPU-side checks of the HIP library: it loads, exports every entry point that
+``include/mbddc.h`` declares, and its host symbolic setup (interior/interface
+split, vertex/edge/face globs, primal constraints; paper §3.2) is integer-exact
+against the oracle's decomposition. No kernel runs here."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import bddc
+from paper_2208_06191_amd import mbddc
+from paper_2208_06191_amd import workloads as W
+from tests.conftest import problem
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "mbddc.h")
+
+
+def declared_entry_points():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:int|const char\*)\s+(mbddc_\w+)\s*\(", text, flags=re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = mbddc.lib()
+    names = declared_entry_points()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(L, n), n
+        assert n in mbddc._SIGNATURES, f"binding lacks {n}"
+    assert set(mbddc._SIGNATURES) == set(names)
+    assert L.mbddc_strerror(mbddc.MBDDC_ERR_SINGULAR) == b"singular local or coarse problem"
+
+
+def test_default_options():
+    o = mbddc.default_options()
+    assert (o.primal, o.levels, o.precision, o.restart, o.rtol, o.max_it) == (3, 2, 1, 30, 1e-8, 1000)
+
+
+def _compare_plan(P, primal):
+    dec = bddc.Decomposition(P.mesh.elem_nodes, P.mesh.n_nodes, P.elem_part, P.n_sub, P.dirichlet,
+                             P.mesh.node_tags, primal=primal)
+    sz, node_glob, kind, cg, cc, sc = mbddc.mbddc_inspect_symbolic(mbddc.mesh_from_problem(P), primal)
+    assert (sz.n_vertices, sz.n_edges, sz.n_faces) == dec.glob_counts()
+    assert sz.n_coarse == dec.n_coarse
+    assert sz.n_free == len(dec.free)
+    np.testing.assert_array_equal(node_glob, dec.node_glob)
+    np.testing.assert_array_equal(kind, [g[0] for g in dec.globs])
+    np.testing.assert_array_equal(cg, [g for g, _ in dec.coarse])
+    np.testing.assert_array_equal(cc, [c for _, c in dec.coarse])
+    for s, sd in enumerate(dec.subdomains):
+        assert tuple(sc[s]) == (sd.n_interior, len(sd.dofs) - sd.n_interior, len(sd.coarse))
+    return sz
+
+
+@pytest.mark.parametrize("name,primal", [("small", 1), ("small_ve", 3), ("small_ve", 7), ("small_ve", 6),
+                                         ("tiny_q2", 7), ("ragged", 3), ("tiny", 1)])
+def test_host_plan_equals_oracle(name, primal):
+    _compare_plan(problem(name), primal)
+
+
+def test_host_plan_equals_oracle_paper_scale_box():
+    mesh = W.box_mesh(32, 32, 32, 1)
+    part, nsub = W.block_partition(mesh, 4)
+    P = W.Problem("box32", mesh, part, nsub, W.clamp_dofs(mesh), np.zeros((1, 1)), np.zeros((1, 1)), 3)
+    sz = _compare_plan(P, 3)
+    assert sz.n_coarse == 7140 and sz.n_sub == 512
+
+
+def test_host_plan_rejects_bad_input():
+    P = problem("tiny")
+    m = mbddc.mesh_from_problem(P)
+    bad = m.elem_part.copy()
+    bad[0] = P.n_sub          # out of range
+    m2 = mbddc._MeshArrays(P.mesh.coords, P.mesh.elem_nodes, P.mesh.elem_type, bad, P.n_sub, P.mesh.node_tags,
+                           P.dirichlet)
+    with pytest.raises(mbddc.MbddcError) as e:
+        mbddc.mbddc_inspect_symbolic(m2, 1)
+    assert e.value.status == mbddc.MBDDC_ERR_ARG
+    with pytest.raises(mbddc.MbddcError):
+        mbddc.mbddc_inspect_symbolic(m, 8)   # unknown primal bit
