@@ -84,7 +84,10 @@ typedef struct {
   int32_t restart;               /* GMRES restart length, 1..64 */
   double rtol;                   /* relative residual target on ||b - K x||_2 */
   int32_t max_it;                /* Arnoldi steps summed over restarts */
-  int32_t symmetric_hint;        /* reserved */
+  int32_t symmetric_hint;        /* 1: the tangent is symmetric and positive definite on the
+                                    constrained local spaces (hyperelastic tangents): local and coarse
+                                    inverses by pivot-free symmetric sweeps; 0: general path with
+                                    partial pivoting (the paper's symmetry flag, §4 and §6.1) */
   const char* tune_table;        /* reserved, may be NULL */
   int32_t keep_coarse_matrix;    /* 1: keep S_PiPi for mbddc_get_coarse_matrix (8 n_c^2 bytes) */
 } mbddc_options;
@@ -180,6 +183,24 @@ int mbddc_get_bsr(const mbddc_ctx* ctx, int32_t* rowptr, int32_t* colidx, double
  * primal) DOFs per subdomain. */
 int mbddc_inspect_symbolic(const mbddc_mesh* mesh, uint32_t primal, mbddc_sizes* sizes, int32_t* node_glob,
                            int32_t* glob_kind, int32_t* coarse_glob, int32_t* coarse_comp, int32_t* sub_counts);
+
+/* Built-in kernel profiler. When bit f of `family_mask` is set, every launch of
+ * kernel family f is bracketed by HIP events recorded on the handle's stream;
+ * mbddc_get_profile() synchronises, returns per family the launch count, the
+ * summed event time and the summed algorithmic bytes / flops of those launches
+ * (operators and vectors counted once per launch), then resets the counters.
+ * Families: see the names returned. `out` may hold `max_entries` records. */
+typedef struct {
+  char name[32];
+  int64_t launches;
+  double ms;
+  double bytes;
+  double flops;
+} mbddc_kernel_stat;
+int mbddc_set_profiling(mbddc_ctx* ctx, uint32_t family_mask);
+/* Name of profiler family f (bit f of the mask), NULL past the last one. */
+const char* mbddc_profile_family_name(int family);
+int mbddc_get_profile(mbddc_ctx* ctx, mbddc_kernel_stat* out, int max_entries, int* n_entries);
 
 /* Subdomain of the last MBDDC_ERR_SINGULAR (-1: coarse problem). */
 int mbddc_last_bad_subdomain(const mbddc_ctx* ctx);

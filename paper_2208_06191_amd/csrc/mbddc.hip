@@ -59,6 +59,38 @@ struct DevMem {
   size_t bytes = 0;
 };
 
+// Kernel families timed by the built-in profiler.
+enum Family {
+  F_ASSEMBLE_BSR, F_ASSEMBLE_LOCAL, F_GJ_KII, F_GEMM_GH, F_GEMM_S, F_CONSTRAINTS, F_GJ_P, F_EXTRACT,
+  F_COARSE_ASSEMBLE, F_COARSE_GJ_SMALL, F_COARSE_DIAG, F_COARSE_PREP, F_COARSE_GEMM, F_COARSE_ROWS,
+  F_APPLY_A, F_APPLY_C, F_APPLY_E, F_APPLY_F, F_APPLY_H, F_SPMV, F_KRYLOV_DOTS, F_KRYLOV_UPDATE,
+  F_KRYLOV_SMALL, F_KRYLOV_VEC, F_COUNT
+};
+const char* const kFamilyName[F_COUNT] = {
+  "assemble_bsr", "assemble_local", "gj_interior", "gemm_condense", "gemm_schur", "constraints", "gj_interface",
+  "extract_operators", "coarse_assemble", "coarse_gj_small", "coarse_gj_diag", "coarse_gj_prep", "coarse_gj_gemm",
+  "coarse_gj_rows", "apply_A_interior", "apply_C_interface", "apply_E_coarse", "apply_F_coarse_ext",
+  "apply_H_average", "spmv_bsr", "krylov_dots", "krylov_update", "krylov_small", "krylov_vectors"};
+
+struct Profiler {
+  uint32_t mask = 0;
+  struct Pending { int fam; hipEvent_t a, b; };
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> pool;
+  int64_t launches[F_COUNT] = {};
+  double ms[F_COUNT] = {}, bytes[F_COUNT] = {}, flops[F_COUNT] = {};
+  hipEvent_t get() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    (void)hipEventCreate(&e);
+    return e;
+  }
+};
+
 }  // namespace
 
 struct mbddc_ctx {
@@ -80,7 +112,9 @@ struct mbddc_ctx {
   std::vector<GjDesc> gj_kii, gj_p, gj_coarse_small;
   std::vector<int32_t> coarse_large;                 // instances inverted by the blocked path
   std::vector<GemmDesc> gemm_desc;
-  std::vector<GemmItem> gemm_items_gh, gemm_items_s;
+  std::vector<GemmItem> gemm_items_gh, gemm_items_s, gemm_items_g, gemm_items_ssym;
+  std::vector<GjDesc> gj_x;                          // (S + rho C^T C) blocks of the symmetric path
+  bool sym = false;                                  // symmetric (SPD) factor path
   std::vector<ApplyItem> itA, itC, itE, itF, itH;
   std::vector<int64_t> inst_coarse_off, inst_kc_off;
   std::vector<int32_t> inst_nc, inst_kc_ld, inst_nchunk, coarse_inst, cslot_sub;
@@ -108,7 +142,9 @@ struct mbddc_ctx {
   int32_t* d_dof_inst = nullptr;
   GjDesc *d_gj_kii = nullptr, *d_gj_p = nullptr, *d_gj_cs = nullptr;
   GemmDesc* d_gemm_desc = nullptr;
-  GemmItem *d_gemm_gh = nullptr, *d_gemm_s = nullptr;
+  GemmItem *d_gemm_gh = nullptr, *d_gemm_s = nullptr, *d_gemm_g = nullptr, *d_gemm_ssym = nullptr;
+  GjDesc* d_gj_x = nullptr;
+  double* d_rho = nullptr;
   ApplyItem *d_itA = nullptr, *d_itC = nullptr, *d_itE = nullptr, *d_itF = nullptr, *d_itH = nullptr;
   int32_t *d_chunk_inst = nullptr, *d_inst_chunk_off = nullptr;
   int64_t* d_chunk_begin = nullptr;
@@ -144,6 +180,11 @@ struct mbddc_ctx {
   uint8_t *d_active = nullptr, *d_mode = nullptr, *d_fin = nullptr;
   double* h_est = nullptr;       // pinned host
   double* h_norm = nullptr;      // pinned host
+  Profiler prof;
+  // algorithmic bytes / flops per launch, filled by build_layout
+  double op_bytes[F_COUNT] = {};
+  double vec_words[F_COUNT] = {};   // FP64 vector words per right-hand side
+  double fam_flops[F_COUNT] = {};
 };
 
 namespace {
@@ -179,6 +220,13 @@ void dfree(mbddc_ctx* c, T*& p) {
 }
 
 void free_all(mbddc_ctx* c) {
+  for (auto& e : c->prof.pending) {
+    c->prof.pool.push_back(e.a);
+    c->prof.pool.push_back(e.b);
+  }
+  c->prof.pending.clear();
+  for (hipEvent_t e : c->prof.pool) (void)hipEventDestroy(e);
+  c->prof.pool.clear();
   for (auto& a : c->allocs) (void)hipFree(a.p);
   c->allocs.clear();
   c->bytes = 0;
@@ -201,6 +249,29 @@ int upload(mbddc_ctx* c, T** p, const std::vector<T>& v) {
     if (s_ != MBDDC_OK) return s_; \
   } while (0)
 
+// Brackets one launch (or launch group) of family f with events on the handle's stream.
+struct ProfScope {
+  mbddc_ctx* c;
+  int f;
+  hipEvent_t a = nullptr;
+  double bytes, flops;
+  ProfScope(mbddc_ctx* c_, int f_, double bytes_, double flops_) : c(c_), f(f_), bytes(bytes_), flops(flops_) {
+    if (c->prof.mask & (1u << f)) {
+      a = c->prof.get();
+      (void)hipEventRecord(a, c->stream);
+    }
+  }
+  ~ProfScope() {
+    if (!a) return;
+    hipEvent_t b = c->prof.get();
+    (void)hipEventRecord(b, c->stream);
+    c->prof.pending.push_back({f, a, b});
+    c->prof.launches[f]++;
+    c->prof.bytes[f] += bytes;
+    c->prof.flops[f] += flops;
+  }
+};
+
 int apply_R(int nrhs) {
   if (nrhs <= 1) return 1;
   if (nrhs <= 2) return 2;
@@ -222,9 +293,12 @@ int build_layout(mbddc_ctx* c) {
   c->gemm_desc.clear();
   c->gemm_items_gh.clear();
   c->gemm_items_s.clear();
+  c->gemm_items_g.clear();
+  c->gemm_items_ssym.clear();
+  c->gj_x.clear();
   c->itA.clear(); c->itC.clear(); c->itE.clear(); c->itF.clear(); c->itH.clear();
   c->max_cols = 1;
-  std::vector<GemmDesc> dS;
+  std::vector<GemmDesc> dS, dSs;
   for (int64_t s = 0; s < P.n_sub; ++s) {
     const SubLayout& L = P.subs[s];
     SubDev& d = c->subs[s];
@@ -233,6 +307,7 @@ int build_layout(mbddc_ctx* c) {
     d.dof_off = L.dof_off; d.if_off = L.if_off; d.c_off = L.c_off; d.elem_off = L.elem_off; d.cons_off = L.cons_off;
     const int64_t ni = L.ni(), nI = L.nI, nG = L.nG, nc = L.nc, m = L.mP();
     if (std::max<int64_t>(nI, m) > kGjMax) return MBDDC_ERR_UNSUPPORTED;
+    if (c->sym && nc > kMaxLocalConstraints) return MBDDC_ERR_UNSUPPORTED;
     d.oK = w; w += round_up(ni * ni, 64);
     d.oG = w; w += round_up(nG * nI, 64);
     d.oH = w; w += round_up(nI * nG, 64);
@@ -250,6 +325,7 @@ int build_layout(mbddc_ctx* c) {
     c->max_cols = std::max<int>(c->max_cols, (int)std::max(std::max(nI, nG), nc));
     c->gj_kii.push_back({d.oK, (int32_t)nI, (int32_t)ni, d.oPiv, (int32_t)s, 0});
     c->gj_p.push_back({d.oP, (int32_t)m, (int32_t)m, d.oPiv + nI, (int32_t)s, 0});
+    c->gj_x.push_back({d.oP, (int32_t)nG, (int32_t)nG, 0, (int32_t)s, 0});
     // G = K_GI K_II^-1, H = K_II^-1 K_IG, S = K_GG - G K_IG
     GemmDesc g{};
     g.M = (int32_t)nG; g.N = (int32_t)nI; g.K = (int32_t)nI; g.lda = (int32_t)ni; g.ldb = (int32_t)ni; g.ldc = (int32_t)nI;
@@ -267,10 +343,16 @@ int build_layout(mbddc_ctx* c) {
       int32_t id = (int32_t)c->gemm_desc.size();
       c->gemm_desc.push_back(*gd);
       for (int32_t a = 0; a < tm; ++a)
-        for (int32_t b = 0; b < tn; ++b) c->gemm_items_gh.push_back({id, a, b, 0});
+        for (int32_t b = 0; b < tn; ++b) {
+          c->gemm_items_gh.push_back({id, a, b, 0});
+          if (gd == &g) c->gemm_items_g.push_back({id, a, b, 0});
+        }
     }
     sS.tiles_n = (int32_t)((sS.N + 63) / 64);
     dS.push_back(sS);
+    GemmDesc sX = sS;               // symmetric path: S written into the X block (ld nG)
+    sX.ldc = (int32_t)nG;
+    dSs.push_back(sX);
     // apply work items
     auto add = [](std::vector<ApplyItem>& v, int64_t sub, int64_t rows) {
       int64_t nb = std::max<int64_t>(1, (rows + 255) / 256);
@@ -287,6 +369,13 @@ int build_layout(mbddc_ctx* c) {
     int32_t tm = (sS.M + 63) / 64, tn = sS.tiles_n;
     for (int32_t a = 0; a < tm; ++a)
       for (int32_t b = 0; b < tn; ++b) c->gemm_items_s.push_back({id, a, b, 0});
+  }
+  for (GemmDesc& sX : dSs) {
+    int32_t id = (int32_t)c->gemm_desc.size();
+    c->gemm_desc.push_back(sX);
+    int32_t tm = (sX.M + 63) / 64, tn = sX.tiles_n;
+    for (int32_t a = 0; a < tm; ++a)
+      for (int32_t b = 0; b < tn; ++b) c->gemm_items_ssym.push_back({id, a, b, 0});
   }
   c->w_elems = w;
   c->op_elems = op;
@@ -348,6 +437,39 @@ int build_layout(mbddc_ctx* c) {
   c->inst_chunk_off[P.n_inst] = (int32_t)c->chunk_inst.size();
   c->chunk_begin.push_back(P.n_dofs);
   c->nblocks = (int64_t)P.bsr_col.size();
+  // algorithmic bytes (operators once) and flops of each launch family
+  for (int f = 0; f < F_COUNT; ++f) c->op_bytes[f] = c->vec_words[f] = c->fam_flops[f] = 0.0;
+  const double eo = (double)elem_size(c->mixed), ef = (double)elem_size(c->fact32);
+  for (const SubDev& d : c->subs) {
+    const double nI = d.nI, nG = d.nG, nc = d.nc, m = d.nG + d.nc;
+    c->op_bytes[F_APPLY_A] += eo * d.ld1 * nI;
+    c->op_bytes[F_APPLY_C] += eo * d.ld2 * nG;
+    c->op_bytes[F_APPLY_F] += eo * d.ld3 * nc;
+    c->op_bytes[F_APPLY_H] += eo * d.ld4 * nG;
+    c->fam_flops[F_APPLY_A] += (nI + nG) * nI;
+    c->fam_flops[F_APPLY_C] += (nG + nc) * nG;
+    c->fam_flops[F_APPLY_F] += nG * nc;
+    c->fam_flops[F_APPLY_H] += nI * nG;
+    c->vec_words[F_APPLY_A] += 2 * nI + nG;
+    c->vec_words[F_APPLY_C] += 2 * nG + nG + nc;
+    c->vec_words[F_APPLY_F] += nc + 2 * nG;
+    c->vec_words[F_APPLY_H] += nG + 2 * nI;
+    c->fam_flops[F_GJ_KII] += 2.0 * nI * nI * nI;
+    c->fam_flops[F_GJ_P] += 2.0 * m * m * m;
+    c->fam_flops[F_GEMM_GH] += 4.0 * nG * nI * nI;
+    c->fam_flops[F_GEMM_S] += 2.0 * nG * nG * nI;
+    c->op_bytes[F_ASSEMBLE_LOCAL] += ef * (nI + nG) * (nI + nG);
+  }
+  for (int32_t ii = 0; ii < P.n_inst; ++ii) {
+    const double nc = c->inst_nc[ii];
+    c->op_bytes[F_APPLY_E] += 8.0 * c->inst_kc_ld[ii] * nc;
+    c->fam_flops[F_APPLY_E] += nc * nc;
+    c->vec_words[F_APPLY_E] += nc * (1 + c->inst_nchunk[ii]);
+    if (nc > 0 && nc <= kGjMax) c->fam_flops[F_COARSE_GJ_SMALL] += 2.0 * nc * nc * nc;
+  }
+  c->op_bytes[F_ASSEMBLE_LOCAL] += 8.0 * P.ke_total;
+  c->op_bytes[F_ASSEMBLE_BSR] = 8.0 * P.ke_total + 72.0 * c->nblocks;
+  c->op_bytes[F_SPMV] = 76.0 * c->nblocks + 4.0 * (P.n_nodes + 1);
   return MBDDC_OK;
 }
 
@@ -398,6 +520,10 @@ int upload_plan(mbddc_ctx* c) {
   CHK(upload(c, &c->d_gemm_desc, c->gemm_desc));
   CHK(upload(c, &c->d_gemm_gh, c->gemm_items_gh));
   CHK(upload(c, &c->d_gemm_s, c->gemm_items_s));
+  CHK(upload(c, &c->d_gemm_g, c->gemm_items_g));
+  CHK(upload(c, &c->d_gemm_ssym, c->gemm_items_ssym));
+  CHK(upload(c, &c->d_gj_x, c->gj_x));
+  CHK(dalloc(c, &c->d_rho, std::max<int64_t>(P.n_sub, 1)));
   CHK(upload(c, &c->d_itA, c->itA));
   CHK(upload(c, &c->d_itC, c->itC));
   CHK(upload(c, &c->d_itE, c->itE));
@@ -477,6 +603,18 @@ int run_gj(mbddc_ctx* c, T* base, const GjDesc* d_desc, int64_t count, int maxn,
   return MBDDC_OK;
 }
 
+template <typename T>
+int run_sym(mbddc_ctx* c, T* base, const GjDesc* d_desc, int64_t count, int maxn, int32_t* d_stat) {
+  if (count == 0) return MBDDC_OK;
+  constexpr int BP = sizeof(T) == 4 ? 32 : 16;
+  size_t lds = std::max<size_t>((size_t)2 * maxn * (BP + 1) * sizeof(T), 16);
+  CHK(set_lds(k_sym_inv_batched<T, BP>, lds));
+  hipLaunchKernelGGL((k_sym_inv_batched<T, BP>), dim3((unsigned)count), dim3(kBlock), lds, c->stream, base, d_desc,
+                     d_stat);
+  HIPCHK(hipGetLastError());
+  return MBDDC_OK;
+}
+
 int check_status(mbddc_ctx* c, int64_t count, const std::vector<GjDesc>& descs, int* bad) {
   std::vector<int32_t> st(count);
   if (count == 0) return MBDDC_OK;
@@ -522,17 +660,30 @@ int coarse_invert_large(mbddc_ctx* c, int32_t ii) {
   CHK(upload(c, &d_gd, std::vector<GemmDesc>{gd}));
   CHK(upload(c, &d_items, items));
   const unsigned ncb = nblk(n, 64);
+  const double gemm_flops = 2.0 * n * (double)n * kCoarseBlock;
   for (int k0 = 0; k0 < n; k0 += kCoarseBlock) {
-    hipLaunchKernelGGL(k_cgj_diag, dim3(1), dim3(kBlock), 0, c->stream, A, n, ld, k0, c->d_cDinv, c->d_piv_c,
-                       c->d_status, thresh);
-    hipLaunchKernelGGL(k_cgj_prep, dim3(ncb), dim3(kBlock), 0, c->stream, A, n, ld, k0, c->d_cDinv, c->d_piv_c,
-                       c->d_cY, c->d_cCcol);
-    hipLaunchKernelGGL(k_cgj_clear_panel, dim3(std::min<unsigned>(1024, nblk((int64_t)n * kCoarseBlock))), dim3(kBlock),
-                       0, c->stream, A, n, ld, k0);
-    hipLaunchKernelGGL((k_gemm_batched<double>), dim3((unsigned)items.size()), dim3(kBlock), 0, c->stream, d_gd,
-                       d_items, c->d_cCcol, c->d_cY, A, A);
-    hipLaunchKernelGGL(k_cgj_rows, dim3(std::min<unsigned>(1024, nblk((int64_t)n * kCoarseBlock))), dim3(kBlock), 0,
-                       c->stream, A, n, ld, k0, c->d_cY);
+    {
+      ProfScope ps(c, F_COARSE_DIAG, 0.0, 2.0 * kCoarseBlock * kCoarseBlock * (double)kCoarseBlock);
+      hipLaunchKernelGGL(k_cgj_diag, dim3(1), dim3(kBlock), 0, c->stream, A, n, ld, k0, c->d_cDinv, c->d_piv_c,
+                         c->d_status, thresh);
+    }
+    {
+      ProfScope ps(c, F_COARSE_PREP, 0.0, 2.0 * kCoarseBlock * kCoarseBlock * (double)n);
+      hipLaunchKernelGGL(k_cgj_prep, dim3(ncb), dim3(kBlock), 0, c->stream, A, n, ld, k0, c->d_cDinv, c->d_piv_c,
+                         c->d_cY, c->d_cCcol);
+      hipLaunchKernelGGL(k_cgj_clear_panel, dim3(std::min<unsigned>(1024, nblk((int64_t)n * kCoarseBlock))),
+                         dim3(kBlock), 0, c->stream, A, n, ld, k0);
+    }
+    {
+      ProfScope ps(c, F_COARSE_GEMM, 16.0 * n * (double)n, gemm_flops);
+      hipLaunchKernelGGL((k_gemm_batched<double>), dim3((unsigned)items.size()), dim3(kBlock), 0, c->stream, d_gd,
+                         d_items, c->d_cCcol, c->d_cY, A, A);
+    }
+    {
+      ProfScope ps(c, F_COARSE_ROWS, 0.0, 0.0);
+      hipLaunchKernelGGL(k_cgj_rows, dim3(std::min<unsigned>(1024, nblk((int64_t)n * kCoarseBlock))), dim3(kBlock), 0,
+                         c->stream, A, n, ld, k0, c->d_cY);
+    }
   }
   hipLaunchKernelGGL(k_cgj_unswap, dim3(ncb, (unsigned)((n + kCoarseBlock - 1) / kCoarseBlock)), dim3(kBlock), 0,
                      c->stream, A, n, ld, c->d_piv_c);
@@ -555,49 +706,116 @@ int factor_impl(mbddc_ctx* c) {
   T* W = reinterpret_cast<T*>(c->d_W);
   To* Op = reinterpret_cast<To*>(c->d_Op);
   const unsigned nsub = (unsigned)P.n_sub;
-  hipLaunchKernelGGL((k_assemble_local<T>), dim3(nsub), dim3(kBlock), 0, c->stream, c->d_Ke, c->d_subs,
-                     c->d_sub_elems, c->d_ke_off, c->d_elem_npe, c->d_elem_ldof, c->d_elem_ldof_off, W);
+  {
+    ProfScope ps(c, F_ASSEMBLE_LOCAL, c->op_bytes[F_ASSEMBLE_LOCAL], 0.0);
+    hipLaunchKernelGGL((k_assemble_local<T>), dim3(nsub), dim3(kBlock), 0, c->stream, c->d_Ke, c->d_subs,
+                       c->d_sub_elems, c->d_ke_off, c->d_elem_npe, c->d_elem_ldof, c->d_elem_ldof_off, W);
+  }
   HIPCHK(hipGetLastError());
-  int maxI = 1, maxP = 1;
+  int maxI = 1, maxP = 1, maxG = 1;
   for (const SubDev& d : c->subs) {
     maxI = std::max(maxI, d.nI);
     maxP = std::max(maxP, d.nG + d.nc);
+    maxG = std::max(maxG, d.nG);
   }
-  CHK(run_gj<T>(c, W, c->d_gj_kii, (int64_t)c->gj_kii.size(), maxI, c->d_status, c->d_piv));
-  int bad = 0;
-  int st = check_status(c, (int64_t)c->gj_kii.size(), c->gj_kii, &bad);
+  int bad = 0, st = 0;
+  // K_II^-1 (interior / Dirichlet problems, §3.2 block factorisation)
+  {
+    ProfScope ps(c, F_GJ_KII, 0.0, c->fam_flops[F_GJ_KII]);
+    if (c->sym) CHK(run_sym<T>(c, W, c->d_gj_kii, (int64_t)c->gj_kii.size(), maxI, c->d_status));
+    else CHK(run_gj<T>(c, W, c->d_gj_kii, (int64_t)c->gj_kii.size(), maxI, c->d_status, c->d_piv));
+  }
+  st = check_status(c, (int64_t)c->gj_kii.size(), c->gj_kii, &bad);
   if (st) {
     c->last_bad = bad;
     return st;
   }
-  if (!c->gemm_items_gh.empty())
-    hipLaunchKernelGGL((k_gemm_batched<T>), dim3((unsigned)c->gemm_items_gh.size()), dim3(kBlock), 0, c->stream,
-                       c->d_gemm_desc, c->d_gemm_gh, W, W, W, W);
-  if (!c->gemm_items_s.empty())
-    hipLaunchKernelGGL((k_gemm_batched<T>), dim3((unsigned)c->gemm_items_s.size()), dim3(kBlock), 0, c->stream,
-                       c->d_gemm_desc, c->d_gemm_s, W, W, W, W);
-  hipLaunchKernelGGL((k_build_constraints<T>), dim3(nsub), dim3(kBlock), 0, c->stream, c->d_subs, c->d_cons_ptr,
-                     c->d_cons_idx, c->d_cons_w, W);
+  // G = K_GI K_II^-1 (and H = K_II^-1 K_IG on the general path), S = K_GG - G K_IG
+  const std::vector<GemmItem>& igh = c->sym ? c->gemm_items_g : c->gemm_items_gh;
+  const std::vector<GemmItem>& is = c->sym ? c->gemm_items_ssym : c->gemm_items_s;
+  if (!igh.empty()) {
+    ProfScope ps(c, F_GEMM_GH, 0.0, c->fam_flops[F_GEMM_GH] * (c->sym ? 0.5 : 1.0));
+    hipLaunchKernelGGL((k_gemm_batched<T>), dim3((unsigned)igh.size()), dim3(kBlock), 0, c->stream, c->d_gemm_desc,
+                       c->sym ? c->d_gemm_g : c->d_gemm_gh, W, W, W, W);
+  }
+  if (!is.empty()) {
+    ProfScope ps(c, F_GEMM_S, 0.0, c->fam_flops[F_GEMM_S]);
+    hipLaunchKernelGGL((k_gemm_batched<T>), dim3((unsigned)is.size()), dim3(kBlock), 0, c->stream, c->d_gemm_desc,
+                       c->sym ? c->d_gemm_ssym : c->d_gemm_s, W, W, W, W);
+  }
   HIPCHK(hipGetLastError());
-  CHK(run_gj<T>(c, W, c->d_gj_p, (int64_t)c->gj_p.size(), maxP, c->d_status, c->d_piv));
-  st = check_status(c, (int64_t)c->gj_p.size(), c->gj_p, &bad);
-  if (st) {
-    c->last_bad = bad;
-    return st;
+  if (c->sym) {
+    // [S C^T; C 0]^-1 through X = (S + rho C^T C)^-1 and the constraint Schur complement
+    {
+      ProfScope ps(c, F_CONSTRAINTS, 0.0, 0.0);
+      hipLaunchKernelGGL((k_add_ctc<T>), dim3(nsub), dim3(kBlock), 0, c->stream, c->d_subs, c->d_cons_ptr,
+                         c->d_cons_idx, c->d_cons_w, W, c->d_rho);
+    }
+    {
+      ProfScope ps(c, F_GJ_P, 0.0, c->fam_flops[F_GJ_P]);
+      CHK(run_sym<T>(c, W, c->d_gj_x, (int64_t)c->gj_x.size(), maxG, c->d_status));
+    }
+    st = check_status(c, (int64_t)c->gj_x.size(), c->gj_x, &bad);
+    if (st) {
+      c->last_bad = bad;
+      return st;
+    }
+    {
+      ProfScope ps(c, F_EXTRACT, 0.0, 0.0);
+      hipLaunchKernelGGL((k_constrained_blocks<T>), dim3(nsub), dim3(kBlock), 0, c->stream, c->d_subs,
+                         c->d_cons_ptr, c->d_cons_idx, c->d_cons_w, c->d_rho, W, c->d_Kcl, c->d_status);
+      hipLaunchKernelGGL((k_extract_sym<T, To>), dim3(nsub), dim3(kBlock), 0, c->stream, c->d_subs, c->d_slot_w, W,
+                         Op);
+    }
+    HIPCHK(hipGetLastError());
+    st = check_status(c, (int64_t)c->gj_x.size(), c->gj_x, &bad);
+    if (st) {
+      c->last_bad = bad;
+      return st;
+    }
+  } else {
+    {
+      ProfScope ps(c, F_CONSTRAINTS, 0.0, 0.0);
+      hipLaunchKernelGGL((k_build_constraints<T>), dim3(nsub), dim3(kBlock), 0, c->stream, c->d_subs, c->d_cons_ptr,
+                         c->d_cons_idx, c->d_cons_w, W);
+    }
+    HIPCHK(hipGetLastError());
+    {
+      ProfScope ps(c, F_GJ_P, 0.0, c->fam_flops[F_GJ_P]);
+      CHK(run_gj<T>(c, W, c->d_gj_p, (int64_t)c->gj_p.size(), maxP, c->d_status, c->d_piv));
+    }
+    st = check_status(c, (int64_t)c->gj_p.size(), c->gj_p, &bad);
+    if (st) {
+      c->last_bad = bad;
+      return st;
+    }
+    {
+      ProfScope ps(c, F_EXTRACT, 0.0, 0.0);
+      hipLaunchKernelGGL((k_extract<T, To>), dim3(nsub), dim3(kBlock), 0, c->stream, c->d_subs, c->d_slot_w, W, Op,
+                         c->d_Kcl);
+    }
   }
-  hipLaunchKernelGGL((k_extract<T, To>), dim3(nsub), dim3(kBlock), 0, c->stream, c->d_subs, c->d_slot_w, W, Op, c->d_Kcl);
   if (P.n_coarse > 0) {
-    hipLaunchKernelGGL(k_coarse_assemble, dim3((unsigned)P.n_coarse), dim3(kBlock), 0, c->stream, c->d_subs,
-                       c->d_coarse_ptr, c->d_coarse_slots, c->d_cslot_sub, c->d_cslot_coarse, c->d_inst_coarse_off,
-                       c->d_inst_nc, c->d_inst_kc_off, c->d_inst_kc_ld, c->d_coarse_inst, c->d_Kcl, c->d_Kc);
+    {
+      ProfScope ps(c, F_COARSE_ASSEMBLE, 0.0, 0.0);
+      hipLaunchKernelGGL(k_coarse_assemble, dim3((unsigned)P.n_coarse), dim3(kBlock), 0, c->stream, c->d_subs,
+                         c->d_coarse_ptr, c->d_coarse_slots, c->d_cslot_sub, c->d_cslot_coarse, c->d_inst_coarse_off,
+                         c->d_inst_nc, c->d_inst_kc_off, c->d_inst_kc_ld, c->d_coarse_inst, c->d_Kcl, c->d_Kc);
+    }
     HIPCHK(hipGetLastError());
     if (c->d_Kc_keep)
       HIPCHK(hipMemcpyAsync(c->d_Kc_keep, c->d_Kc, c->kc_elems * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
     if (!c->gj_coarse_small.empty()) {
       int maxc = 1;
       for (auto& g : c->gj_coarse_small) maxc = std::max(maxc, g.n);
-      CHK(run_gj<double>(c, c->d_Kc, c->d_gj_cs, (int64_t)c->gj_coarse_small.size(), maxc, c->d_status, c->d_piv_c));
-      // pivots of several small coarse problems: they share d_piv_c only when one exists
+      {
+        ProfScope ps(c, F_COARSE_GJ_SMALL, 0.0, c->fam_flops[F_COARSE_GJ_SMALL]);
+        if (c->sym)
+          CHK(run_sym<double>(c, c->d_Kc, c->d_gj_cs, (int64_t)c->gj_coarse_small.size(), maxc, c->d_status));
+        else
+          CHK(run_gj<double>(c, c->d_Kc, c->d_gj_cs, (int64_t)c->gj_coarse_small.size(), maxc, c->d_status,
+                             c->d_piv_c));
+      }
       st = check_status(c, (int64_t)c->gj_coarse_small.size(), c->gj_coarse_small, &bad);
       if (st) {
         c->last_bad = -1;
@@ -635,19 +853,33 @@ int apply_impl(mbddc_ctx* c, const double* r, double* z) {
     attr_set = true;
   }
   if (lds_local > 160 * 1024) return MBDDC_ERR_UNSUPPORTED;
-  a.items = c->d_itA;
-  hipLaunchKernelGGL((k_apply_local<To, R, 0>), dim3((unsigned)c->itA.size()), dim3(kBlock), lds_local, c->stream, a);
-  a.items = c->d_itC;
-  hipLaunchKernelGGL((k_apply_local<To, R, 1>), dim3((unsigned)c->itC.size()), dim3(kBlock), lds_local, c->stream, a);
+  {
+    ProfScope ps(c, F_APPLY_A, c->op_bytes[F_APPLY_A] + 8.0 * R * c->vec_words[F_APPLY_A], 2.0 * R * c->fam_flops[F_APPLY_A]);
+    a.items = c->d_itA;
+    hipLaunchKernelGGL((k_apply_local<To, R, 0>), dim3((unsigned)c->itA.size()), dim3(kBlock), lds_local, c->stream, a);
+  }
+  {
+    ProfScope ps(c, F_APPLY_C, c->op_bytes[F_APPLY_C] + 8.0 * R * c->vec_words[F_APPLY_C], 2.0 * R * c->fam_flops[F_APPLY_C]);
+    a.items = c->d_itC;
+    hipLaunchKernelGGL((k_apply_local<To, R, 1>), dim3((unsigned)c->itC.size()), dim3(kBlock), lds_local, c->stream, a);
+  }
   if (!c->itE.empty()) {
     const size_t lds_c = (size_t)(4 * 256 * R + kCoarseChunk * R) * sizeof(double);
+    ProfScope ps(c, F_APPLY_E, c->op_bytes[F_APPLY_E] + 8.0 * R * c->vec_words[F_APPLY_E],
+                 2.0 * R * c->fam_flops[F_APPLY_E]);
     a.items = c->d_itE;
     hipLaunchKernelGGL((k_apply_coarse<To, R>), dim3((unsigned)c->itE.size()), dim3(kBlock), lds_c, c->stream, a);
   }
-  a.items = c->d_itF;
-  hipLaunchKernelGGL((k_apply_local<To, R, 3>), dim3((unsigned)c->itF.size()), dim3(kBlock), lds_local, c->stream, a);
-  a.items = c->d_itH;
-  hipLaunchKernelGGL((k_apply_local<To, R, 4>), dim3((unsigned)c->itH.size()), dim3(kBlock), lds_local, c->stream, a);
+  {
+    ProfScope ps(c, F_APPLY_F, c->op_bytes[F_APPLY_F] + 8.0 * R * c->vec_words[F_APPLY_F], 2.0 * R * c->fam_flops[F_APPLY_F]);
+    a.items = c->d_itF;
+    hipLaunchKernelGGL((k_apply_local<To, R, 3>), dim3((unsigned)c->itF.size()), dim3(kBlock), lds_local, c->stream, a);
+  }
+  {
+    ProfScope ps(c, F_APPLY_H, c->op_bytes[F_APPLY_H] + 8.0 * R * c->vec_words[F_APPLY_H], 2.0 * R * c->fam_flops[F_APPLY_H]);
+    a.items = c->d_itH;
+    hipLaunchKernelGGL((k_apply_local<To, R, 4>), dim3((unsigned)c->itH.size()), dim3(kBlock), lds_local, c->stream, a);
+  }
   HIPCHK(hipGetLastError());
   return MBDDC_OK;
 }
@@ -672,6 +904,7 @@ int apply_dispatch(mbddc_ctx* c, int R, const double* r, double* z) {
 int spmv_dispatch(mbddc_ctx* c, int R, const double* x, double* y) {
   const int64_t nd = c->plan.n_dofs;
   const unsigned g = nblk(nd * 16);
+  ProfScope ps(c, F_SPMV, c->op_bytes[F_SPMV] + 16.0 * R * nd, 18.0 * R * c->nblocks);
   switch (R) {
     case 1: hipLaunchKernelGGL(k_spmv<1>, dim3(g), dim3(kBlock), 0, c->stream, c->d_bsr_rowptr, c->d_bsr_col, c->d_vals, nd, x, y); break;
     case 2: hipLaunchKernelGGL(k_spmv<2>, dim3(g), dim3(kBlock), 0, c->stream, c->d_bsr_rowptr, c->d_bsr_col, c->d_vals, nd, x, y); break;
@@ -774,7 +1007,7 @@ int gmres_impl(mbddc_ctx* c, int nrhs, mbddc_info* info) {
   auto h2d = [&](void* d, const void* h, size_t b) { return hipMemcpyAsync(d, h, b, hipMemcpyHostToDevice, c->stream); };
   // ||b||
   hipLaunchKernelGGL((k_residual<R>), dim3(nch), dim3(kBlock), 0, c->stream, ka, c->d_B, nullptr, nullptr, c->d_npart);
-  hipLaunchKernelGGL(k_norms, dim3(gs), dim3(64), 0, c->stream, ka, nsys, c->d_npart, c->h_norm);
+  hipLaunchKernelGGL(k_norms, dim3(nsys), dim3(64), 0, c->stream, ka, nsys, c->d_npart, c->h_norm);
   HIPCHK(hipMemsetAsync(c->d_x, 0, n * R * sizeof(double), c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
   for (int s = 0; s < nsys; ++s) {
@@ -806,27 +1039,56 @@ int gmres_impl(mbddc_ctx* c, int nrhs, mbddc_info* info) {
     int jtop = 0;
     for (int s = 0; s < nsys; ++s)
       if (active[s]) jtop = std::max(jtop, j[s]);
-    hipLaunchKernelGGL((k_next_vector<R>), dim3(gv), dim3(kBlock), 0, c->stream, ka, c->d_V, c->d_Wv, c->d_jsys,
-                       c->d_mode, c->d_hnorm, c->d_dof_inst, c->d_X);
+    const double vbytes = 8.0 * n * R;                 // one block vector
+    {
+      ProfScope ps(c, F_KRYLOV_VEC, 2.0 * vbytes, 0.0);
+      hipLaunchKernelGGL((k_next_vector<R>), dim3(gv), dim3(kBlock), 0, c->stream, ka, c->d_V, c->d_Wv, c->d_jsys,
+                         c->d_mode, c->d_hnorm, c->d_dof_inst, c->d_X);
+    }
     CHK(apply_dispatch(c, R, c->d_X, c->d_Y));
-    hipLaunchKernelGGL((k_store_z<R>), dim3(gv), dim3(kBlock), 0, c->stream, ka, c->d_Y, c->d_Z, c->d_jsys,
-                       c->d_active, c->d_dof_inst);
+    {
+      ProfScope ps(c, F_KRYLOV_VEC, 2.0 * vbytes, 0.0);
+      hipLaunchKernelGGL((k_store_z<R>), dim3(gv), dim3(kBlock), 0, c->stream, ka, c->d_Y, c->d_Z, c->d_jsys,
+                         c->d_active, c->d_dof_inst);
+    }
     CHK(spmv_dispatch(c, R, c->d_Y, c->d_Wv));
     // CGS2
-    hipLaunchKernelGGL((k_dots<R>), dim3(nch), dim3(kBlock), 0, c->stream, ka, c->d_V, c->d_Wv, c->d_jsys, c->d_active,
-                       jtop, c->d_part);
-    hipLaunchKernelGGL(k_reduce_dots, dim3(nblk((int64_t)nsys * (jtop + 1))), dim3(kBlock), 0, c->stream, ka, c->d_part,
-                       nsys, jtop, c->d_h1);
-    hipLaunchKernelGGL((k_update<R>), dim3(nch), dim3(kBlock), 0, c->stream, ka, c->d_V, c->d_Wv, c->d_h1, c->d_jsys,
-                       c->d_active, c->d_dof_inst, jtop, (double*)nullptr);
-    hipLaunchKernelGGL((k_dots<R>), dim3(nch), dim3(kBlock), 0, c->stream, ka, c->d_V, c->d_Wv, c->d_jsys, c->d_active,
-                       jtop, c->d_part2);
-    hipLaunchKernelGGL(k_reduce_dots, dim3(nblk((int64_t)nsys * (jtop + 1))), dim3(kBlock), 0, c->stream, ka,
-                       c->d_part2, nsys, jtop, c->d_h2);
-    hipLaunchKernelGGL((k_update<R>), dim3(nch), dim3(kBlock), 0, c->stream, ka, c->d_V, c->d_Wv, c->d_h2, c->d_jsys,
-                       c->d_active, c->d_dof_inst, jtop, c->d_npart);
-    hipLaunchKernelGGL(k_givens, dim3(gs), dim3(64), 0, c->stream, ka, nsys, c->d_h1, c->d_h2, c->d_npart, c->d_jsys,
-                       c->d_active, c->d_Hs, c->d_cs, c->d_sn, c->d_g, c->d_hnorm, c->h_est);
+    const double jb = (jtop + 1) * vbytes, jf = 2.0 * (jtop + 1) * n * R;
+    {
+      ProfScope ps(c, F_KRYLOV_DOTS, jb + vbytes, jf);
+      hipLaunchKernelGGL((k_dots<R>), dim3(nch), dim3(kBlock), 0, c->stream, ka, c->d_V, c->d_Wv, c->d_jsys,
+                         c->d_active, jtop, c->d_part);
+    }
+    {
+      ProfScope ps(c, F_KRYLOV_SMALL, 0.0, 0.0);
+      hipLaunchKernelGGL(k_reduce_dots, dim3(nblk((int64_t)nsys * (jtop + 1), 4)), dim3(kBlock), 0, c->stream, ka,
+                         c->d_part, nsys, jtop, c->d_h1);
+    }
+    {
+      ProfScope ps(c, F_KRYLOV_UPDATE, jb + 2.0 * vbytes, jf);
+      hipLaunchKernelGGL((k_update<R>), dim3(nch), dim3(kBlock), 0, c->stream, ka, c->d_V, c->d_Wv, c->d_h1,
+                         c->d_jsys, c->d_active, c->d_dof_inst, jtop, (double*)nullptr);
+    }
+    {
+      ProfScope ps(c, F_KRYLOV_DOTS, jb + vbytes, jf);
+      hipLaunchKernelGGL((k_dots<R>), dim3(nch), dim3(kBlock), 0, c->stream, ka, c->d_V, c->d_Wv, c->d_jsys,
+                         c->d_active, jtop, c->d_part2);
+    }
+    {
+      ProfScope ps(c, F_KRYLOV_SMALL, 0.0, 0.0);
+      hipLaunchKernelGGL(k_reduce_dots, dim3(nblk((int64_t)nsys * (jtop + 1), 4)), dim3(kBlock), 0, c->stream, ka,
+                         c->d_part2, nsys, jtop, c->d_h2);
+    }
+    {
+      ProfScope ps(c, F_KRYLOV_UPDATE, jb + 2.0 * vbytes, jf);
+      hipLaunchKernelGGL((k_update<R>), dim3(nch), dim3(kBlock), 0, c->stream, ka, c->d_V, c->d_Wv, c->d_h2,
+                         c->d_jsys, c->d_active, c->d_dof_inst, jtop, c->d_npart);
+    }
+    {
+      ProfScope ps(c, F_KRYLOV_SMALL, 0.0, 0.0);
+      hipLaunchKernelGGL(k_givens, dim3(nsys), dim3(64), 0, c->stream, ka, nsys, c->d_h1, c->d_h2, c->d_npart,
+                         c->d_jsys, c->d_active, c->d_Hs, c->d_cs, c->d_sn, c->d_g, c->d_hnorm, c->h_est);
+    }
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(c->stream));
     bool any_fin = false;
@@ -855,7 +1117,7 @@ int gmres_impl(mbddc_ctx* c, int nrhs, mbddc_info* info) {
                        c->d_nk, c->d_dof_inst);
     CHK(spmv_dispatch(c, R, c->d_x, c->d_Y));   // W of continuing systems stays intact
     hipLaunchKernelGGL((k_residual<R>), dim3(nch), dim3(kBlock), 0, c->stream, ka, c->d_B, c->d_Y, c->d_r, c->d_npart);
-    hipLaunchKernelGGL(k_norms, dim3(gs), dim3(64), 0, c->stream, ka, nsys, c->d_npart, c->h_norm);
+    hipLaunchKernelGGL(k_norms, dim3(nsys), dim3(64), 0, c->stream, ka, nsys, c->d_npart, c->h_norm);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(c->stream));
     std::vector<uint8_t> rs(nsys, 0);
@@ -1019,6 +1281,7 @@ int mbddc_setup_symbolic_batch(mbddc_ctx* c, int n_inst, const mbddc_mesh* meshe
   c->opt = o;
   c->mixed = (o.precision != MBDDC_FP64);
   c->fact32 = (o.precision == MBDDC_MIXED_F32FACT);
+  c->sym = (o.symmetric_hint != 0);
   c->state = 0;
   std::string err = build_plan(ms, o.primal, c->plan);
   if (!err.empty()) return MBDDC_ERR_ARG;
@@ -1080,9 +1343,12 @@ int mbddc_set_tangent(mbddc_ctx* c, const double* elem_K, int on_device) {
   }
   HIPCHK(hipMemcpyAsync(c->d_Ke, elem_K, P.ke_total * sizeof(double),
                         on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->stream));
-  hipLaunchKernelGGL(k_assemble_bsr, dim3(nblk(c->nblocks * 9)), dim3(kBlock), 0, c->stream, c->d_Ke, c->d_bsr_rowptr,
-                     c->d_bsr_rownode, c->d_bsr_col, c->d_bsr_cptr, c->d_bsr_contrib, c->d_bsr_kstride, c->d_free,
-                     c->nblocks, c->d_vals);
+  {
+    ProfScope ps(c, F_ASSEMBLE_BSR, c->op_bytes[F_ASSEMBLE_BSR], 0.0);
+    hipLaunchKernelGGL(k_assemble_bsr, dim3(nblk(c->nblocks * 9)), dim3(kBlock), 0, c->stream, c->d_Ke, c->d_bsr_rowptr,
+                       c->d_bsr_rownode, c->d_bsr_col, c->d_bsr_cptr, c->d_bsr_contrib, c->d_bsr_kstride, c->d_free,
+                       c->nblocks, c->d_vals);
+  }
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(c->stream));
   c->state = std::max(c->state, 2);
@@ -1193,6 +1459,46 @@ int mbddc_get_bsr(const mbddc_ctx* c, int32_t* rowptr, int32_t* colidx, double* 
 }
 
 int mbddc_last_bad_subdomain(const mbddc_ctx* c) { return c ? c->last_bad : 0; }
+
+const char* mbddc_profile_family_name(int family) {
+  return (family >= 0 && family < F_COUNT) ? kFamilyName[family] : nullptr;
+}
+
+int mbddc_set_profiling(mbddc_ctx* c, uint32_t family_mask) {
+  if (!c) return MBDDC_ERR_ARG;
+  c->prof.mask = family_mask;
+  return MBDDC_OK;
+}
+
+int mbddc_get_profile(mbddc_ctx* c, mbddc_kernel_stat* out, int max_entries, int* n_entries) {
+  if (!c || (max_entries > 0 && !out)) return MBDDC_ERR_ARG;
+  if (hipSetDevice(c->device) != hipSuccess) return MBDDC_ERR_DEVICE;
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return MBDDC_ERR_DEVICE;
+  Profiler& p = c->prof;
+  for (auto& e : p.pending) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, e.a, e.b) == hipSuccess) p.ms[e.fam] += ms;
+    p.pool.push_back(e.a);
+    p.pool.push_back(e.b);
+  }
+  p.pending.clear();
+  int k = 0;
+  for (int f = 0; f < F_COUNT; ++f) {
+    if (p.launches[f] == 0) continue;
+    if (k < max_entries) {
+      std::snprintf(out[k].name, sizeof(out[k].name), "%s", kFamilyName[f]);
+      out[k].launches = p.launches[f];
+      out[k].ms = p.ms[f];
+      out[k].bytes = p.bytes[f];
+      out[k].flops = p.flops[f];
+    }
+    ++k;
+    p.launches[f] = 0;
+    p.ms[f] = p.bytes[f] = p.flops[f] = 0.0;
+  }
+  if (n_entries) *n_entries = k;
+  return MBDDC_OK;
+}
 
 int mbddc_inspect_symbolic(const mbddc_mesh* m, uint32_t primal, mbddc_sizes* sizes, int32_t* node_glob,
                            int32_t* glob_kind, int32_t* coarse_glob, int32_t* coarse_comp, int32_t* sub_counts) {

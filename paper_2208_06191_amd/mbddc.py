@@ -57,6 +57,11 @@ class mbddc_sizes(ctypes.Structure):
                                                "bsr_blocks")]
 
 
+class mbddc_kernel_stat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_int64), ("ms", ctypes.c_double),
+                ("bytes", ctypes.c_double), ("flops", ctypes.c_double)]
+
+
 _lib = None
 
 # (name, argtypes) for every entry point of include/mbddc.h
@@ -80,6 +85,10 @@ _SIGNATURES = {
     "mbddc_inspect_symbolic": [ctypes.POINTER(mbddc_mesh), ctypes.c_uint32, ctypes.POINTER(mbddc_sizes), _i32p,
                                _i32p, _i32p, _i32p, _i32p],
     "mbddc_last_bad_subdomain": [ctypes.c_void_p],
+    "mbddc_set_profiling": [ctypes.c_void_p, ctypes.c_uint32],
+    "mbddc_profile_family_name": [ctypes.c_int],
+    "mbddc_get_profile": [ctypes.c_void_p, ctypes.POINTER(mbddc_kernel_stat), ctypes.c_int,
+                          ctypes.POINTER(ctypes.c_int)],
     "mbddc_destroy": [ctypes.c_void_p],
     "mbddc_strerror": [ctypes.c_int],
 }
@@ -101,7 +110,7 @@ def lib():
         for name, args in _SIGNATURES.items():
             f = getattr(L, name)
             f.argtypes = args
-            f.restype = ctypes.c_char_p if name == "mbddc_strerror" else ctypes.c_int
+            f.restype = ctypes.c_char_p if name in ("mbddc_strerror", "mbddc_profile_family_name") else ctypes.c_int
         _lib = L
     return _lib
 
@@ -149,6 +158,16 @@ def default_options(**kw) -> mbddc_options:
     for k, v in kw.items():
         setattr(o, k, v)
     return o
+
+
+def profile_families() -> list:
+    """Profiler family names; bit i of a profiling mask selects family i."""
+    out = []
+    while True:
+        n = lib().mbddc_profile_family_name(len(out))
+        if not n:
+            return out
+        out.append(n.decode())
 
 
 def mbddc_inspect_symbolic(mesh: _MeshArrays, primal: int):
@@ -260,6 +279,18 @@ class Solver:
         if st != MBDDC_OK and (raise_on_noconv or st != MBDDC_ERR_NOCONV):
             raise MbddcError(st, "mbddc_solve")
         return res, info
+
+    # -- profiling -----------------------------------------------------------------
+    def mbddc_set_profiling(self, mask: int = 0xFFFFFFFF):
+        _check(lib().mbddc_set_profiling(self._h, mask & 0xFFFFFFFF), "mbddc_set_profiling")
+
+    def mbddc_get_profile(self) -> dict:
+        """{family: {launches, ms, bytes, flops}} since the last call (counters reset)."""
+        buf = (mbddc_kernel_stat * 64)()
+        n = ctypes.c_int()
+        _check(lib().mbddc_get_profile(self._h, buf, 64, ctypes.byref(n)), "mbddc_get_profile")
+        return {buf[i].name.decode(): dict(launches=buf[i].launches, ms=buf[i].ms, bytes=buf[i].bytes,
+                                           flops=buf[i].flops) for i in range(min(n.value, 64))}
 
     # -- inspection ----------------------------------------------------------------
     def mbddc_get_globs(self):

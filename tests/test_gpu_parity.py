@@ -36,9 +36,9 @@ def oracle_of(name, primal):
     return dec, bddc.BDDC(dec, P.mesh.elem_nodes, P.Ke)
 
 
-def solver_for(P, precision, primal, **kw):
+def solver_for(P, precision, primal, sym=0, **kw):
     s = mbddc.Solver(0)
-    o = mbddc.default_options(precision=precision, primal=primal, keep_coarse_matrix=1, **kw)
+    o = mbddc.default_options(precision=precision, primal=primal, keep_coarse_matrix=1, symmetric_hint=sym, **kw)
     s.mbddc_setup_symbolic([mbddc.mesh_from_problem(P)], o)
     s.mbddc_set_tangent(P.Ke)
     s.mbddc_factor()
@@ -76,12 +76,13 @@ def test_assembled_operator(name, primal):
         assert np.abs(y[k][clamped]).max() == 0.0
 
 
+@pytest.mark.parametrize("sym", [0, 1])
 @pytest.mark.parametrize("precision", PRECS)
 @pytest.mark.parametrize("name,primal", CASES)
-def test_coarse_matrix_and_apply(name, primal, precision):
+def test_coarse_matrix_and_apply(name, primal, precision, sym):
     P = problem(name)
     dec, B = oracle_of(name, primal)
-    s = solver_for(P, precision, primal)
+    s = solver_for(P, precision, primal, sym)
     Kc = s.mbddc_get_coarse_matrix(0, dec.n_coarse)
     err_c = rel(Kc, B.Kc)
     rng = np.random.default_rng(7)
@@ -90,18 +91,19 @@ def test_coarse_matrix_and_apply(name, primal, precision):
     z = s.mbddc_apply(r)
     errs = [rel(z[k][dec.free], B.apply(r[k][dec.free])) for k in range(3)]
     clamped = np.setdiff1d(np.arange(P.n_dofs), dec.free)
-    print(f"{name} primal={primal} prec={precision}: coarse {err_c:.2e} apply {max(errs):.2e}")
+    print(f"{name} primal={primal} prec={precision} sym={sym}: coarse {err_c:.2e} apply {max(errs):.2e}")
     assert err_c <= TOL_COARSE[precision]
     assert max(errs) <= TOL_APPLY[precision]
     assert np.abs(z[:, clamped]).max() == 0.0
 
 
+@pytest.mark.parametrize("sym", [0, 1])
 @pytest.mark.parametrize("precision", PRECS)
 @pytest.mark.parametrize("name,primal", CASES)
-def test_solve_matches_oracle(name, primal, precision):
+def test_solve_matches_oracle(name, primal, precision, sym):
     P = problem(name)
     dec, B = oracle_of(name, primal)
-    s = solver_for(P, precision, primal)
+    s = solver_for(P, precision, primal, sym)
     x, info = s.mbddc_solve(P.rhs)
     for k in range(P.rhs.shape[0]):
         b = P.rhs[k][dec.free]
@@ -110,7 +112,7 @@ def test_solve_matches_oracle(name, primal, precision):
         tr = np.linalg.norm(b - B.A @ xr) / np.linalg.norm(b)
         assert tr <= 1e-8
         assert np.abs(x[k][P.dirichlet]).max() == 0.0
-    print(f"{name} primal={primal} prec={precision}: its {info.iterations} (oracle {ref.iterations}) "
+    print(f"{name} primal={primal} prec={precision} sym={sym}: its {info.iterations} (oracle {ref.iterations}) "
           f"res {info.rel_res_true:.2e}")
     # iteration parity per right-hand side
     for k in range(P.rhs.shape[0]):
@@ -176,10 +178,11 @@ def test_one_subdomain_is_one_iteration():
     assert rel(x[free], xd) <= 1e-10
 
 
-def test_floating_subdomains_without_primals_are_singular():
+@pytest.mark.parametrize("sym", [0, 1])
+def test_floating_subdomains_without_primals_are_singular(sym):
     P = problem("small")
     s = mbddc.Solver(0)
-    s.mbddc_setup_symbolic([mbddc.mesh_from_problem(P)], mbddc.default_options(primal=0,
+    s.mbddc_setup_symbolic([mbddc.mesh_from_problem(P)], mbddc.default_options(primal=0, symmetric_hint=sym,
                                                                               precision=mbddc.MBDDC_FP64))
     s.mbddc_set_tangent(P.Ke)
     with pytest.raises(mbddc.MbddcError) as e:
@@ -224,12 +227,13 @@ def test_device_pointers_match_host_path():
 
 
 @pytest.mark.slow
+@pytest.mark.parametrize("sym", [0, 1])
 @pytest.mark.parametrize("precision", PRECS)
-def test_paper_scale_neo_hookean_box(precision):
+def test_paper_scale_neo_hookean_box(precision, sym):
     """512 subdomains, 7140 coarse DOFs (VE): apply parity, iteration parity, residuals."""
     P = nh32()
     dec, B = nh32_oracle()
-    s = solver_for(P, precision, 3)
+    s = solver_for(P, precision, 3, sym)
     rng = np.random.default_rng(3)
     r = rng.standard_normal(P.n_dofs)
     r[P.dirichlet] = 0.0
@@ -237,7 +241,7 @@ def test_paper_scale_neo_hookean_box(precision):
     e = rel(z[dec.free], B.apply(r[dec.free]))
     x, info = s.mbddc_solve(P.rhs)
     ref = nh32_ref()
-    print(f"32^3 prec={precision}: apply err {e:.2e}, its {info.iterations} (oracle {ref.iterations}), "
+    print(f"32^3 prec={precision} sym={sym}: apply err {e:.2e}, its {info.iterations} (oracle {ref.iterations}), "
           f"res {info.rel_res_true:.2e}")
     assert e <= TOL_APPLY[precision]
     assert info.rel_res_true <= 1e-8
@@ -271,19 +275,20 @@ def nh32_ref():
     return gmres.gmres(lambda v: B.A @ v, B.apply, P.rhs[0][dec.free], 1e-8, 30, 1000)
 
 
+@pytest.mark.parametrize("sym", [0, 1])
 @pytest.mark.parametrize("name,primal", [("small", 1), ("small_ve", 3), ("tiny_nh", 3)])
-def test_fp32_factorisation_path_converges(name, primal):
+def test_fp32_factorisation_path_converges(name, primal, sym):
     """FP32 local factorisations: the FP64 outer GMRES still reaches the FP64 residual; the
     iteration overhead of the less accurate local operators is reported."""
     P = problem(name)
     dec, B = oracle_of(name, primal)
-    s = solver_for(P, mbddc.MBDDC_MIXED_F32FACT, primal)
+    s = solver_for(P, mbddc.MBDDC_MIXED_F32FACT, primal, sym)
     r = np.random.default_rng(7).standard_normal(P.n_dofs)
     r[P.dirichlet] = 0.0
     e = rel(s.mbddc_apply(r)[dec.free], B.apply(r[dec.free]))
     b = P.rhs[0]
     ref = gmres.gmres(lambda v: B.A @ v, B.apply, b[dec.free], 1e-8, 30, 1000)
     x, info = s.mbddc_solve(b)
-    print(f"{name}: FP32-factor apply error {e:.2e}, its {info.iterations} (oracle {ref.iterations})")
+    print(f"{name} sym={sym}: FP32-factor apply error {e:.2e}, its {info.iterations} (oracle {ref.iterations})")
     assert info.rel_res_true <= 1e-8
     assert e <= 1e-2
