@@ -84,10 +84,12 @@ typedef struct {
   int32_t restart;               /* GMRES restart length, 1..64 */
   double rtol;                   /* relative residual target on ||b - K x||_2 */
   int32_t max_it;                /* Arnoldi steps summed over restarts */
-  int32_t symmetric_hint;        /* 1: the tangent is symmetric and positive definite on the
-                                    constrained local spaces (hyperelastic tangents): local and coarse
-                                    inverses by pivot-free symmetric sweeps; 0: general path with
-                                    partial pivoting (the paper's symmetry flag, §4 and §6.1) */
+  int32_t symmetric_hint;        /* 1: the tangent is symmetric (hyperelastic tangents): local and
+                                    coarse inverses by pivot-free symmetric sweeps, which need the
+                                    pivots (Schur complements of leading blocks) nonsingular: SPD
+                                    local problems, coarse problems SPD or mildly indefinite;
+                                    0: general path with partial pivoting (the paper's symmetry
+                                    flag, §4 and §6.1) */
   const char* tune_table;        /* reserved, may be NULL */
   int32_t keep_coarse_matrix;    /* 1: keep S_PiPi for mbddc_get_coarse_matrix (8 n_c^2 bytes) */
 } mbddc_options;

@@ -45,6 +45,7 @@ struct GemmDesc {
   int32_t M, N, K, lda, ldb, ldc, ldci, tiles_n;
   int64_t oA, oB, oC, oCi;
   double alpha, beta;
+  int32_t transB, pad;                 // transB: B(k, n) is stored at B[n * ldb + k]
 };
 
 struct GemmItem {

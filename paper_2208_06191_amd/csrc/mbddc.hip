@@ -112,7 +112,7 @@ struct mbddc_ctx {
   std::vector<GjDesc> gj_kii, gj_p, gj_coarse_small;
   std::vector<int32_t> coarse_large;                 // instances inverted by the blocked path
   std::vector<GemmDesc> gemm_desc;
-  std::vector<GemmItem> gemm_items_gh, gemm_items_s, gemm_items_g, gemm_items_ssym;
+  std::vector<GemmItem> gemm_items_gh, gemm_items_s, gemm_items_g, gemm_items_ssym, gemm_items_phi, gemm_items_stil;
   std::vector<GjDesc> gj_x;                          // (S + rho C^T C) blocks of the symmetric path
   bool sym = false;                                  // symmetric (SPD) factor path
   std::vector<ApplyItem> itA, itC, itE, itF, itH;
@@ -142,7 +142,8 @@ struct mbddc_ctx {
   int32_t* d_dof_inst = nullptr;
   GjDesc *d_gj_kii = nullptr, *d_gj_p = nullptr, *d_gj_cs = nullptr;
   GemmDesc* d_gemm_desc = nullptr;
-  GemmItem *d_gemm_gh = nullptr, *d_gemm_s = nullptr, *d_gemm_g = nullptr, *d_gemm_ssym = nullptr;
+  GemmItem *d_gemm_gh = nullptr, *d_gemm_s = nullptr, *d_gemm_g = nullptr, *d_gemm_ssym = nullptr,
+           *d_gemm_phi = nullptr, *d_gemm_stil = nullptr;
   GjDesc* d_gj_x = nullptr;
   double* d_rho = nullptr;
   ApplyItem *d_itA = nullptr, *d_itC = nullptr, *d_itE = nullptr, *d_itF = nullptr, *d_itH = nullptr;
@@ -181,6 +182,8 @@ struct mbddc_ctx {
   double* h_est = nullptr;       // pinned host
   double* h_norm = nullptr;      // pinned host
   Profiler prof;
+  hipStream_t aux = nullptr;     // lookahead stream of the coarse sweep (default priority)
+  hipEvent_t ev_a = nullptr, ev_b = nullptr;
   // algorithmic bytes / flops per launch, filled by build_layout
   double op_bytes[F_COUNT] = {};
   double vec_words[F_COUNT] = {};   // FP64 vector words per right-hand side
@@ -227,6 +230,11 @@ void free_all(mbddc_ctx* c) {
   c->prof.pending.clear();
   for (hipEvent_t e : c->prof.pool) (void)hipEventDestroy(e);
   c->prof.pool.clear();
+  if (c->ev_a) (void)hipEventDestroy(c->ev_a);
+  if (c->ev_b) (void)hipEventDestroy(c->ev_b);
+  if (c->aux) (void)hipStreamDestroy(c->aux);
+  c->ev_a = c->ev_b = nullptr;
+  c->aux = nullptr;
   for (auto& a : c->allocs) (void)hipFree(a.p);
   c->allocs.clear();
   c->bytes = 0;
@@ -295,10 +303,12 @@ int build_layout(mbddc_ctx* c) {
   c->gemm_items_s.clear();
   c->gemm_items_g.clear();
   c->gemm_items_ssym.clear();
+  c->gemm_items_phi.clear();
+  c->gemm_items_stil.clear();
   c->gj_x.clear();
   c->itA.clear(); c->itC.clear(); c->itE.clear(); c->itF.clear(); c->itH.clear();
   c->max_cols = 1;
-  std::vector<GemmDesc> dS, dSs;
+  std::vector<GemmDesc> dS, dSs, dPhi, dStil;
   for (int64_t s = 0; s < P.n_sub; ++s) {
     const SubLayout& L = P.subs[s];
     SubDev& d = c->subs[s];
@@ -353,6 +363,19 @@ int build_layout(mbddc_ctx* c) {
     GemmDesc sX = sS;               // symmetric path: S written into the X block (ld nG)
     sX.ldc = (int32_t)nG;
     dSs.push_back(sX);
+    // symmetric path: Phi = XC T^-1 and S~ = X - Phi XC^T inside the P block
+    GemmDesc ph{};
+    ph.M = (int32_t)nG; ph.N = (int32_t)nc; ph.K = (int32_t)nc; ph.lda = (int32_t)nc; ph.ldb = (int32_t)nc;
+    ph.ldc = (int32_t)nc; ph.ldci = 1; ph.oA = d.oP + nG * nG; ph.oB = d.oP + nG * nG + 2 * nG * nc;
+    ph.oC = d.oP + nG * nG + nG * nc; ph.oCi = 0; ph.alpha = 1.0; ph.beta = 0.0;
+    ph.tiles_n = (int32_t)((nc + 63) / 64);
+    dPhi.push_back(ph);
+    GemmDesc st{};
+    st.M = (int32_t)nG; st.N = (int32_t)nG; st.K = (int32_t)nc; st.lda = (int32_t)nc; st.ldb = (int32_t)nc;
+    st.ldc = (int32_t)nG; st.ldci = (int32_t)nG; st.oA = d.oP + nG * nG + nG * nc; st.oB = d.oP + nG * nG;
+    st.oC = d.oP; st.oCi = d.oP; st.alpha = -1.0; st.beta = 1.0; st.transB = 1;
+    st.tiles_n = (int32_t)((nG + 63) / 64);
+    dStil.push_back(st);
     // apply work items
     auto add = [](std::vector<ApplyItem>& v, int64_t sub, int64_t rows) {
       int64_t nb = std::max<int64_t>(1, (rows + 255) / 256);
@@ -370,13 +393,18 @@ int build_layout(mbddc_ctx* c) {
     for (int32_t a = 0; a < tm; ++a)
       for (int32_t b = 0; b < tn; ++b) c->gemm_items_s.push_back({id, a, b, 0});
   }
-  for (GemmDesc& sX : dSs) {
-    int32_t id = (int32_t)c->gemm_desc.size();
-    c->gemm_desc.push_back(sX);
-    int32_t tm = (sX.M + 63) / 64, tn = sX.tiles_n;
-    for (int32_t a = 0; a < tm; ++a)
-      for (int32_t b = 0; b < tn; ++b) c->gemm_items_ssym.push_back({id, a, b, 0});
-  }
+  auto add_items = [&](std::vector<GemmDesc>& ds, std::vector<GemmItem>& items) {
+    for (GemmDesc& g : ds) {
+      int32_t id = (int32_t)c->gemm_desc.size();
+      c->gemm_desc.push_back(g);
+      int32_t tm = (g.M + 63) / 64, tn = g.tiles_n;
+      for (int32_t a = 0; a < tm; ++a)
+        for (int32_t b = 0; b < tn; ++b) items.push_back({id, a, b, 0});
+    }
+  };
+  add_items(dSs, c->gemm_items_ssym);
+  add_items(dPhi, c->gemm_items_phi);
+  add_items(dStil, c->gemm_items_stil);
   c->w_elems = w;
   c->op_elems = op;
   c->kcl_elems = kcl;
@@ -522,6 +550,8 @@ int upload_plan(mbddc_ctx* c) {
   CHK(upload(c, &c->d_gemm_s, c->gemm_items_s));
   CHK(upload(c, &c->d_gemm_g, c->gemm_items_g));
   CHK(upload(c, &c->d_gemm_ssym, c->gemm_items_ssym));
+  CHK(upload(c, &c->d_gemm_phi, c->gemm_items_phi));
+  CHK(upload(c, &c->d_gemm_stil, c->gemm_items_stil));
   CHK(upload(c, &c->d_gj_x, c->gj_x));
   CHK(dalloc(c, &c->d_rho, std::max<int64_t>(P.n_sub, 1)));
   CHK(upload(c, &c->d_itA, c->itA));
@@ -547,9 +577,10 @@ int upload_plan(mbddc_ctx* c) {
   CHK(dalloc(c, &c->d_piv_c, std::max<int64_t>(std::max<int64_t>(P.n_coarse, c->coarse_max_nc), 1)));
   if (!c->coarse_large.empty()) {
     int64_t ldmax = round_up(c->coarse_max_nc, 4);
-    CHK(dalloc(c, &c->d_cDinv, kCoarseBlock * kCoarseBlock));
-    CHK(dalloc(c, &c->d_cY, kCoarseBlock * ldmax));
-    CHK(dalloc(c, &c->d_cCcol, ldmax * kCoarseBlock));
+    const int64_t cb = std::max(kCoarseBlock, kSymCB);
+    CHK(dalloc(c, &c->d_cDinv, 2 * cb * cb));
+    CHK(dalloc(c, &c->d_cY, cb * ldmax));
+    CHK(dalloc(c, &c->d_cCcol, ldmax * cb));
   }
   CHK(dalloc(c, &c->d_amax, 1));
   HIPCHK(hipStreamSynchronize(c->stream));
@@ -636,6 +667,89 @@ __global__ void k_absmax(const double* __restrict__ A, int n, int ld, double* ou
   }
   m = wave_max(m);
   if ((threadIdx.x & 63) == 0) atomicMax(reinterpret_cast<unsigned long long*>(out), (unsigned long long)__double_as_longlong(m));
+}
+
+// Symmetric coarse inverse: blocked sweep, lower triangle, MFMA update.
+int coarse_sweep_large(mbddc_ctx* c, int32_t ii) {
+  const int n = c->inst_nc[ii], ld = c->inst_kc_ld[ii];
+  double* A = c->d_Kc + c->inst_kc_off[ii];
+  HIPCHK(hipMemsetAsync(c->d_amax, 0, sizeof(double), c->stream));
+  hipLaunchKernelGGL(k_absmax, dim3(512), dim3(kBlock), 0, c->stream, A, n, ld, c->d_amax);
+  double amax = 0.0;
+  HIPCHK(hipMemcpyAsync(&amax, c->d_amax, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipMemsetAsync(c->d_status, 0, sizeof(int32_t), c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  const double thresh = std::max((double)n * 2.220446049250313e-16, 1e-12) * amax;
+  double* Wg = c->d_cCcol;     // n x kSymCB
+  double* Ug = c->d_cY;        // n x kSymCB
+  GemmDesc gd{};
+  gd.M = n; gd.N = kSymCB; gd.K = kSymCB; gd.lda = kSymCB; gd.ldb = kSymCB; gd.ldc = kSymCB; gd.ldci = kSymCB;
+  gd.tiles_n = kSymCB / 64; gd.oA = 0; gd.oB = 0; gd.oC = 0; gd.oCi = 0; gd.alpha = 1.0; gd.beta = 0.0;
+  std::vector<GemmItem> items;
+  for (int a = 0; a < (n + 63) / 64; ++a)
+    for (int b = 0; b < gd.tiles_n; ++b) items.push_back({0, a, b, 0});
+  GemmDesc* d_gd = nullptr;
+  GemmItem* d_items = nullptr;
+  CHK(upload(c, &d_gd, std::vector<GemmDesc>{gd}));
+  CHK(upload(c, &d_items, items));
+  const unsigned nt = (unsigned)((n + 63) / 64);
+  const unsigned ntiles = nt * (nt + 1) / 2;
+  const unsigned nt2 = (unsigned)((n + kUpdTile - 1) / kUpdTile);
+  const unsigned ntiles2 = nt2 * (nt2 + 1) / 2;
+  const unsigned gg = std::min<unsigned>(2048, nblk((int64_t)n * kSymCB));
+  if (!c->aux) {
+    HIPCHK(hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&c->ev_a, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&c->ev_b, hipEventDisableTiming));
+  }
+  const int nb = (n + kSymCB - 1) / kSymCB;
+  double* Dbuf[2] = {c->d_cDinv, c->d_cDinv + kSymCB * kSymCB};
+  // block 0: invert on the main stream
+  hipLaunchKernelGGL(k_csym_diag, dim3(1), dim3(kBlock), 0, c->stream, A, n, ld, 0, Dbuf[0], c->d_status, thresh);
+  for (int kb = 0; kb < nb; ++kb) {
+    const int k0 = kb * kSymCB;
+    const int bw = std::min(kSymCB, n - k0);
+    double* Dk = Dbuf[kb & 1];
+    {
+      ProfScope ps(c, F_COARSE_PREP, 16.0 * n * kSymCB, 2.0 * n * (double)kSymCB * kSymCB);
+      hipLaunchKernelGGL(k_csym_gather, dim3(gg), dim3(kBlock), 0, c->stream, A, n, ld, k0, Wg);
+      if (kb > 0) HIPCHK(hipStreamWaitEvent(c->stream, c->ev_b, 0));     // Dinv of block kb (lookahead)
+      hipLaunchKernelGGL((k_gemm_batched<double>), dim3((unsigned)items.size()), dim3(kBlock), 0, c->stream, d_gd,
+                         d_items, Wg, Dk, Ug, Ug);
+    }
+    const bool ahead = kb + 1 < nb;
+    if (ahead) {
+      // update diagonal block kb+1 first, then invert it on the lookahead stream
+      hipLaunchKernelGGL(k_csym_update, dim3(3), dim3(kBlock), 0, c->stream, A, n, ld, k0, Ug, Wg, Dk, 1, kb + 1);
+      HIPCHK(hipEventRecord(c->ev_a, c->stream));
+      HIPCHK(hipStreamWaitEvent(c->aux, c->ev_a, 0));
+      hipLaunchKernelGGL(k_csym_diag, dim3(1), dim3(kBlock), 0, c->aux, A, n, ld, k0 + kSymCB, Dbuf[(kb + 1) & 1],
+                         c->d_status, thresh);
+      HIPCHK(hipEventRecord(c->ev_b, c->aux));
+    }
+    {
+      // algorithmic: lower-triangle read+write of A, flops 2 bw per lower entry
+      const double lower = 0.5 * n * (double)(n + 1);
+      ProfScope ps(c, F_COARSE_GEMM, 16.0 * lower, 2.0 * bw * lower);
+      hipLaunchKernelGGL(k_csym_update, dim3(ntiles2), dim3(kBlock), 0, c->stream, A, n, ld, k0, Ug, Wg, Dk, 0,
+                         ahead ? kb + 1 : -1);
+    }
+  }
+  {
+    ProfScope ps(c, F_COARSE_ROWS, 16.0 * n * (double)n, 0.0);
+    hipLaunchKernelGGL(k_csym_finish, dim3(ntiles), dim3(kBlock), 0, c->stream, A, n, ld);
+  }
+  HIPCHK(hipGetLastError());
+  int32_t st = 0;
+  HIPCHK(hipMemcpyAsync(&st, c->d_status, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  dfree(c, d_gd);
+  dfree(c, d_items);
+  if (st != 0) {
+    c->last_bad = -1;
+    return MBDDC_ERR_SINGULAR;
+  }
+  return MBDDC_OK;
 }
 
 int coarse_invert_large(mbddc_ctx* c, int32_t ii) {
@@ -762,8 +876,14 @@ int factor_impl(mbddc_ctx* c) {
     }
     {
       ProfScope ps(c, F_EXTRACT, 0.0, 0.0);
-      hipLaunchKernelGGL((k_constrained_blocks<T>), dim3(nsub), dim3(kBlock), 0, c->stream, c->d_subs,
+      hipLaunchKernelGGL((k_constrained_small<T>), dim3(nsub), dim3(kBlock), 0, c->stream, c->d_subs,
                          c->d_cons_ptr, c->d_cons_idx, c->d_cons_w, c->d_rho, W, c->d_Kcl, c->d_status);
+      if (!c->gemm_items_phi.empty())
+        hipLaunchKernelGGL((k_gemm_batched<T>), dim3((unsigned)c->gemm_items_phi.size()), dim3(kBlock), 0,
+                           c->stream, c->d_gemm_desc, c->d_gemm_phi, W, W, W, W);
+      if (!c->gemm_items_stil.empty())
+        hipLaunchKernelGGL((k_gemm_batched<T>), dim3((unsigned)c->gemm_items_stil.size()), dim3(kBlock), 0,
+                           c->stream, c->d_gemm_desc, c->d_gemm_stil, W, W, W, W);
       hipLaunchKernelGGL((k_extract_sym<T, To>), dim3(nsub), dim3(kBlock), 0, c->stream, c->d_subs, c->d_slot_w, W,
                          Op);
     }
@@ -822,7 +942,7 @@ int factor_impl(mbddc_ctx* c) {
         return st;
       }
     }
-    for (int32_t ii : c->coarse_large) CHK(coarse_invert_large(c, ii));
+    for (int32_t ii : c->coarse_large) CHK(c->sym ? coarse_sweep_large(c, ii) : coarse_invert_large(c, ii));
   }
   HIPCHK(hipStreamSynchronize(c->stream));
   return MBDDC_OK;

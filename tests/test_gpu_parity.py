@@ -41,7 +41,10 @@ def solver_for(P, precision, primal, sym=0, **kw):
     o = mbddc.default_options(precision=precision, primal=primal, keep_coarse_matrix=1, symmetric_hint=sym, **kw)
     s.mbddc_setup_symbolic([mbddc.mesh_from_problem(P)], o)
     s.mbddc_set_tangent(P.Ke)
-    s.mbddc_factor()
+    try:
+        s.mbddc_factor()
+    except mbddc.MbddcError as e:
+        raise AssertionError(f"factor failed: {e}, subdomain {s.last_bad_subdomain()}") from e
     return s
 
 
