@@ -78,8 +78,11 @@ typedef struct {
 
 typedef struct {
   uint32_t primal;               /* MBDDC_PRIMAL_* bitmask */
-  int32_t levels;                /* 2 (this build) */
-  int32_t coarse_group;          /* level-2 group size (reserved) */
+  int32_t levels;                /* 2: exact (dense FP64) coarse solve; 3: the coarse problem is itself
+                                    solved approximately by one BDDC application (multilevel BDDC,
+                                    §3.2 last paragraph), whose level-3 coarse problem is exact */
+  int32_t coarse_group;          /* levels = 3: fine subdomain i of an instance belongs to level-2
+                                    subdomain i / coarse_group (§7 uses groups of 8) */
   int32_t precision;             /* MBDDC_FP64 or MBDDC_MIXED */
   int32_t restart;               /* GMRES restart length, 1..64 */
   double rtol;                   /* relative residual target on ||b - K x||_2 */
@@ -92,6 +95,13 @@ typedef struct {
                                     flag, §4 and §6.1) */
   const char* tune_table;        /* reserved, may be NULL */
   int32_t keep_coarse_matrix;    /* 1: keep S_PiPi for mbddc_get_coarse_matrix (8 n_c^2 bytes) */
+  uint32_t coarse_primal;        /* levels = 3: primal globs of the level-2 decomposition
+                                    (MBDDC_PRIMAL_* bitmask; default V|E|F). Level-2 nodes are the
+                                    fine primal globs (three coarse components each; a component
+                                    without a coarse DOF is treated as clamped), level-2 elements
+                                    the fine subdomains with their matrices Phi_i^T A^(i) Phi_i;
+                                    level-2 globs use the fine glob's first-node boundary tags.
+                                    Level 2 and 3 are always computed in FP64. */
 } mbddc_options;
 
 typedef struct {
@@ -114,6 +124,8 @@ typedef struct {
   int64_t n_vertices, n_edges, n_faces;
   int64_t max_local;             /* largest local dense problem size */
   int64_t bsr_blocks;            /* 3x3 blocks of the assembled operator */
+  int64_t n_sub2;                /* levels = 3: level-2 subdomains (all instances), else 0 */
+  int64_t n_coarse2;             /* levels = 3: level-3 coarse DOFs (all instances), else 0 */
 } mbddc_sizes;
 
 /* Creates a handle on HIP device `hip_device`, enqueuing on `hip_stream` (a
@@ -121,7 +133,7 @@ typedef struct {
 int mbddc_create(mbddc_ctx** out, int hip_device, void* hip_stream);
 
 /* Fills `opt` with the defaults: primal V|E, 2 levels, group 8, MIXED, restart
- * 30, rtol 1e-8, max_it 1000. */
+ * 30, rtol 1e-8, max_it 1000, level-2 primal V|E|F. */
 int mbddc_default_options(mbddc_options* opt);
 
 /* Host-side symbolic setup (§3.2 index sets: interior / interface, vertex /
@@ -147,8 +159,12 @@ int mbddc_get_sizes(const mbddc_ctx* ctx, mbddc_sizes* out);
 int mbddc_set_tangent(mbddc_ctx* ctx, const double* elem_K, int on_device);
 
 /* Numeric BDDC setup (§3.2): local interior and constrained-Neumann problems,
- * coarse basis Phi, coarse matrix S_PiPi and its FP64 factorisation.
- * Returns MBDDC_ERR_SINGULAR on a zero pivot (mbddc_last_bad_subdomain). */
+ * coarse basis Phi, coarse matrix S_PiPi and its FP64 factorisation. With
+ * levels = 3 S_PiPi is not factorised: the level-2 BDDC setup on the coarse
+ * problem runs instead (its local problems, its coarse basis and the FP64
+ * factorisation of the level-3 coarse matrix).
+ * Returns MBDDC_ERR_SINGULAR on a zero pivot (mbddc_last_bad_subdomain; -1 for
+ * the coarse problem, and for any level-2 or level-3 problem). */
 int mbddc_factor(mbddc_ctx* ctx);
 
 /* Right-preconditioned GMRES(restart) for `nrhs` right-hand sides (each
@@ -170,7 +186,8 @@ int mbddc_get_globs(const mbddc_ctx* ctx, int32_t* node_glob, int32_t* n_globs, 
                     int32_t* coarse_glob, int32_t* coarse_comp);
 
 /* The assembled coarse matrix S_PiPi of instance `inst` before factorisation,
- * [n_c][n_c] FP64 row-major (host). Available after factor. */
+ * [n_c][n_c] FP64 row-major (host). Available after factor when the options
+ * asked to keep it (also with levels = 3, where it is the level-2 operator). */
 int mbddc_get_coarse_matrix(const mbddc_ctx* ctx, int inst, double* out, int64_t n_c);
 
 /* The assembled operator in 3x3-block CSR over nodes (host): rowptr [n_nodes+1],

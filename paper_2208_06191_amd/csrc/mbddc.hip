@@ -64,13 +64,14 @@ enum Family {
   F_ASSEMBLE_BSR, F_ASSEMBLE_LOCAL, F_GJ_KII, F_GEMM_GH, F_GEMM_S, F_CONSTRAINTS, F_GJ_P, F_EXTRACT,
   F_COARSE_ASSEMBLE, F_COARSE_GJ_SMALL, F_COARSE_DIAG, F_COARSE_PREP, F_COARSE_GEMM, F_COARSE_ROWS,
   F_APPLY_A, F_APPLY_C, F_APPLY_E, F_APPLY_F, F_APPLY_H, F_SPMV, F_KRYLOV_DOTS, F_KRYLOV_UPDATE,
-  F_KRYLOV_SMALL, F_KRYLOV_VEC, F_COUNT
+  F_KRYLOV_SMALL, F_KRYLOV_VEC, F_LEVEL2_SETUP, F_LEVEL2_APPLY, F_COUNT
 };
 const char* const kFamilyName[F_COUNT] = {
   "assemble_bsr", "assemble_local", "gj_interior", "gemm_condense", "gemm_schur", "constraints", "gj_interface",
   "extract_operators", "coarse_assemble", "coarse_gj_small", "coarse_gj_diag", "coarse_gj_prep", "coarse_gj_gemm",
   "coarse_gj_rows", "apply_A_interior", "apply_C_interface", "apply_E_coarse", "apply_F_coarse_ext",
-  "apply_H_average", "spmv_bsr", "krylov_dots", "krylov_update", "krylov_small", "krylov_vectors"};
+  "apply_H_average", "spmv_bsr", "krylov_dots", "krylov_update", "krylov_small", "krylov_vectors",
+  "level2_setup", "apply_E_level2"};
 
 struct Profiler {
   uint32_t mask = 0;
@@ -114,6 +115,7 @@ struct mbddc_ctx {
   std::vector<GemmDesc> gemm_desc;
   std::vector<GemmItem> gemm_items_gh, gemm_items_s, gemm_items_g, gemm_items_ssym, gemm_items_phi, gemm_items_stil;
   std::vector<GjDesc> gj_x;                          // (S + rho C^T C) blocks of the symmetric path
+  std::vector<GjDesc> gj_t;                          // T = C X C^T blocks too large for LDS (symmetric path)
   bool sym = false;                                  // symmetric (SPD) factor path
   std::vector<ApplyItem> itA, itC, itE, itF, itH;
   std::vector<int64_t> inst_coarse_off, inst_kc_off;
@@ -145,6 +147,7 @@ struct mbddc_ctx {
   GemmItem *d_gemm_gh = nullptr, *d_gemm_s = nullptr, *d_gemm_g = nullptr, *d_gemm_ssym = nullptr,
            *d_gemm_phi = nullptr, *d_gemm_stil = nullptr;
   GjDesc* d_gj_x = nullptr;
+  GjDesc* d_gj_t = nullptr;
   double* d_rho = nullptr;
   ApplyItem *d_itA = nullptr, *d_itC = nullptr, *d_itE = nullptr, *d_itF = nullptr, *d_itH = nullptr;
   int32_t *d_chunk_inst = nullptr, *d_inst_chunk_off = nullptr;
@@ -188,6 +191,11 @@ struct mbddc_ctx {
   double op_bytes[F_COUNT] = {};
   double vec_words[F_COUNT] = {};   // FP64 vector words per right-hand side
   double fam_flops[F_COUNT] = {};
+  // three levels: the coarse problem is a level-2 BDDC instance of its own (FP64)
+  mbddc_ctx* child = nullptr;
+  std::vector<int32_t> l2_dof;      // [n_coarse] level-2 DOF of each coarse DOF
+  std::vector<int32_t> l2_eidx;     // [n_cslots] level-2 element-local DOF of each coarse slot
+  int32_t *d_l2_dof = nullptr, *d_l2_eidx = nullptr;
 };
 
 namespace {
@@ -223,6 +231,11 @@ void dfree(mbddc_ctx* c, T*& p) {
 }
 
 void free_all(mbddc_ctx* c) {
+  if (c->child) {
+    free_all(c->child);
+    delete c->child;
+    c->child = nullptr;
+  }
   for (auto& e : c->prof.pending) {
     c->prof.pool.push_back(e.a);
     c->prof.pool.push_back(e.b);
@@ -306,6 +319,7 @@ int build_layout(mbddc_ctx* c) {
   c->gemm_items_phi.clear();
   c->gemm_items_stil.clear();
   c->gj_x.clear();
+  c->gj_t.clear();
   c->itA.clear(); c->itC.clear(); c->itE.clear(); c->itF.clear(); c->itH.clear();
   c->max_cols = 1;
   std::vector<GemmDesc> dS, dSs, dPhi, dStil;
@@ -317,7 +331,6 @@ int build_layout(mbddc_ctx* c) {
     d.dof_off = L.dof_off; d.if_off = L.if_off; d.c_off = L.c_off; d.elem_off = L.elem_off; d.cons_off = L.cons_off;
     const int64_t ni = L.ni(), nI = L.nI, nG = L.nG, nc = L.nc, m = L.mP();
     if (std::max<int64_t>(nI, m) > kGjMax) return MBDDC_ERR_UNSUPPORTED;
-    if (c->sym && nc > kMaxLocalConstraints) return MBDDC_ERR_UNSUPPORTED;
     d.oK = w; w += round_up(ni * ni, 64);
     d.oG = w; w += round_up(nG * nI, 64);
     d.oH = w; w += round_up(nI * nG, 64);
@@ -336,6 +349,8 @@ int build_layout(mbddc_ctx* c) {
     c->gj_kii.push_back({d.oK, (int32_t)nI, (int32_t)ni, d.oPiv, (int32_t)s, 0});
     c->gj_p.push_back({d.oP, (int32_t)m, (int32_t)m, d.oPiv + nI, (int32_t)s, 0});
     c->gj_x.push_back({d.oP, (int32_t)nG, (int32_t)nG, 0, (int32_t)s, 0});
+    if (c->sym && nc > kMaxLocalConstraints)   // T = C X C^T inverted by the batched sweep
+      c->gj_t.push_back({d.oP + nG * nG + 2 * nG * nc, (int32_t)nc, (int32_t)nc, 0, (int32_t)s, 0});
     // G = K_GI K_II^-1, H = K_II^-1 K_IG, S = K_GG - G K_IG
     GemmDesc g{};
     g.M = (int32_t)nG; g.N = (int32_t)nI; g.K = (int32_t)nI; g.lda = (int32_t)ni; g.ldb = (int32_t)ni; g.ldc = (int32_t)nI;
@@ -429,10 +444,11 @@ int build_layout(mbddc_ctx* c) {
     c->inst_kc_off[ii] = kc;
     kc += round_up((int64_t)ld * std::max(in.n_coarse, 1), 64);
     c->coarse_max_nc = std::max(c->coarse_max_nc, in.n_coarse);
-    int32_t nch = std::max(1, (in.n_coarse + kCoarseChunk - 1) / kCoarseChunk);
+    const bool three = c->opt.levels == 3;
+    int32_t nch = three ? 1 : std::max(1, (in.n_coarse + kCoarseChunk - 1) / kCoarseChunk);
     c->inst_nchunk[ii] = nch;
     c->nchunk_max = std::max(c->nchunk_max, nch);
-    if (in.n_coarse > 0) {
+    if (in.n_coarse > 0 && !three) {
       if (in.n_coarse <= kGjMax)
         c->gj_coarse_small.push_back({c->inst_kc_off[ii], in.n_coarse, ld, in.coarse_off, ii, 0});
       else
@@ -493,7 +509,7 @@ int build_layout(mbddc_ctx* c) {
     c->op_bytes[F_APPLY_E] += 8.0 * c->inst_kc_ld[ii] * nc;
     c->fam_flops[F_APPLY_E] += nc * nc;
     c->vec_words[F_APPLY_E] += nc * (1 + c->inst_nchunk[ii]);
-    if (nc > 0 && nc <= kGjMax) c->fam_flops[F_COARSE_GJ_SMALL] += 2.0 * nc * nc * nc;
+    if (nc > 0 && nc <= kGjMax && c->opt.levels != 3) c->fam_flops[F_COARSE_GJ_SMALL] += 2.0 * nc * nc * nc;
   }
   c->op_bytes[F_ASSEMBLE_LOCAL] += 8.0 * P.ke_total;
   c->op_bytes[F_ASSEMBLE_BSR] = 8.0 * P.ke_total + 72.0 * c->nblocks;
@@ -553,6 +569,7 @@ int upload_plan(mbddc_ctx* c) {
   CHK(upload(c, &c->d_gemm_phi, c->gemm_items_phi));
   CHK(upload(c, &c->d_gemm_stil, c->gemm_items_stil));
   CHK(upload(c, &c->d_gj_x, c->gj_x));
+  CHK(upload(c, &c->d_gj_t, c->gj_t));
   CHK(dalloc(c, &c->d_rho, std::max<int64_t>(P.n_sub, 1)));
   CHK(upload(c, &c->d_itA, c->itA));
   CHK(upload(c, &c->d_itC, c->itC));
@@ -569,7 +586,7 @@ int upload_plan(mbddc_ctx* c) {
   CHK(dalloc(c, reinterpret_cast<unsigned char**>(&c->d_W), c->w_elems * (int64_t)elem_size(c->fact32)));
   CHK(dalloc(c, reinterpret_cast<unsigned char**>(&c->d_Op), c->op_elems * (int64_t)es));
   CHK(dalloc(c, &c->d_Kcl, c->kcl_elems));
-  CHK(dalloc(c, &c->d_Kc, c->kc_elems));
+  CHK(dalloc(c, &c->d_Kc, c->opt.levels == 3 ? 1 : c->kc_elems));
   if (c->opt.keep_coarse_matrix) CHK(dalloc(c, &c->d_Kc_keep, c->kc_elems));
   CHK(dalloc(c, &c->d_piv, c->piv_elems));
   c->status_len = std::max<int64_t>(P.n_sub, (int64_t)c->gj_coarse_small.size()) + 1;
@@ -587,7 +604,94 @@ int upload_plan(mbddc_ctx* c) {
   return MBDDC_OK;
 }
 
+// Multilevel BDDC (§3.2, last paragraph): the coarse problem of every instance
+// becomes a BDDC problem of its own. Level-2 nodes are the instance's fine
+// primal globs (in glob order), each with the three components of a
+// displacement; a component without a coarse DOF is clamped. Level-2 elements
+// are the fine subdomains (nodes: their primal globs, ascending), fine
+// subdomain i belongs to level-2 subdomain i / coarse_group, and a level-2
+// node carries the boundary tags of its glob's first node.
+int build_level2(mbddc_ctx* c, const std::vector<MeshIn>& fine) {
+  const Plan& P = c->plan;
+  const int32_t group = c->opt.coarse_group;
+  std::vector<MeshIn> m2(P.n_inst);
+  c->l2_dof.assign(P.n_coarse, -1);
+  c->l2_eidx.assign(P.n_cslots, -1);
+  int64_t node_off2 = 0;
+  for (int32_t ii = 0; ii < P.n_inst; ++ii) {
+    const Instance& in = P.inst[ii];
+    if (in.n_coarse <= 0) return MBDDC_ERR_UNSUPPORTED;   // nothing to coarsen
+    MeshIn& m = m2[ii];
+    std::vector<int32_t> gnode(in.n_globs, -1);
+    int32_t nn = 0;
+    for (int32_t k = 0; k < in.n_coarse; ++k) {
+      const int64_t cid = in.coarse_off + k;
+      const int32_t g = P.coarse_glob[cid] - (int32_t)in.glob_off;
+      if (gnode[g] < 0) gnode[g] = nn++;
+      c->l2_dof[cid] = (int32_t)(3 * (node_off2 + gnode[g]) + P.coarse_comp[cid]);
+    }
+    m.n_nodes = nn;
+    std::vector<uint8_t> present(3 * (size_t)nn, 0);
+    for (int32_t k = 0; k < in.n_coarse; ++k) present[c->l2_dof[in.coarse_off + k] - 3 * node_off2] = 1;
+    for (int32_t d = 0; d < 3 * nn; ++d)
+      if (!present[d]) m.dirichlet.push_back(d);
+    const std::vector<uint32_t>& tags = fine[ii].node_tags;
+    if (!tags.empty()) {
+      m.node_tags.assign(nn, 0u);
+      for (int32_t g = 0; g < in.n_globs; ++g)
+        if (gnode[g] >= 0) m.node_tags[gnode[g]] = tags[P.glob_node0[in.glob_off + g] - in.node_off];
+    }
+    m.n_elems = in.n_sub;
+    m.n_sub = (in.n_sub + group - 1) / group;
+    m.npe = 0;
+    m.elem_ptr.push_back(0);
+    for (int32_t i = 0; i < in.n_sub; ++i) {
+      const SubLayout& L = P.subs[in.sub_off + i];
+      if (L.nc <= 0) return MBDDC_ERR_UNSUPPORTED;        // a subdomain without primal DOFs
+      std::vector<int32_t> nodes;
+      for (int32_t p = 0; p < L.nc; ++p) {
+        const int32_t cid = P.cslot_coarse[L.c_off + p];
+        nodes.push_back((int32_t)(c->l2_dof[cid] / 3 - node_off2));
+      }
+      std::sort(nodes.begin(), nodes.end());
+      nodes.erase(std::unique(nodes.begin(), nodes.end()), nodes.end());
+      for (int32_t p = 0; p < L.nc; ++p) {
+        const int32_t cid = P.cslot_coarse[L.c_off + p];
+        const int32_t nd = (int32_t)(c->l2_dof[cid] / 3 - node_off2);
+        const int32_t a = (int32_t)(std::lower_bound(nodes.begin(), nodes.end(), nd) - nodes.begin());
+        c->l2_eidx[L.c_off + p] = 3 * a + P.coarse_comp[cid];
+      }
+      m.elem_nodes.insert(m.elem_nodes.end(), nodes.begin(), nodes.end());
+      m.elem_ptr.push_back((int32_t)m.elem_nodes.size());
+      m.elem_part.push_back(i / group);
+    }
+    node_off2 += nn;
+  }
+  mbddc_ctx* ch = new (std::nothrow) mbddc_ctx();
+  if (!ch) return MBDDC_ERR_OOM;
+  c->child = ch;
+  ch->device = c->device;
+  ch->stream = c->stream;
+  ch->opt = c->opt;
+  ch->opt.levels = 2;
+  ch->opt.primal = c->opt.coarse_primal;
+  ch->opt.precision = MBDDC_FP64;
+  ch->mixed = false;
+  ch->fact32 = false;
+  ch->sym = c->sym;
+  if (!build_plan(m2, ch->opt.primal, ch->plan).empty()) return MBDDC_ERR_ARG;
+  CHK(build_layout(ch));
+  CHK(upload_plan(ch));
+  HIPCHK(hipMemsetAsync(ch->d_Ke, 0, ch->plan.ke_total * sizeof(double), c->stream));
+  CHK(upload(c, &c->d_l2_dof, c->l2_dof));
+  CHK(upload(c, &c->d_l2_eidx, c->l2_eidx));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  ch->state = 2;
+  return MBDDC_OK;
+}
+
 int ensure_apply_buffers(mbddc_ctx* c, int R) {
+  if (c->child) CHK(ensure_apply_buffers(c->child, R));
   if (c->R_alloc >= R) {
     if (c->Y_R != R) {   // clamped entries of the output block are never written by the apply
       HIPCHK(hipMemsetAsync(c->d_Y, 0, c->plan.n_dofs * c->R_alloc * sizeof(double), c->stream));
@@ -878,6 +982,26 @@ int factor_impl(mbddc_ctx* c) {
       ProfScope ps(c, F_EXTRACT, 0.0, 0.0);
       hipLaunchKernelGGL((k_constrained_small<T>), dim3(nsub), dim3(kBlock), 0, c->stream, c->d_subs,
                          c->d_cons_ptr, c->d_cons_idx, c->d_cons_w, c->d_rho, W, c->d_Kcl, c->d_status);
+      if (!c->gj_t.empty()) {   // T^-1 of the subdomains with many constraints
+        HIPCHK(hipGetLastError());
+        st = check_status(c, (int64_t)c->gj_x.size(), c->gj_x, &bad);
+        if (st) {
+          c->last_bad = bad;
+          return st;
+        }
+        int maxt = 1;
+        for (const GjDesc& g : c->gj_t) maxt = std::max(maxt, g.n);
+        CHK(run_sym<T>(c, W, c->d_gj_t, (int64_t)c->gj_t.size(), maxt, c->d_status));
+        st = check_status(c, (int64_t)c->gj_t.size(), c->gj_t, &bad);
+        if (st) {
+          c->last_bad = bad;
+          return st;
+        }
+        hipLaunchKernelGGL((k_tinv_finish<T>), dim3((unsigned)c->gj_t.size()), dim3(kBlock), 0, c->stream, c->d_subs,
+                           c->d_gj_t, c->d_rho, W, c->d_Kcl);
+        // the statuses of the first launch were read; clear them for the check after extraction
+        hipLaunchKernelGGL(k_fill_i32, dim3(nblk(nsub)), dim3(kBlock), 0, c->stream, c->d_status, (int64_t)nsub, 0);
+      }
       if (!c->gemm_items_phi.empty())
         hipLaunchKernelGGL((k_gemm_batched<T>), dim3((unsigned)c->gemm_items_phi.size()), dim3(kBlock), 0,
                            c->stream, c->d_gemm_desc, c->d_gemm_phi, W, W, W, W);
@@ -915,7 +1039,29 @@ int factor_impl(mbddc_ctx* c) {
                          c->d_Kcl);
     }
   }
-  if (P.n_coarse > 0) {
+  if (P.n_coarse > 0 && c->child) {
+    // multilevel BDDC: S_PiPi is handed to the level-2 BDDC setup unassembled
+    if (c->d_Kc_keep) {
+      hipLaunchKernelGGL(k_coarse_assemble, dim3((unsigned)P.n_coarse), dim3(kBlock), 0, c->stream, c->d_subs,
+                         c->d_coarse_ptr, c->d_coarse_slots, c->d_cslot_sub, c->d_cslot_coarse, c->d_inst_coarse_off,
+                         c->d_inst_nc, c->d_inst_kc_off, c->d_inst_kc_ld, c->d_coarse_inst, c->d_Kcl, c->d_Kc_keep);
+      HIPCHK(hipGetLastError());
+    }
+    mbddc_ctx* ch = c->child;
+    {
+      ProfScope ps(c, F_LEVEL2_SETUP, 0.0, 0.0);
+      hipLaunchKernelGGL(k_l2_elements, dim3(nsub), dim3(kBlock), 0, c->stream, c->d_subs, c->d_Kcl, c->d_l2_eidx,
+                         ch->d_ke_off, ch->d_elem_npe, ch->d_Ke);
+      HIPCHK(hipGetLastError());
+      ch->last_bad = 0;
+      st = factor_impl<double, double>(ch);
+    }
+    if (st) {
+      c->last_bad = -1;
+      return st;
+    }
+    ch->state = 3;
+  } else if (P.n_coarse > 0) {
     {
       ProfScope ps(c, F_COARSE_ASSEMBLE, 0.0, 0.0);
       hipLaunchKernelGGL(k_coarse_assemble, dim3((unsigned)P.n_coarse), dim3(kBlock), 0, c->stream, c->d_subs,
@@ -983,7 +1129,17 @@ int apply_impl(mbddc_ctx* c, const double* r, double* z) {
     a.items = c->d_itC;
     hipLaunchKernelGGL((k_apply_local<To, R, 1>), dim3((unsigned)c->itC.size()), dim3(kBlock), lds_local, c->stream, a);
   }
-  if (!c->itE.empty()) {
+  if (c->child) {
+    mbddc_ctx* ch = c->child;
+    ProfScope ps(c, F_LEVEL2_APPLY, 0.0, 0.0);
+    const unsigned g = nblk(P.n_coarse * R);
+    hipLaunchKernelGGL(k_l2_gather, dim3(g), dim3(kBlock), 0, c->stream, (int64_t)P.n_coarse, R, c->d_coarse_ptr,
+                       c->d_coarse_slots, c->d_cc, c->d_l2_dof, ch->d_X);
+    HIPCHK(hipGetLastError());
+    CHK((apply_impl<double, R>(ch, ch->d_X, ch->d_Y)));
+    hipLaunchKernelGGL(k_l2_scatter, dim3(g), dim3(kBlock), 0, c->stream, (int64_t)P.n_coarse, R, c->d_l2_dof, ch->d_Y,
+                       c->d_ep);
+  } else if (!c->itE.empty()) {
     const size_t lds_c = (size_t)(4 * 256 * R + kCoarseChunk * R) * sizeof(double);
     ProfScope ps(c, F_APPLY_E, c->op_bytes[F_APPLY_E] + 8.0 * R * c->vec_words[F_APPLY_E],
                  2.0 * R * c->fam_flops[F_APPLY_E]);
@@ -1327,6 +1483,7 @@ int mbddc_default_options(mbddc_options* opt) {
   opt->primal = MBDDC_PRIMAL_V | MBDDC_PRIMAL_E;
   opt->levels = 2;
   opt->coarse_group = 8;
+  opt->coarse_primal = MBDDC_PRIMAL_V | MBDDC_PRIMAL_E | MBDDC_PRIMAL_F;
   opt->precision = MBDDC_MIXED;
   opt->restart = 30;
   opt->rtol = 1e-8;
@@ -1366,7 +1523,7 @@ int mbddc_setup_symbolic_batch(mbddc_ctx* c, int n_inst, const mbddc_mesh* meshe
   mbddc_options o;
   if (opt) o = *opt;
   else mbddc_default_options(&o);
-  if (o.levels != 2 || o.restart < 1 || o.restart > 63 || !(o.rtol > 0.0) || o.max_it < 1 ||
+  if ((o.levels != 2 && o.levels != 3) || o.coarse_group < 1 || (o.coarse_primal & ~7u) || o.restart < 1 || o.restart > 63 || !(o.rtol > 0.0) || o.max_it < 1 ||
       (o.precision != MBDDC_FP64 && o.precision != MBDDC_MIXED && o.precision != MBDDC_MIXED_F32FACT) ||
       (o.primal & ~7u))
     return MBDDC_ERR_ARG;
@@ -1398,6 +1555,7 @@ int mbddc_setup_symbolic_batch(mbddc_ctx* c, int n_inst, const mbddc_mesh* meshe
   c->d_active = c->d_mode = c->d_fin = nullptr;
   c->d_Kc_keep = nullptr;
   c->d_cDinv = c->d_cY = c->d_cCcol = nullptr;
+  c->d_l2_dof = c->d_l2_eidx = nullptr;
   c->opt = o;
   c->mixed = (o.precision != MBDDC_FP64);
   c->fact32 = (o.precision == MBDDC_MIXED_F32FACT);
@@ -1408,6 +1566,7 @@ int mbddc_setup_symbolic_batch(mbddc_ctx* c, int n_inst, const mbddc_mesh* meshe
   int st = build_layout(c);
   if (st) return st;
   st = upload_plan(c);
+  if (!st && o.levels == 3) st = build_level2(c, ms);
   if (st) {
     free_all(c);
     return st;
@@ -1430,6 +1589,11 @@ int mbddc_footprint(const mbddc_ctx* c, size_t* device_bytes) {
   extra += (size_t)P.n_slots * R * 8 * 2 + (size_t)std::max<int64_t>(P.n_cslots, 1) * R * 8;
   extra += (size_t)c->nchunk_max * std::max<int64_t>(P.n_coarse, 1) * R * 8;
   extra += (size_t)P.n_dofs * R * 8 * (3 + 2 * J + 4);
+  if (const mbddc_ctx* ch = c->child) {   // level-2 operators and its apply buffers
+    const Plan& Q = ch->plan;
+    extra += ch->bytes + (size_t)Q.n_slots * R * 8 * 2 + (size_t)std::max<int64_t>(Q.n_cslots, 1) * R * 8;
+    extra += (size_t)ch->nchunk_max * std::max<int64_t>(Q.n_coarse, 1) * R * 8 + (size_t)Q.n_dofs * R * 8 * 3;
+  }
   *device_bytes = c->bytes + extra;
   return MBDDC_OK;
 }
@@ -1449,6 +1613,8 @@ int mbddc_get_sizes(const mbddc_ctx* c, mbddc_sizes* out) {
   out->n_faces = P.n_faces;
   out->max_local = P.max_local;
   out->bsr_blocks = c->nblocks;
+  out->n_sub2 = c->child ? c->child->plan.n_sub : 0;
+  out->n_coarse2 = c->child ? c->child->plan.n_coarse : 0;
   return MBDDC_OK;
 }
 

@@ -34,10 +34,22 @@ std::string build_plan(const std::vector<MeshIn>& meshes, uint32_t primal, Plan&
   P.n_inst = static_cast<int32_t>(meshes.size());
   if (P.n_inst <= 0) return "no instance";
   // ---------------------------------------------------------------- offsets
+  auto npe_of = [](const MeshIn& m, int32_t e) {
+    return m.elem_ptr.empty() ? m.npe : m.elem_ptr[e + 1] - m.elem_ptr[e];
+  };
+  auto node_of = [](const MeshIn& m, int32_t e, int32_t a) {
+    return m.elem_ptr.empty() ? m.elem_nodes[(int64_t)e * m.npe + a] : m.elem_nodes[m.elem_ptr[e] + a];
+  };
   for (const MeshIn& m : meshes) {
-    if (m.npe != 8 && m.npe != 27) return "element type must be HEX8 or HEX27";
     if (m.n_nodes <= 0 || m.n_elems <= 0 || m.n_sub <= 0) return "empty mesh or partition";
-    if ((int64_t)m.elem_nodes.size() != (int64_t)m.n_elems * m.npe) return "elem_nodes size";
+    if (m.elem_ptr.empty()) {
+      if (m.npe != 8 && m.npe != 27) return "element type must be HEX8 or HEX27";
+      if ((int64_t)m.elem_nodes.size() != (int64_t)m.n_elems * m.npe) return "elem_nodes size";
+    } else {
+      if ((int64_t)m.elem_ptr.size() != (int64_t)m.n_elems + 1 || m.elem_ptr[0] != 0 ||
+          m.elem_ptr[m.n_elems] != (int32_t)m.elem_nodes.size())
+        return "elem_ptr size";
+    }
     Instance in;
     in.npe = m.npe;
     in.node_off = P.n_nodes;
@@ -51,7 +63,10 @@ std::string build_plan(const std::vector<MeshIn>& meshes, uint32_t primal, Plan&
     P.n_nodes += m.n_nodes;
     P.n_elems += m.n_elems;
     P.n_sub += m.n_sub;
-    P.ke_total += (int64_t)m.n_elems * (3 * m.npe) * (3 * m.npe);
+    for (int32_t e = 0; e < m.n_elems; ++e) {
+      int64_t k = 3LL * npe_of(m, e);
+      P.ke_total += k * k;
+    }
   }
   if (P.n_nodes * 3 > INT32_MAX) return "too many DOFs for 32-bit indices";
   P.n_dofs = 3 * P.n_nodes;
@@ -71,16 +86,19 @@ std::string build_plan(const std::vector<MeshIn>& meshes, uint32_t primal, Plan&
   for (int32_t ii = 0; ii < P.n_inst; ++ii) {
     const MeshIn& m = meshes[ii];
     Instance& in = P.inst[ii];
-    const int32_t npe = m.npe;
+    in.npe = m.npe;
+    int64_t ko = in.ke_off;
     for (int32_t e = 0; e < m.n_elems; ++e) {
       const int64_t ge = in.elem_off + e;
-      P.ke_off[ge] = in.ke_off + (int64_t)e * (3 * npe) * (3 * npe);
+      const int32_t npe = npe_of(m, e);
+      P.ke_off[ge] = ko;
+      ko += (int64_t)(3 * npe) * (3 * npe);
       P.elem_npe[ge] = npe;
       P.elem_node_off[ge] = (int64_t)P.elem_nodes_flat.size();
       int32_t part = m.elem_part[e];
       if (part < 0 || part >= m.n_sub) return "elem_part out of range";
       for (int32_t a = 0; a < npe; ++a) {
-        int32_t nd = m.elem_nodes[(int64_t)e * npe + a];
+        int32_t nd = node_of(m, e, a);
         if (nd < 0 || nd >= m.n_nodes) return "elem_nodes out of range";
         P.elem_nodes_flat.push_back((int32_t)(in.node_off + nd));
       }
@@ -93,9 +111,9 @@ std::string build_plan(const std::vector<MeshIn>& meshes, uint32_t primal, Plan&
 
     // ------------------------------------------------ N(x): subdomains per node
     std::vector<std::pair<int32_t, int32_t>> ns;
-    ns.reserve((size_t)m.n_elems * npe);
+    ns.reserve(m.elem_nodes.size());
     for (int32_t e = 0; e < m.n_elems; ++e)
-      for (int32_t a = 0; a < npe; ++a) ns.emplace_back(m.elem_nodes[(int64_t)e * npe + a], m.elem_part[e]);
+      for (int32_t a = 0; a < npe_of(m, e); ++a) ns.emplace_back(node_of(m, e, a), m.elem_part[e]);
     std::sort(ns.begin(), ns.end());
     ns.erase(std::unique(ns.begin(), ns.end()), ns.end());
     std::vector<int32_t> nsp(m.n_nodes + 1, 0), nsl(ns.size());
@@ -124,7 +142,8 @@ std::string build_plan(const std::vector<MeshIn>& meshes, uint32_t primal, Plan&
     }
     UnionFind uf(m.n_nodes);
     for (int32_t e = 0; e < m.n_elems; ++e) {
-      const int32_t* en = &m.elem_nodes[(int64_t)e * npe];
+      const int32_t npe = npe_of(m, e);
+      const int32_t* en = m.elem_ptr.empty() ? &m.elem_nodes[(int64_t)e * npe] : &m.elem_nodes[m.elem_ptr[e]];
       for (int32_t a = 0; a < npe; ++a) {
         int32_t ka = key_id[en[a]];
         if (ka < 0) continue;
@@ -154,6 +173,7 @@ std::string build_plan(const std::vector<MeshIn>& meshes, uint32_t primal, Plan&
       int32_t nprime = deg + popcount32(m.node_tags.empty() ? 0u : m.node_tags[n0]);
       int32_t kind = (gn.size() == 1) ? kVertex : (nprime >= 3 ? kEdge : kFace);
       P.glob_kind.push_back(kind);
+      P.glob_node0.push_back((int32_t)(in.node_off + n0));
       if (kind == kVertex) P.n_vertices++;
       else if (kind == kEdge) P.n_edges++;
       else P.n_faces++;

@@ -19,8 +19,9 @@ enum GlobKind { kVertex = 1, kEdge = 2, kFace = 4 };
 struct MeshIn {
   int32_t n_nodes = 0;
   int32_t n_elems = 0;
-  int32_t npe = 0;         // 8 or 27
+  int32_t npe = 0;         // 8 or 27 (fixed-size elements)
   int32_t n_sub = 0;
+  std::vector<int32_t> elem_ptr;  // optional [n_elems+1]: variable-size elements (coarse levels)
   std::vector<int32_t> elem_nodes;
   std::vector<int32_t> elem_part;
   std::vector<uint32_t> node_tags;
@@ -64,6 +65,7 @@ struct Plan {
 
   // globs (global numbering across instances, sorted per instance by first node)
   std::vector<int32_t> glob_kind;
+  std::vector<int32_t> glob_node0;    // first (lowest) global node of each glob
   std::vector<int32_t> node_glob;     // [n_nodes] or -1
   std::vector<int32_t> coarse_glob, coarse_comp;   // [n_coarse]
   int64_t n_vertices = 0, n_edges = 0, n_faces = 0;

@@ -41,7 +41,7 @@ class mbddc_options(ctypes.Structure):
     _fields_ = [("primal", ctypes.c_uint32), ("levels", ctypes.c_int32), ("coarse_group", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("restart", ctypes.c_int32), ("rtol", ctypes.c_double),
                 ("max_it", ctypes.c_int32), ("symmetric_hint", ctypes.c_int32), ("tune_table", ctypes.c_char_p),
-                ("keep_coarse_matrix", ctypes.c_int32)]
+                ("keep_coarse_matrix", ctypes.c_int32), ("coarse_primal", ctypes.c_uint32)]
 
 
 class mbddc_info(ctypes.Structure):
@@ -54,7 +54,7 @@ class mbddc_info(ctypes.Structure):
 class mbddc_sizes(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in ("n_dofs", "n_free", "n_interface", "n_coarse", "n_sub",
                                                "n_instances", "n_vertices", "n_edges", "n_faces", "max_local",
-                                               "bsr_blocks")]
+                                               "bsr_blocks", "n_sub2", "n_coarse2")]
 
 
 class mbddc_kernel_stat(ctypes.Structure):

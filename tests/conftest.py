@@ -29,6 +29,16 @@ def problem(name: str):
         return W.neo_hookean_box(8, 4, 1, nrhs=2, amplitude=0.02, primal=3, name="tiny_nh")
     if name == "tiny_q2":          # Q2 on 4^3 elements, 2x2x2 subdomains of 2^3
         return W.linear_box(4, 2, 2, nrhs=1, primal=3, name="tiny_q2")
+    if name == "l3_nh":            # neo-Hookean on 12^3, 4x4x4 subdomains of 3^3: three-level cases
+        return W.neo_hookean_box(12, 3, 1, nrhs=2, amplitude=0.02, primal=3, name="l3_nh")
+    if name == "l3_ragged":        # 7x6x9 Q1 box, blocks of 2 -> 4x3x5 uneven subdomains, linear elastic
+        from paper_2208_06191_amd.workloads import Problem
+        mesh = W.box_mesh(7, 6, 9, 1)
+        part, nsub = W.block_partition(mesh, 2)
+        dirichlet = W.clamp_dofs(mesh, 1)
+        Ke = W.element_tangents(mesh, W.linear_elastic(1.0, 0.3))
+        rhs = W._loads(mesh, dirichlet, 1, 11)
+        return Problem("l3_ragged", mesh, part, nsub, dirichlet, Ke, rhs, 1, {})
     if name == "ragged":           # 6x5x7 Q1 box, blocks of 4 -> uneven subdomains
         from paper_2208_06191_amd.workloads import Problem
         mesh = W.box_mesh(6, 5, 7, 1)

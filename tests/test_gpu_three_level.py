@@ -1,0 +1,136 @@
+"""GPU parity of multilevel (three-level) BDDC against the FP64 oracle.
+
+The coarse problem S_PiPi is not factorised: one level-2 BDDC application
+replaces its solve (paper §3.2, last paragraph; §7 groups 8 fine subdomains).
+Checkpoints:
+* level-2 / level-3 sizes equal the oracle's (integer, exact)
+* the kept level-1 coarse matrix (the level-2 operator)   FP64 <= 1e-12
+* one preconditioner application                           FP64 <= 1e-12, mixed <= 1e-5
+* GMRES iterations                                         FP64: oracle +-1, mixed: <= oracle + 2
+* a single group (every fine subdomain in one level-2 subdomain) reproduces two-level BDDC
+"""
+import functools
+
+import numpy as np
+import pytest
+
+from oracle import bddc, gmres
+from paper_2208_06191_amd import mbddc
+from tests.conftest import problem
+
+pytestmark = pytest.mark.gpu
+
+TOL_APPLY = {mbddc.MBDDC_FP64: 1e-12, mbddc.MBDDC_MIXED: 1e-5}
+VEF = 7
+
+# (problem, fine primal, coarse group, level-2 primal)
+CASES = [("l3_nh", 3, 8, VEF), ("l3_nh", 1, 8, VEF), ("l3_ragged", 1, 5, VEF), ("l3_ragged", 3, 7, 3),
+         ("small_ve", 3, 3, VEF)]
+
+
+@functools.lru_cache(maxsize=None)
+def oracle3(name, primal, group, primal2):
+    P = problem(name)
+    dec = bddc.Decomposition(P.mesh.elem_nodes, P.mesh.n_nodes, P.elem_part, P.n_sub, P.dirichlet,
+                             P.mesh.node_tags, primal=primal)
+    return dec, bddc.BDDC(dec, P.mesh.elem_nodes, P.Ke, levels=3, coarse_group=group, level2_primal=primal2)
+
+
+def solver3(P, precision, primal, group, primal2, sym=0, levels=3):
+    s = mbddc.Solver(0)
+    o = mbddc.default_options(precision=precision, primal=primal, keep_coarse_matrix=1, symmetric_hint=sym,
+                              levels=levels, coarse_group=group, coarse_primal=primal2)
+    s.mbddc_setup_symbolic([mbddc.mesh_from_problem(P)], o)
+    s.mbddc_set_tangent(P.Ke)
+    try:
+        s.mbddc_factor()
+    except mbddc.MbddcError as e:
+        raise AssertionError(f"factor failed: {e}, subdomain {s.last_bad_subdomain()}") from e
+    return s
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+@pytest.mark.parametrize("name,primal,group,primal2", CASES)
+def test_level2_sizes(name, primal, group, primal2):
+    P = problem(name)
+    dec, B = oracle3(name, primal, group, primal2)
+    s = solver3(P, mbddc.MBDDC_FP64, primal, group, primal2)
+    z = s.sizes()
+    assert z.n_coarse == dec.n_coarse
+    assert z.n_sub2 == len(B.L2.spaces)
+    assert z.n_coarse2 == B.L2.n_coarse
+    s.close()
+
+
+@pytest.mark.parametrize("sym", [0, 1])
+@pytest.mark.parametrize("precision", [mbddc.MBDDC_FP64, mbddc.MBDDC_MIXED])
+@pytest.mark.parametrize("name,primal,group,primal2", CASES)
+def test_three_level_apply(name, primal, group, primal2, precision, sym):
+    P = problem(name)
+    dec, B = oracle3(name, primal, group, primal2)
+    s = solver3(P, precision, primal, group, primal2, sym)
+    Kc = s.mbddc_get_coarse_matrix(0, dec.n_coarse)
+    assert rel(Kc, B.Kc) <= 1e-12
+    rng = np.random.default_rng(3)
+    r = rng.standard_normal((2, P.n_dofs))
+    r[:, P.dirichlet] = 0.0
+    z = s.mbddc_apply(r)
+    errs = [rel(z[k][dec.free], B.apply(r[k][dec.free])) for k in range(2)]
+    clamped = np.setdiff1d(np.arange(P.n_dofs), dec.free)
+    print(f"{name} primal={primal} group={group} primal2={primal2} prec={precision} sym={sym}: "
+          f"apply {max(errs):.2e}")
+    assert max(errs) <= TOL_APPLY[precision]
+    assert np.abs(z[:, clamped]).max() == 0.0
+    s.close()
+
+
+@pytest.mark.parametrize("sym", [0, 1])
+@pytest.mark.parametrize("precision", [mbddc.MBDDC_FP64, mbddc.MBDDC_MIXED])
+@pytest.mark.parametrize("name,primal,group,primal2", CASES[:3])
+def test_three_level_solve(name, primal, group, primal2, precision, sym):
+    P = problem(name)
+    dec, B = oracle3(name, primal, group, primal2)
+    s = solver3(P, precision, primal, group, primal2, sym)
+    x, info = s.mbddc_solve(P.rhs)
+    its = []
+    for k in range(P.rhs.shape[0]):
+        b = P.rhs[k][dec.free]
+        ref = gmres.gmres(lambda v: B.A @ v, B.apply, b, 1e-8, 30, 1000)
+        its.append(ref.iterations)
+        xr = x[k][dec.free]
+        assert np.linalg.norm(b - B.A @ xr) / np.linalg.norm(b) <= 1e-8
+    print(f"{name} prec={precision} sym={sym}: its {info.iterations} (oracle {its})")
+    lo = max(its) - 1 if precision == mbddc.MBDDC_FP64 else 0
+    hi = max(its) + (1 if precision == mbddc.MBDDC_FP64 else 2)
+    assert lo <= info.iterations <= hi
+    s.close()
+
+
+@pytest.mark.parametrize("sym", [0, 1])
+def test_one_group_equals_two_level(sym):
+    """All fine subdomains in one level-2 subdomain: the level-2 problem is solved exactly,
+    so three-level BDDC is the two-level preconditioner (an oracle pin, here on the GPU)."""
+    P = problem("small_ve")
+    s2 = solver3(P, mbddc.MBDDC_FP64, 3, 8, VEF, sym, levels=2)
+    s3 = solver3(P, mbddc.MBDDC_FP64, 3, P.n_sub, VEF, sym, levels=3)
+    assert s3.sizes().n_sub2 == 1 and s3.sizes().n_coarse2 == 0
+    r = np.random.default_rng(5).standard_normal((2, P.n_dofs))
+    r[:, P.dirichlet] = 0.0
+    assert rel(s3.mbddc_apply(r), s2.mbddc_apply(r)) <= 1e-11
+    s2.close()
+    s3.close()
+
+
+def test_three_level_rejects_coarse_free_instance():
+    """One subdomain has no primal DOF: nothing to coarsen, the setup says so."""
+    P = problem("small")
+    m = mbddc._MeshArrays(P.mesh.coords, P.mesh.elem_nodes, P.mesh.elem_type, np.zeros_like(P.elem_part), 1,
+                          P.mesh.node_tags, P.dirichlet)
+    s = mbddc.Solver(0)
+    o = mbddc.default_options(levels=3)
+    with pytest.raises(mbddc.MbddcError):
+        s.mbddc_setup_symbolic([m], o)
+    s.close()
