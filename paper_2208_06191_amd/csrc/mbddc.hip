@@ -148,6 +148,9 @@ struct mbddc_ctx {
            *d_gemm_phi = nullptr, *d_gemm_stil = nullptr;
   GjDesc* d_gj_x = nullptr;
   GjDesc* d_gj_t = nullptr;
+  GemmDesc* d_csym_gd = nullptr;       // panel GEMM of the blocked coarse sweep, one per large instance
+  GemmItem* d_csym_items = nullptr;
+  std::vector<int64_t> csym_item_off;  // [coarse_large.size() + 1]
   double* d_rho = nullptr;
   ApplyItem *d_itA = nullptr, *d_itC = nullptr, *d_itE = nullptr, *d_itF = nullptr, *d_itH = nullptr;
   int32_t *d_chunk_inst = nullptr, *d_inst_chunk_off = nullptr;
@@ -598,6 +601,22 @@ int upload_plan(mbddc_ctx* c) {
     CHK(dalloc(c, &c->d_cDinv, 2 * cb * cb));
     CHK(dalloc(c, &c->d_cY, cb * ldmax));
     CHK(dalloc(c, &c->d_cCcol, ldmax * cb));
+    // panel products U = W Dinv of the symmetric sweep, n x kSymCB per instance
+    std::vector<GemmDesc> gds;
+    std::vector<GemmItem> items;
+    c->csym_item_off.assign(1, 0);
+    for (int32_t ii : c->coarse_large) {
+      GemmDesc gd{};
+      gd.M = c->inst_nc[ii]; gd.N = kSymCB; gd.K = kSymCB; gd.lda = kSymCB; gd.ldb = kSymCB; gd.ldc = kSymCB;
+      gd.ldci = kSymCB; gd.tiles_n = kSymCB / 64; gd.alpha = 1.0; gd.beta = 0.0;
+      const int32_t id = (int32_t)gds.size();
+      gds.push_back(gd);
+      for (int a = 0; a < (gd.M + 63) / 64; ++a)
+        for (int b = 0; b < gd.tiles_n; ++b) items.push_back({id, a, b, 0});
+      c->csym_item_off.push_back((int64_t)items.size());
+    }
+    CHK(upload(c, &c->d_csym_gd, gds));
+    CHK(upload(c, &c->d_csym_items, items));
   }
   CHK(dalloc(c, &c->d_amax, 1));
   HIPCHK(hipStreamSynchronize(c->stream));
@@ -786,16 +805,9 @@ int coarse_sweep_large(mbddc_ctx* c, int32_t ii) {
   const double thresh = std::max((double)n * 2.220446049250313e-16, 1e-12) * amax;
   double* Wg = c->d_cCcol;     // n x kSymCB
   double* Ug = c->d_cY;        // n x kSymCB
-  GemmDesc gd{};
-  gd.M = n; gd.N = kSymCB; gd.K = kSymCB; gd.lda = kSymCB; gd.ldb = kSymCB; gd.ldc = kSymCB; gd.ldci = kSymCB;
-  gd.tiles_n = kSymCB / 64; gd.oA = 0; gd.oB = 0; gd.oC = 0; gd.oCi = 0; gd.alpha = 1.0; gd.beta = 0.0;
-  std::vector<GemmItem> items;
-  for (int a = 0; a < (n + 63) / 64; ++a)
-    for (int b = 0; b < gd.tiles_n; ++b) items.push_back({0, a, b, 0});
-  GemmDesc* d_gd = nullptr;
-  GemmItem* d_items = nullptr;
-  CHK(upload(c, &d_gd, std::vector<GemmDesc>{gd}));
-  CHK(upload(c, &d_items, items));
+  const int64_t li = std::find(c->coarse_large.begin(), c->coarse_large.end(), ii) - c->coarse_large.begin();
+  const GemmItem* d_items = c->d_csym_items + c->csym_item_off[li];
+  const unsigned n_items = (unsigned)(c->csym_item_off[li + 1] - c->csym_item_off[li]);
   const unsigned nt = (unsigned)((n + 63) / 64);
   const unsigned ntiles = nt * (nt + 1) / 2;
   const unsigned nt2 = (unsigned)((n + kUpdTile - 1) / kUpdTile);
@@ -818,13 +830,13 @@ int coarse_sweep_large(mbddc_ctx* c, int32_t ii) {
       ProfScope ps(c, F_COARSE_PREP, 16.0 * n * kSymCB, 2.0 * n * (double)kSymCB * kSymCB);
       hipLaunchKernelGGL(k_csym_gather, dim3(gg), dim3(kBlock), 0, c->stream, A, n, ld, k0, Wg);
       if (kb > 0) HIPCHK(hipStreamWaitEvent(c->stream, c->ev_b, 0));     // Dinv of block kb (lookahead)
-      hipLaunchKernelGGL((k_gemm_batched<double>), dim3((unsigned)items.size()), dim3(kBlock), 0, c->stream, d_gd,
+      hipLaunchKernelGGL((k_gemm_batched<double>), dim3(n_items), dim3(kBlock), 0, c->stream, c->d_csym_gd,
                          d_items, Wg, Dk, Ug, Ug);
     }
     const bool ahead = kb + 1 < nb;
     if (ahead) {
       // update diagonal block kb+1 first, then invert it on the lookahead stream
-      hipLaunchKernelGGL(k_csym_update, dim3(3), dim3(kBlock), 0, c->stream, A, n, ld, k0, Ug, Wg, Dk, 1, kb + 1);
+      hipLaunchKernelGGL(k_csym_update<1>, dim3(3), dim3(kBlock), 0, c->stream, A, n, ld, k0, Ug, Wg, Dk, kb + 1);
       HIPCHK(hipEventRecord(c->ev_a, c->stream));
       HIPCHK(hipStreamWaitEvent(c->aux, c->ev_a, 0));
       hipLaunchKernelGGL(k_csym_diag, dim3(1), dim3(kBlock), 0, c->aux, A, n, ld, k0 + kSymCB, Dbuf[(kb + 1) & 1],
@@ -835,7 +847,7 @@ int coarse_sweep_large(mbddc_ctx* c, int32_t ii) {
       // algorithmic: lower-triangle read+write of A, flops 2 bw per lower entry
       const double lower = 0.5 * n * (double)(n + 1);
       ProfScope ps(c, F_COARSE_GEMM, 16.0 * lower, 2.0 * bw * lower);
-      hipLaunchKernelGGL(k_csym_update, dim3(ntiles2), dim3(kBlock), 0, c->stream, A, n, ld, k0, Ug, Wg, Dk, 0,
+      hipLaunchKernelGGL(k_csym_update<0>, dim3(ntiles2), dim3(kBlock), 0, c->stream, A, n, ld, k0, Ug, Wg, Dk,
                          ahead ? kb + 1 : -1);
     }
   }
@@ -847,8 +859,6 @@ int coarse_sweep_large(mbddc_ctx* c, int32_t ii) {
   int32_t st = 0;
   HIPCHK(hipMemcpyAsync(&st, c->d_status, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
-  dfree(c, d_gd);
-  dfree(c, d_items);
   if (st != 0) {
     c->last_bad = -1;
     return MBDDC_ERR_SINGULAR;
@@ -1555,6 +1565,8 @@ int mbddc_setup_symbolic_batch(mbddc_ctx* c, int n_inst, const mbddc_mesh* meshe
   c->d_active = c->d_mode = c->d_fin = nullptr;
   c->d_Kc_keep = nullptr;
   c->d_cDinv = c->d_cY = c->d_cCcol = nullptr;
+  c->d_csym_gd = nullptr;
+  c->d_csym_items = nullptr;
   c->d_l2_dof = c->d_l2_eidx = nullptr;
   c->opt = o;
   c->mixed = (o.precision != MBDDC_FP64);

@@ -138,14 +138,28 @@ def box_mesh(nx: int, ny: int, nz: int, order: int = 1, lengths=(1.0, 1.0, 1.0))
                 node_tags=tags, shape=(nx, ny, nz))
 
 
-def block_partition(mesh: Mesh, block) -> tuple[np.ndarray, int]:
-    """Element -> subdomain map for axis-aligned blocks of ``block`` elements per direction."""
+def block_partition(mesh: Mesh, block, cluster: int = 1) -> tuple[np.ndarray, int]:
+    """Element -> subdomain map for axis-aligned blocks of ``block`` elements per direction.
+
+    Subdomains are numbered lexicographically; with ``cluster`` > 1 they are numbered
+    cluster by cluster instead (clusters of cluster^3 neighbouring subdomains, each
+    lexicographic inside), so that consecutive groups of cluster^3 subdomain ids are
+    compact clusters (the grouping of fine subdomains into level-2 subdomains)."""
     nx, ny, nz = mesh.shape
     bx, by, bz = (block, block, block) if np.isscalar(block) else block
     sx, sy, sz = -(-nx // bx), -(-ny // by), -(-nz // bz)
     e = np.arange(nx * ny * nz)
     ex, ey, ez = e % nx, (e // nx) % ny, e // (nx * ny)
     part = (ex // bx) + sx * ((ey // by) + sy * (ez // bz))
+    if cluster > 1:
+        s = np.arange(sx * sy * sz)
+        i, j, k = s % sx, (s // sx) % sy, s // (sx * sy)
+        c = cluster
+        cx, cy = -(-sx // c), -(-sy // c)
+        key = ((i // c) + cx * ((j // c) + cy * (k // c))) * c ** 3 + (i % c) + c * ((j % c) + c * (k % c))
+        rank = np.empty_like(s)
+        rank[np.argsort(key, kind="stable")] = s
+        part = rank[part]
     return part.astype(np.int32), sx * sy * sz
 
 
@@ -421,10 +435,11 @@ def linear_box(n: int = 8, block: int = 4, order: int = 1, nrhs: int = 1, E: flo
 
 def neo_hookean_box(n: int = 32, block: int = 4, order: int = 1, nrhs: int = 4, mu: float = 1.0,
                     kappa: float = 50.0, amplitude: float = 0.05, field_seed: int = 0,
-                    rhs_seed: int = 1, primal: int = 3, name: str = "neo_hookean_box") -> Problem:
+                    rhs_seed: int = 1, primal: int = 3, name: str = "neo_hookean_box",
+                    cluster: int = 1) -> Problem:
     """Compressible neo-Hookean tangent linearised at a seeded isochoric 8-mode field."""
     mesh = box_mesh(n, n, n, order)
-    part, nsub = block_partition(mesh, block)
+    part, nsub = block_partition(mesh, block, cluster)
     dirichlet = clamp_dofs(mesh, 1)
     u = isochoric_field(mesh.coords, field_seed, amplitude)
     Ke = element_tangents(mesh, neo_hookean(mu, kappa), u)
