@@ -150,6 +150,13 @@ int mbddc_setup_symbolic_batch(mbddc_ctx* ctx, int n_inst, const mbddc_mesh* mes
 /* Device bytes the handle will hold after factor (exact; call after setup). */
 int mbddc_footprint(const mbddc_ctx* ctx, size_t* device_bytes);
 
+/* Host-only estimate of the device bytes a handle set up with these meshes and
+ * options holds after factor and a solve of up to 4 right-hand sides (the
+ * admission test of the serving loop; no device is touched). Same argument
+ * rules and errors as mbddc_setup_symbolic_batch. */
+int mbddc_estimate_footprint(int n_inst, const mbddc_mesh* meshes, const mbddc_options* opt,
+                             size_t* device_bytes);
+
 int mbddc_get_sizes(const mbddc_ctx* ctx, mbddc_sizes* out);
 
 /* Element tangents K_e, [n_elems][3npe][3npe] row-major FP64 in element-local
@@ -163,8 +170,9 @@ int mbddc_set_tangent(mbddc_ctx* ctx, const double* elem_K, int on_device);
  * levels = 3 S_PiPi is not factorised: the level-2 BDDC setup on the coarse
  * problem runs instead (its local problems, its coarse basis and the FP64
  * factorisation of the level-3 coarse matrix).
- * Returns MBDDC_ERR_SINGULAR on a zero pivot (mbddc_last_bad_subdomain; -1 for
- * the coarse problem, and for any level-2 or level-3 problem). */
+ * Returns MBDDC_ERR_SINGULAR on a zero pivot (mbddc_last_bad_subdomain: the
+ * subdomain, -1 for the coarse problem; with levels = 3, -2 - j for level-2
+ * subdomain j and -2 - n_sub2 for the level-3 coarse problem). */
 int mbddc_factor(mbddc_ctx* ctx);
 
 /* Right-preconditioned GMRES(restart) for `nrhs` right-hand sides (each
@@ -221,10 +229,63 @@ int mbddc_set_profiling(mbddc_ctx* ctx, uint32_t family_mask);
 const char* mbddc_profile_family_name(int family);
 int mbddc_get_profile(mbddc_ctx* ctx, mbddc_kernel_stat* out, int max_entries, int* n_entries);
 
-/* Subdomain of the last MBDDC_ERR_SINGULAR (-1: coarse problem). */
+/* Subdomain of the last MBDDC_ERR_SINGULAR (-1: coarse problem; see mbddc_factor). */
 int mbddc_last_bad_subdomain(const mbddc_ctx* ctx);
 
 int mbddc_destroy(mbddc_ctx* ctx);
+
+/* ---- Serving: a request loop over independent tangent solves -------------
+ * Not a paper step: the production pattern around it (Newton iterations of many
+ * independent problems, §2: one tangent system per Newton step). A server owns
+ * `max_active` worker threads, each with its own HIP stream (default priority)
+ * on `hip_device`. Requests are admitted in arrival order when a worker is free
+ * and the sum of the estimated footprints (mbddc_estimate_footprint) of the
+ * active requests stays within `hbm_budget` bytes; requests that arrive while
+ * others run are admitted as slots and memory free up, and the kernels of all
+ * active requests run concurrently on the device. A request runs its Newton
+ * steps on one handle: step k sets the tangent K_k, factors it (every step, or
+ * only at step 0 when `lagged`, keeping the factors resident as a lagged
+ * preconditioner) and solves its right-hand sides with GMRES. Each request's
+ * arithmetic is the same alone and in any mix (deterministic kernels, private
+ * handle and stream). */
+typedef struct mbddc_server mbddc_server;
+
+typedef struct {
+  mbddc_mesh mesh;               /* the mesh arrays are copied at submit */
+  mbddc_options opt;
+  int32_t n_steps;               /* Newton steps, 1..16 */
+  int32_t nrhs;                  /* right-hand sides per step, 1..8 */
+  int32_t lagged;                /* 1: factor at step 0 only; 0: factor at every step */
+  const double* elem_K;          /* [n_steps][n_elems][3npe][3npe] host; read while the request runs */
+  const double* rhs;             /* [n_steps][nrhs][n_dofs] host; read while the request runs */
+  double* x;                     /* [n_steps][nrhs][n_dofs] host output, written while the request runs */
+} mbddc_request;
+
+typedef struct {
+  int32_t status;                /* MBDDC_OK or the first error of the request */
+  int32_t n_steps;
+  int32_t iterations[16];        /* GMRES iterations per step (max over its right-hand sides) */
+  double rel_res_true;           /* max over steps and right-hand sides (FP64 true residual) */
+  double t_submit_ms, t_admit_ms, t_done_ms;   /* server clock (ms since mbddc_server_create) */
+  size_t footprint;              /* admitted device bytes (estimate) */
+} mbddc_request_result;
+
+/* max_active 1..64 workers; hbm_budget > 0. */
+int mbddc_server_create(mbddc_server** out, int hip_device, size_t hbm_budget, int max_active);
+
+/* Queues a request; returns immediately with its ticket (>= 0). The caller keeps
+ * elem_K, rhs and x alive until mbddc_server_wait returns for the ticket.
+ * MBDDC_ERR_OOM if its estimated footprint exceeds the whole budget. */
+int mbddc_server_submit(mbddc_server* srv, const mbddc_request* req, int64_t* ticket);
+
+/* Blocks until the request is done and returns its result (once per ticket). */
+int mbddc_server_wait(mbddc_server* srv, int64_t ticket, mbddc_request_result* res);
+
+/* Current queue length, active requests and admitted bytes (any pointer may be NULL). */
+int mbddc_server_state(mbddc_server* srv, int32_t* queued, int32_t* active, size_t* admitted_bytes);
+
+/* Finishes every queued and active request, then frees the server. */
+int mbddc_server_destroy(mbddc_server* srv);
 
 const char* mbddc_strerror(int status);
 

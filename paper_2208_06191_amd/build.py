@@ -24,10 +24,14 @@ def build(verbose: bool = True) -> str:
     inc = ["-I", os.path.join(ROOT, "include"), "-I", CSRC]
     plan_o = os.path.join(bdir, "plan.o")
     _run(["g++", "-O2", "-std=c++17", "-fPIC", "-Wall", "-c", os.path.join(CSRC, "plan.cpp"), "-o", plan_o] + inc)
+    rocm = os.environ.get("ROCM_PATH", "/opt/rocm")
+    srv_o = os.path.join(bdir, "server.o")
+    _run(["g++", "-O2", "-std=c++17", "-fPIC", "-Wall", "-pthread", "-D__HIP_PLATFORM_AMD__", "-I",
+          os.path.join(rocm, "include"), "-c", os.path.join(CSRC, "server.cpp"), "-o", srv_o] + inc)
     dev_o = os.path.join(bdir, "mbddc.o")
     _run([hipcc] + HIP_FLAGS + inc + ["-c", os.path.join(CSRC, "mbddc.hip"), "-o", dev_o])
     tmp = LIB + ".tmp"
-    _run([hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", dev_o, plan_o, "-o", tmp])
+    _run([hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-pthread", dev_o, plan_o, srv_o, "-o", tmp])
     os.replace(tmp, LIB)
     return LIB
 

@@ -18,6 +18,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -630,7 +631,7 @@ int upload_plan(mbddc_ctx* c) {
 // are the fine subdomains (nodes: their primal globs, ascending), fine
 // subdomain i belongs to level-2 subdomain i / coarse_group, and a level-2
 // node carries the boundary tags of its glob's first node.
-int build_level2(mbddc_ctx* c, const std::vector<MeshIn>& fine) {
+int build_level2_host(mbddc_ctx* c, const std::vector<MeshIn>& fine) {
   const Plan& P = c->plan;
   const int32_t group = c->opt.coarse_group;
   std::vector<MeshIn> m2(P.n_inst);
@@ -699,7 +700,11 @@ int build_level2(mbddc_ctx* c, const std::vector<MeshIn>& fine) {
   ch->fact32 = false;
   ch->sym = c->sym;
   if (!build_plan(m2, ch->opt.primal, ch->plan).empty()) return MBDDC_ERR_ARG;
-  CHK(build_layout(ch));
+  return build_layout(ch);
+}
+
+int upload_level2(mbddc_ctx* c) {
+  mbddc_ctx* ch = c->child;
   CHK(upload_plan(ch));
   HIPCHK(hipMemsetAsync(ch->d_Ke, 0, ch->plan.ke_total * sizeof(double), c->stream));
   CHK(upload(c, &c->d_l2_dof, c->l2_dof));
@@ -707,6 +712,34 @@ int build_level2(mbddc_ctx* c, const std::vector<MeshIn>& fine) {
   HIPCHK(hipStreamSynchronize(c->stream));
   ch->state = 2;
   return MBDDC_OK;
+}
+
+// Device bytes that a handle set up for `c`'s plan holds after factorisation and one
+// solve with 4 right-hand sides (host-side estimate for admission control).
+double device_bytes_estimate(const mbddc_ctx* c, bool krylov) {
+  const Plan& P = c->plan;
+  const double es = (double)elem_size(c->mixed), ef = (double)elem_size(c->fact32);
+  const double R = 4.0, J = c->opt.restart + 1;
+  double b = 8.0 * P.ke_total + 72.0 * c->nblocks + ef * c->w_elems + es * c->op_elems + 8.0 * c->kcl_elems;
+  b += 8.0 * (c->opt.levels == 3 ? 0 : c->kc_elems) + (c->opt.keep_coarse_matrix ? 8.0 * c->kc_elems : 0.0);
+  b += 4.0 * c->piv_elems;
+  b += 4.0 * (P.sub_dofs.size() + P.sub_elems.size() + 2 * P.elem_npe.size() + P.elem_ldof.size());
+  b += 8.0 * (P.ke_off.size() + P.elem_ldof_off.size() + P.cons_w.size() + P.slot_w.size() + P.bsr_contrib.size());
+  b += 4.0 * (P.cons_idx.size() + P.cons_ptr.size() + 2 * P.slot_dof.size() + P.ifx_slots.size() + P.ifx_ptr.size());
+  b += 4.0 * (2 * P.cslot_coarse.size() + P.coarse_slots.size() + P.coarse_ptr.size() + 2 * P.n_coarse);
+  b += 4.0 * (P.bsr_rowptr.size() + 3 * P.bsr_col.size() + P.bsr_cptr.size()) + 5.0 * P.n_dofs;
+  b += (double)sizeof(SubDev) * P.n_sub + 64.0 * (c->gj_kii.size() + c->gj_p.size() + c->gj_x.size());
+  b += 48.0 * (c->gemm_desc.size()) + 16.0 * (c->gemm_items_gh.size() + c->gemm_items_s.size() +
+       c->gemm_items_ssym.size() + c->gemm_items_phi.size() + c->gemm_items_stil.size());
+  b += 16.0 * (c->itA.size() + c->itC.size() + c->itE.size() + c->itF.size() + c->itH.size());
+  if (!c->coarse_large.empty()) {
+    const double cb = std::max(kCoarseBlock, kSymCB), ld = round_up(c->coarse_max_nc, 4);
+    b += 8.0 * (2 * cb * cb + 2 * cb * ld);
+  }
+  b += 8.0 * R * (2.0 * P.n_slots + std::max<int64_t>(P.n_cslots, 1) + c->nchunk_max * std::max<int64_t>(P.n_coarse, 1));
+  b += 8.0 * R * P.n_dofs * (krylov ? (3 + 2 * J + 4) : 3);
+  if (c->child) b += device_bytes_estimate(c->child, false) + 8.0 * (P.n_coarse + P.n_cslots);
+  return 1.02 * b + (1 << 20);
 }
 
 int ensure_apply_buffers(mbddc_ctx* c, int R) {
@@ -1066,8 +1099,8 @@ int factor_impl(mbddc_ctx* c) {
       ch->last_bad = 0;
       st = factor_impl<double, double>(ch);
     }
-    if (st) {
-      c->last_bad = -1;
+    if (st) {   // level-2 subdomain j -> -2 - j; level-3 coarse problem -> -2 - n_sub2
+      c->last_bad = ch->last_bad >= 0 ? -2 - ch->last_bad : -2 - (int)ch->plan.n_sub;
       return st;
     }
     ch->state = 3;
@@ -1118,16 +1151,18 @@ int apply_impl(mbddc_ctx* c, const double* r, double* z) {
   a.inst_kc_ld = c->d_inst_kc_ld; a.inst_coarse_off = c->d_inst_coarse_off; a.inst_nc = c->d_inst_nc;
   a.r = r; a.z = z; a.tb = c->d_tb; a.wb = c->d_wb; a.cc = c->d_cc; a.ep = c->d_ep; a.n_coarse = P.n_coarse;
   const size_t lds_local = (size_t)(4 * 256 * R + (size_t)c->max_cols * R) * sizeof(double);
-  static bool attr_set = false;
-  if (!attr_set) {
-    size_t mx = 160 * 1024;
-    CHK(set_lds(k_apply_local<To, R, 0>, mx));
-    CHK(set_lds(k_apply_local<To, R, 1>, mx));
-    CHK(set_lds(k_apply_local<To, R, 3>, mx));
-    CHK(set_lds(k_apply_local<To, R, 4>, mx));
-    CHK(set_lds(k_apply_coarse<To, R>, mx));
-    attr_set = true;
-  }
+  static std::once_flag attr_once;   // one attribute setting per instantiation, thread-safe
+  static int attr_st = MBDDC_OK;
+  std::call_once(attr_once, [] {
+    const size_t mx = 160 * 1024;
+    int st = set_lds(k_apply_local<To, R, 0>, mx);
+    if (!st) st = set_lds(k_apply_local<To, R, 1>, mx);
+    if (!st) st = set_lds(k_apply_local<To, R, 3>, mx);
+    if (!st) st = set_lds(k_apply_local<To, R, 4>, mx);
+    if (!st) st = set_lds(k_apply_coarse<To, R>, mx);
+    attr_st = st;
+  });
+  CHK(attr_st);
   if (lds_local > 160 * 1024) return MBDDC_ERR_UNSUPPORTED;
   {
     ProfScope ps(c, F_APPLY_A, c->op_bytes[F_APPLY_A] + 8.0 * R * c->vec_words[F_APPLY_A], 2.0 * R * c->fam_flops[F_APPLY_A]);
@@ -1527,17 +1562,19 @@ int mbddc_destroy(mbddc_ctx* c) {
   return MBDDC_OK;
 }
 
-int mbddc_setup_symbolic_batch(mbddc_ctx* c, int n_inst, const mbddc_mesh* meshes, const mbddc_options* opt) {
-  if (!c || n_inst <= 0 || !meshes) return MBDDC_ERR_ARG;
-  if (hipSetDevice(c->device) != hipSuccess) return MBDDC_ERR_DEVICE;
-  mbddc_options o;
+}  // extern "C"
+
+namespace {
+int parse_meshes(int n_inst, const mbddc_mesh* meshes, const mbddc_options* opt, mbddc_options& o,
+                 std::vector<MeshIn>& ms) {
+  if (n_inst <= 0 || !meshes) return MBDDC_ERR_ARG;
   if (opt) o = *opt;
   else mbddc_default_options(&o);
   if ((o.levels != 2 && o.levels != 3) || o.coarse_group < 1 || (o.coarse_primal & ~7u) || o.restart < 1 || o.restart > 63 || !(o.rtol > 0.0) || o.max_it < 1 ||
       (o.precision != MBDDC_FP64 && o.precision != MBDDC_MIXED && o.precision != MBDDC_MIXED_F32FACT) ||
       (o.primal & ~7u))
     return MBDDC_ERR_ARG;
-  std::vector<MeshIn> ms(n_inst);
+  ms.assign(n_inst, MeshIn());
   for (int i = 0; i < n_inst; ++i) {
     const mbddc_mesh& m = meshes[i];
     if (m.n_nodes <= 0 || m.n_elems <= 0 || m.n_sub <= 0 || !m.elem_nodes || !m.elem_part ||
@@ -1552,6 +1589,47 @@ int mbddc_setup_symbolic_batch(mbddc_ctx* c, int n_inst, const mbddc_mesh* meshe
     if (m.node_tags) mi.node_tags.assign(m.node_tags, m.node_tags + m.n_nodes);
     if (m.n_dirichlet > 0) mi.dirichlet.assign(m.dirichlet_dofs, m.dirichlet_dofs + m.n_dirichlet);
   }
+  return MBDDC_OK;
+}
+
+// Host part of the symbolic setup: plan, layout and (three levels) the level-2 plan.
+int prepare_host(mbddc_ctx* c, const mbddc_options& o, const std::vector<MeshIn>& ms) {
+  c->opt = o;
+  c->mixed = (o.precision != MBDDC_FP64);
+  c->fact32 = (o.precision == MBDDC_MIXED_F32FACT);
+  c->sym = (o.symmetric_hint != 0);
+  std::string err = build_plan(ms, o.primal, c->plan);
+  if (!err.empty()) return MBDDC_ERR_ARG;
+  CHK(build_layout(c));
+  if (o.levels == 3) CHK(build_level2_host(c, ms));
+  return MBDDC_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int mbddc_estimate_footprint(int n_inst, const mbddc_mesh* meshes, const mbddc_options* opt, size_t* device_bytes) {
+  if (!device_bytes) return MBDDC_ERR_ARG;
+  mbddc_options o;
+  std::vector<MeshIn> ms;
+  int st = parse_meshes(n_inst, meshes, opt, o, ms);
+  if (st) return st;
+  mbddc_ctx tmp;   // host only: no device call is made on it
+  st = prepare_host(&tmp, o, ms);
+  if (!st) *device_bytes = (size_t)device_bytes_estimate(&tmp, true);
+  if (tmp.child) {
+    delete tmp.child;
+    tmp.child = nullptr;
+  }
+  return st;
+}
+
+int mbddc_setup_symbolic_batch(mbddc_ctx* c, int n_inst, const mbddc_mesh* meshes, const mbddc_options* opt) {
+  if (!c || n_inst <= 0 || !meshes) return MBDDC_ERR_ARG;
+  if (hipSetDevice(c->device) != hipSuccess) return MBDDC_ERR_DEVICE;
+  mbddc_options o;
+  std::vector<MeshIn> ms;
+  CHK(parse_meshes(n_inst, meshes, opt, o, ms));
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   free_all(c);
   c->subs.clear();
@@ -1568,17 +1646,10 @@ int mbddc_setup_symbolic_batch(mbddc_ctx* c, int n_inst, const mbddc_mesh* meshe
   c->d_csym_gd = nullptr;
   c->d_csym_items = nullptr;
   c->d_l2_dof = c->d_l2_eidx = nullptr;
-  c->opt = o;
-  c->mixed = (o.precision != MBDDC_FP64);
-  c->fact32 = (o.precision == MBDDC_MIXED_F32FACT);
-  c->sym = (o.symmetric_hint != 0);
   c->state = 0;
-  std::string err = build_plan(ms, o.primal, c->plan);
-  if (!err.empty()) return MBDDC_ERR_ARG;
-  int st = build_layout(c);
-  if (st) return st;
-  st = upload_plan(c);
-  if (!st && o.levels == 3) st = build_level2(c, ms);
+  int st = prepare_host(c, o, ms);
+  if (!st) st = upload_plan(c);
+  if (!st && c->child) st = upload_level2(c);
   if (st) {
     free_all(c);
     return st;
@@ -1597,14 +1668,20 @@ int mbddc_footprint(const mbddc_ctx* c, size_t* device_bytes) {
   const Plan& P = c->plan;
   const size_t es = elem_size(c->mixed);
   const int R = 4, J = c->opt.restart + 1;
+  // per-call buffers that a solve with 4 right-hand sides allocates, unless already held
   size_t extra = 0;
-  extra += (size_t)P.n_slots * R * 8 * 2 + (size_t)std::max<int64_t>(P.n_cslots, 1) * R * 8;
-  extra += (size_t)c->nchunk_max * std::max<int64_t>(P.n_coarse, 1) * R * 8;
-  extra += (size_t)P.n_dofs * R * 8 * (3 + 2 * J + 4);
+  if (c->R_alloc < R) {
+    extra += (size_t)P.n_slots * R * 8 * 2 + (size_t)std::max<int64_t>(P.n_cslots, 1) * R * 8;
+    extra += (size_t)c->nchunk_max * std::max<int64_t>(P.n_coarse, 1) * R * 8 + (size_t)P.n_dofs * R * 8 * 3;
+  }
+  if (c->R_kry < R || c->restart_kry < c->opt.restart) extra += (size_t)P.n_dofs * R * 8 * (2 * J + 4);
   if (const mbddc_ctx* ch = c->child) {   // level-2 operators and its apply buffers
     const Plan& Q = ch->plan;
-    extra += ch->bytes + (size_t)Q.n_slots * R * 8 * 2 + (size_t)std::max<int64_t>(Q.n_cslots, 1) * R * 8;
-    extra += (size_t)ch->nchunk_max * std::max<int64_t>(Q.n_coarse, 1) * R * 8 + (size_t)Q.n_dofs * R * 8 * 3;
+    extra += ch->bytes;
+    if (ch->R_alloc < R) {
+      extra += (size_t)Q.n_slots * R * 8 * 2 + (size_t)std::max<int64_t>(Q.n_cslots, 1) * R * 8;
+      extra += (size_t)ch->nchunk_max * std::max<int64_t>(Q.n_coarse, 1) * R * 8 + (size_t)Q.n_dofs * R * 8 * 3;
+    }
   }
   *device_bytes = c->bytes + extra;
   return MBDDC_OK;

@@ -62,6 +62,17 @@ class mbddc_kernel_stat(ctypes.Structure):
                 ("bytes", ctypes.c_double), ("flops", ctypes.c_double)]
 
 
+class mbddc_request(ctypes.Structure):
+    _fields_ = [("mesh", mbddc_mesh), ("opt", mbddc_options), ("n_steps", ctypes.c_int32), ("nrhs", ctypes.c_int32),
+                ("lagged", ctypes.c_int32), ("elem_K", _f64p), ("rhs", _f64p), ("x", _f64p)]
+
+
+class mbddc_request_result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("n_steps", ctypes.c_int32), ("iterations", ctypes.c_int32 * 16),
+                ("rel_res_true", ctypes.c_double), ("t_submit_ms", ctypes.c_double), ("t_admit_ms", ctypes.c_double),
+                ("t_done_ms", ctypes.c_double), ("footprint", ctypes.c_size_t)]
+
+
 _lib = None
 
 # (name, argtypes) for every entry point of include/mbddc.h
@@ -72,6 +83,8 @@ _SIGNATURES = {
     "mbddc_setup_symbolic_batch": [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(mbddc_mesh),
                                    ctypes.POINTER(mbddc_options)],
     "mbddc_footprint": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t)],
+    "mbddc_estimate_footprint": [ctypes.c_int, ctypes.POINTER(mbddc_mesh), ctypes.POINTER(mbddc_options),
+                                 ctypes.POINTER(ctypes.c_size_t)],
     "mbddc_get_sizes": [ctypes.c_void_p, ctypes.POINTER(mbddc_sizes)],
     "mbddc_set_tangent": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int],
     "mbddc_factor": [ctypes.c_void_p],
@@ -91,6 +104,12 @@ _SIGNATURES = {
                           ctypes.POINTER(ctypes.c_int)],
     "mbddc_destroy": [ctypes.c_void_p],
     "mbddc_strerror": [ctypes.c_int],
+    "mbddc_server_create": [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int, ctypes.c_size_t, ctypes.c_int],
+    "mbddc_server_submit": [ctypes.c_void_p, ctypes.POINTER(mbddc_request), ctypes.POINTER(ctypes.c_int64)],
+    "mbddc_server_wait": [ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(mbddc_request_result)],
+    "mbddc_server_state": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                           ctypes.POINTER(ctypes.c_size_t)],
+    "mbddc_server_destroy": [ctypes.c_void_p],
 }
 
 
@@ -190,6 +209,64 @@ def mbddc_inspect_symbolic(mesh: _MeshArrays, primal: int):
 
 def _dev_ptr(t):
     return ctypes.c_void_p(t.data_ptr())
+
+
+def mbddc_estimate_footprint(meshes: Sequence[_MeshArrays], options: Optional[mbddc_options] = None) -> int:
+    """Host-only estimate of the device bytes of a handle for these meshes (no device needed)."""
+    arr = (mbddc_mesh * len(meshes))(*[m.mesh for m in meshes])
+    o = options if options is not None else default_options()
+    b = ctypes.c_size_t()
+    _check(lib().mbddc_estimate_footprint(len(meshes), arr, ctypes.byref(o), ctypes.byref(b)),
+           "mbddc_estimate_footprint")
+    return b.value
+
+
+class Server:
+    """Serving loop: requests of Newton tangent solves, admitted by footprint, run concurrently."""
+
+    def __init__(self, device: int = 0, hbm_budget: int = 64 << 30, max_active: int = 4):
+        self._s = ctypes.c_void_p()
+        _check(lib().mbddc_server_create(ctypes.byref(self._s), device, int(hbm_budget), max_active),
+               "mbddc_server_create")
+        self._keep = {}
+
+    def submit(self, mesh: _MeshArrays, options: mbddc_options, elem_K_steps: np.ndarray, rhs_steps: np.ndarray,
+               lagged: bool = True) -> int:
+        """elem_K_steps [n_steps, n_elems, 3npe, 3npe]; rhs_steps [n_steps, nrhs, n_dofs]. Returns a ticket."""
+        K = np.ascontiguousarray(elem_K_steps, dtype=np.float64)
+        b = np.ascontiguousarray(rhs_steps, dtype=np.float64)
+        x = np.zeros_like(b)
+        q = mbddc_request(mesh.mesh, options, K.shape[0], b.shape[1], 1 if lagged else 0,
+                          _ptr(K, ctypes.c_double), _ptr(b, ctypes.c_double), _ptr(x, ctypes.c_double))
+        t = ctypes.c_int64()
+        _check(lib().mbddc_server_submit(self._s, ctypes.byref(q), ctypes.byref(t)), "mbddc_server_submit")
+        self._keep[t.value] = (mesh, K, b, x)
+        return t.value
+
+    def wait(self, ticket: int):
+        """(result, x [n_steps, nrhs, n_dofs]) of a submitted request."""
+        r = mbddc_request_result()
+        _check(lib().mbddc_server_wait(self._s, ticket, ctypes.byref(r)), "mbddc_server_wait")
+        _, _, _, x = self._keep.pop(ticket)
+        return r, x
+
+    def state(self):
+        q, a, b = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_size_t()
+        _check(lib().mbddc_server_state(self._s, ctypes.byref(q), ctypes.byref(a), ctypes.byref(b)),
+               "mbddc_server_state")
+        return q.value, a.value, b.value
+
+    def close(self):
+        if self._s:
+            lib().mbddc_server_destroy(self._s)
+            self._s = ctypes.c_void_p()
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Solver:

@@ -449,6 +449,13 @@ def neo_hookean_box(n: int = 32, block: int = 4, order: int = 1, nrhs: int = 4, 
                     "order": order, "amplitude": amplitude, "field_seed": field_seed})
 
 
+def newton_tangents(mesh: Mesh, material, u0: np.ndarray, du: np.ndarray, n_steps: int) -> np.ndarray:
+    """Element tangents of n_steps Newton iterates u_k = u0 + (k / n_steps) du, k = 0..n_steps-1
+    ([n_steps, n_el, 3npe, 3npe]): the sequence of tangent systems one request of the serving
+    loop solves, its factors computed at u0 and reused (lagged) for the later steps."""
+    return np.stack([element_tangents(mesh, material, u0 + (k / n_steps) * du) for k in range(n_steps)])
+
+
 def config_small() -> Problem:
     """8^3 Q1 unit cube, linear elasticity E=1 nu=0.3, 2x2x2 subdomains of 4^3, primal V."""
     return linear_box(8, 4, 1, nrhs=1, primal=1, name="linear_8cube_2x2x2_V")

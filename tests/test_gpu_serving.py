@@ -1,0 +1,158 @@
+"""Serving loop: admission by footprint, concurrent requests, lagged factors across Newton steps.
+
+Each request solves a sequence of Newton tangents (workloads.newton_tangents) on its own handle
+and stream; the results are checked against the FP64 oracle's assembled operator of each step
+(true residual) and against the same request run alone (bitwise: the kernels are deterministic
+and a request's arithmetic does not depend on what else runs on the device).
+"""
+import functools
+
+import numpy as np
+import pytest
+
+from oracle import fem
+from paper_2208_06191_amd import mbddc
+from paper_2208_06191_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@functools.lru_cache(maxsize=None)
+def request_case(kind: str, n: int, steps: int = 3, seed: int = 0):
+    """(mesh arrays, options, Ke_steps, rhs_steps, elem_nodes, n_dofs, free) of one request."""
+    if kind == "nh":
+        mesh = W.box_mesh(n, n, n, 1)
+        part, nsub = W.block_partition(mesh, 4 if n % 4 == 0 else 3)
+        mat = W.neo_hookean(1.0 + 0.25 * seed, 50.0)
+        primal, order = 3, 1
+    elif kind == "lin":
+        mesh = W.box_mesh(n, n, n, 1)
+        part, nsub = W.block_partition(mesh, 4 if n % 4 == 0 else 3)
+        mat = W.linear_elastic(1.0, 0.3)
+        primal, order = 1, 1
+    else:   # "q2"
+        mesh = W.box_mesh(n, n, n, 2)
+        part, nsub = W.block_partition(mesh, 2)
+        mat = W.neo_hookean(1.0, 50.0)
+        primal, order = 3, 2
+    dirichlet = W.clamp_dofs(mesh, 1)
+    u0 = W.isochoric_field(mesh.coords, seed, 0.02)
+    du = W.isochoric_field(mesh.coords, seed + 50, 0.01)
+    Ks = W.newton_tangents(mesh, mat, u0, du, steps)
+    rhs = np.stack([W._loads(mesh, dirichlet, 2, 10 * seed + k) for k in range(steps)])
+    m = mbddc._MeshArrays(mesh.coords, mesh.elem_nodes, mesh.elem_type, part, nsub, mesh.node_tags, dirichlet)
+    free = np.setdiff1d(np.arange(3 * mesh.n_nodes), dirichlet)
+    return m, primal, Ks, rhs, mesh.elem_nodes, 3 * mesh.n_nodes, free
+
+
+def options(primal, levels=2):
+    return mbddc.default_options(primal=primal, symmetric_hint=1, levels=levels)
+
+
+def check_residuals(case, x, tol=1e-8):
+    m, primal, Ks, rhs, en, n, free = case
+    for k in range(Ks.shape[0]):
+        A = fem.reduce_to_free(fem.assemble(en, Ks[k], n), free)
+        for j in range(rhs.shape[1]):
+            b = rhs[k, j][free]
+            assert np.linalg.norm(b - A @ x[k, j][free]) / np.linalg.norm(b) <= tol
+            assert np.abs(np.delete(x[k, j], free)).max() == 0.0
+
+
+def direct(case, lagged=True, levels=2):
+    """The same Newton sequence on a plain handle."""
+    m, primal, Ks, rhs, en, n, free = case
+    s = mbddc.Solver(0)
+    s.mbddc_setup_symbolic([m], options(primal, levels))
+    xs, its = [], []
+    for k in range(Ks.shape[0]):
+        s.mbddc_set_tangent(Ks[k])
+        if k == 0 or not lagged:
+            s.mbddc_factor()
+        x, info = s.mbddc_solve(rhs[k])
+        xs.append(x)
+        its.append(info.iterations)
+    s.close()
+    return np.stack(xs), its
+
+
+@pytest.mark.parametrize("lagged", [True, False])
+def test_server_request_equals_direct_handle(lagged):
+    case = request_case("nh", 8)
+    xd, itd = direct(case, lagged)
+    srv = mbddc.Server(0, 8 << 30, 2)
+    m, primal, Ks, rhs, *_ = case
+    t = srv.submit(m, options(primal), Ks, rhs, lagged=lagged)
+    r, x = srv.wait(t)
+    srv.close()
+    assert r.status == 0 and r.n_steps == Ks.shape[0]
+    assert list(r.iterations[:r.n_steps]) == itd
+    assert np.array_equal(x, xd)
+    check_residuals(case, x)
+    if lagged:   # the lagged preconditioner needs at least as many iterations later on
+        assert min(itd[1:]) >= itd[0] - 1
+
+
+def test_each_result_same_alone_and_in_the_mix():
+    cases = [request_case("nh", 8), request_case("lin", 12), request_case("q2", 4), request_case("nh", 12, seed=1),
+             request_case("lin", 8, seed=2), request_case("nh", 9, seed=3)]
+    alone = []
+    srv = mbddc.Server(0, 32 << 30, 1)
+    for c in cases:
+        m, primal, Ks, rhs, *_ = c
+        alone.append(srv.wait(srv.submit(m, options(primal), Ks, rhs))[1])
+    srv.close()
+    srv = mbddc.Server(0, 32 << 30, 4)
+    tickets = []
+    for rep in range(2):
+        for c in cases:
+            m, primal, Ks, rhs, *_ = c
+            tickets.append(srv.submit(m, options(primal), Ks, rhs))
+    results = [srv.wait(t) for t in tickets]
+    srv.close()
+    spans = [(r.t_admit_ms, r.t_done_ms) for r, _ in results]
+    overlap = any(a0 < b1 and b0 < a1 for i, (a0, a1) in enumerate(spans) for (b0, b1) in spans[i + 1:])
+    assert overlap, "no two requests ran at the same time"
+    for i, (r, x) in enumerate(results):
+        c = cases[i % len(cases)]
+        assert r.status == 0
+        assert np.array_equal(x, alone[i % len(cases)]), f"request {i} differs from its run alone"
+        check_residuals(c, x)
+
+
+def test_admission_respects_the_footprint_budget():
+    cases = [request_case("nh", 12), request_case("nh", 12, seed=1), request_case("lin", 12)]
+    fps = [mbddc.mbddc_estimate_footprint([c[0]], options(c[1])) for c in cases]
+    budget = max(fps) + min(fps) // 2          # never two at a time
+    srv = mbddc.Server(0, budget, 3)
+    tickets = [srv.submit(c[0], options(c[1]), c[2], c[3]) for c in cases]
+    results = [srv.wait(t)[0] for t in tickets]
+    srv.close()
+    spans = sorted((r.t_admit_ms, r.t_done_ms) for r in results)
+    for (a0, a1), (b0, b1) in zip(spans, spans[1:]):
+        assert b0 >= a1, "two requests were admitted together beyond the budget"
+    assert [r.footprint for r in results] == fps
+    assert all(r.status == 0 for r in results)
+
+
+def test_oversized_request_is_refused():
+    c = request_case("nh", 8)
+    srv = mbddc.Server(0, 1 << 20, 1)
+    with pytest.raises(mbddc.MbddcError) as e:
+        srv.submit(c[0], options(c[1]), c[2], c[3])
+    assert e.value.status == mbddc.MBDDC_ERR_OOM
+    srv.close()
+
+
+def test_footprint_estimate_bounds_the_handle():
+    for c, levels in ((request_case("nh", 12), 2), (request_case("q2", 4), 2), (request_case("nh", 12), 3)):
+        m, primal, Ks, rhs, *_ = c
+        est = mbddc.mbddc_estimate_footprint([m], options(primal, levels))
+        s = mbddc.Solver(0)
+        s.mbddc_setup_symbolic([m], options(primal, levels))
+        s.mbddc_set_tangent(Ks[0])
+        s.mbddc_factor()
+        s.mbddc_solve(rhs[0])
+        real = s.mbddc_footprint()
+        s.close()
+        assert 0.95 <= est / real <= 1.3, (est, real)

@@ -80,3 +80,26 @@ def test_host_plan_rejects_bad_input():
     assert e.value.status == mbddc.MBDDC_ERR_ARG
     with pytest.raises(mbddc.MbddcError):
         mbddc.mbddc_inspect_symbolic(m, 8)   # unknown primal bit
+
+
+def test_footprint_estimate_is_host_only_and_grows_with_size():
+    """The admission estimate needs no device and scales with the problem."""
+    from paper_2208_06191_amd import workloads as W
+    sizes = []
+    for n in (4, 8, 12):
+        mesh = W.box_mesh(n, n, n, 1)
+        part, nsub = W.block_partition(mesh, 4)
+        m = mbddc._MeshArrays(mesh.coords, mesh.elem_nodes, mesh.elem_type, part, nsub, mesh.node_tags,
+                              W.clamp_dofs(mesh, 1))
+        sizes.append(mbddc.mbddc_estimate_footprint([m], mbddc.default_options()))
+    assert 0 < sizes[0] < sizes[1] < sizes[2]
+    # a three-level handle carries no dense level-1 coarse inverse (512 subdomains, V+E+F)
+    mesh = W.box_mesh(24, 24, 24, 1)
+    part, nsub = W.block_partition(mesh, 3, cluster=2)
+    m = mbddc._MeshArrays(mesh.coords, mesh.elem_nodes, mesh.elem_type, part, nsub, mesh.node_tags,
+                          W.clamp_dofs(mesh, 1))
+    two = mbddc.mbddc_estimate_footprint([m], mbddc.default_options(primal=7))
+    three = mbddc.mbddc_estimate_footprint([m], mbddc.default_options(primal=7, levels=3))
+    assert three < two
+    with pytest.raises(mbddc.MbddcError):
+        mbddc.mbddc_estimate_footprint([m], mbddc.default_options(levels=5))
