@@ -343,8 +343,12 @@ def element_tangents(mesh: Mesh, material, u: Optional[np.ndarray] = None,
             A = (np.einsum("ik,mJL->miJkL", I, S)
                  + np.einsum("miI,mkK,mIJKL->miJkL", F, F, CC, optimize=True))
             wdet = wts[q] * det
-            Bm = np.einsum("eaJ,eiJkL->eaikL", dNX, A, optimize=True)
-            Ke += wdet[:, None, None, None, None] * np.einsum("eaikL,ebL->eaibk", Bm, dNX, optimize=True)
+            m = len(elems)
+            # B[e,a,(i,k,L)] = sum_J dN_a/dX_J A_iJkL, then K[e,(a,i,k),b] = sum_L B dN_b/dX_L
+            A2 = np.ascontiguousarray(A.transpose(0, 2, 1, 3, 4)).reshape(m, 3, 27)
+            Bm = np.matmul(dNX, A2).reshape(m, npe * 9, 3)
+            Kq = np.matmul(Bm, dNX.transpose(0, 2, 1)).reshape(m, npe, 3, 3, npe)
+            Ke += wdet[:, None, None, None, None] * Kq.transpose(0, 1, 2, 4, 3)
         out[elems] = Ke.reshape(len(elems), nd, nd)
     return out
 
@@ -454,6 +458,55 @@ def newton_tangents(mesh: Mesh, material, u0: np.ndarray, du: np.ndarray, n_step
     ([n_steps, n_el, 3npe, 3npe]): the sequence of tangent systems one request of the serving
     loop solves, its factors computed at u0 and reused (lagged) for the later steps."""
     return np.stack([element_tangents(mesh, material, u0 + (k / n_steps) * du) for k in range(n_steps)])
+
+
+def _nh_basis(mesh: Mesh, u: np.ndarray):
+    """The compressible neo-Hookean tangent is linear in (mu, lambda) at a fixed deformation:
+    K = mu K_mu + lambda K_lambda. Returns (K_mu, K_lambda)."""
+    return (element_tangents(mesh, {"kind": "neo_hookean", "mu": 1.0, "lam": 0.0}, u),
+            element_tangents(mesh, {"kind": "neo_hookean", "mu": 0.0, "lam": 1.0}, u))
+
+
+def batched_instances(n_inst: int = 64, seed: int = 100, dof_min: float = 5e3, dof_max: float = 2e5,
+                      nrhs: int = 4, amplitude: float = 0.02, progress=None) -> list:
+    """Independent neo-Hookean box tangents solved together: element type Q1 or Q2 with
+    probability 1/2, DOF count log-uniform in [dof_min, dof_max] (Q1 boxes n^3 with n a multiple
+    of 4 and subdomains of 4^3 elements, Q2 boxes with n a multiple of 2 and subdomains of 2^3,
+    both 375 DOFs per subdomain, numbered in 2x2x2 clusters), (mu, kappa) = (1, 50) times
+    independent U[0.5, 2] factors,
+    x = 0 clamped, primal V+E, nrhs right-hand sides. Instances of the same mesh share the
+    linearisation field (seed per mesh) and differ by their material factors."""
+    rng = np.random.default_rng(seed)
+    cache = {}
+    out = []
+    for i in range(n_inst):
+        q2 = rng.random() < 0.5
+        N = float(np.exp(rng.uniform(np.log(dof_min), np.log(dof_max))))
+        side = (N / 3.0) ** (1.0 / 3.0)                     # nodes per edge
+        if q2:
+            ne = max(2, 2 * int(round((side - 1.0) / 2.0 / 2.0)))
+            order, block = 2, 2
+        else:
+            ne = max(4, 4 * int(round((side - 1.0) / 4.0)))
+            order, block = 1, 4
+        fmu, fk = rng.uniform(0.5, 2.0, size=2)
+        key = (order, ne)
+        if key not in cache:
+            mesh = box_mesh(ne, ne, ne, order)
+            part, nsub = block_partition(mesh, block, cluster=2)
+            dirichlet = clamp_dofs(mesh, 1)
+            u = isochoric_field(mesh.coords, seed + len(cache), amplitude)
+            Kmu, Klam = _nh_basis(mesh, u)
+            rhs = _loads(mesh, dirichlet, nrhs, seed + 1000 + len(cache))
+            cache[key] = (mesh, part, nsub, dirichlet, Kmu, Klam, rhs)
+            if progress is not None:
+                progress(f"mesh Q{order} {ne}^3: {3 * mesh.n_nodes} DOFs")
+        mesh, part, nsub, dirichlet, Kmu, Klam, rhs = cache[key]
+        mu, kappa = fmu, 50.0 * fk
+        lam = kappa - 2.0 * mu / 3.0
+        out.append(Problem(f"inst{i}", mesh, part, nsub, dirichlet, mu * Kmu + lam * Klam, rhs, 3,
+                           {"order": order, "n": ne, "mu": mu, "kappa": kappa}))
+    return out
 
 
 def config_small() -> Problem:
