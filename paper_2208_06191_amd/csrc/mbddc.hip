@@ -790,16 +790,30 @@ int run_gj(mbddc_ctx* c, T* base, const GjDesc* d_desc, int64_t count, int maxn,
   return MBDDC_OK;
 }
 
+template <typename T, int BP, bool MF>
+int launch_sym(mbddc_ctx* c, T* base, const GjDesc* d_desc, int64_t count, int maxn, int32_t* d_stat) {
+  const size_t lds = std::max<size_t>((size_t)2 * maxn * (BP + 1) * sizeof(T), 16);
+  CHK(set_lds(k_sym_inv_batched<T, BP, MF>, lds));
+  hipLaunchKernelGGL((k_sym_inv_batched<T, BP, MF>), dim3((unsigned)count), dim3(kBlock), lds, c->stream, base,
+                     d_desc, d_stat);
+  HIPCHK(hipGetLastError());
+  return MBDDC_OK;
+}
+
+// Panels of 32 indices when both panel buffers fit in LDS (fewer passes over the
+// matrix in memory), else of 16.
 template <typename T>
 int run_sym(mbddc_ctx* c, T* base, const GjDesc* d_desc, int64_t count, int maxn, int32_t* d_stat) {
   if (count == 0) return MBDDC_OK;
-  constexpr int BP = sizeof(T) == 4 ? 32 : 16;
-  size_t lds = std::max<size_t>((size_t)2 * maxn * (BP + 1) * sizeof(T), 16);
-  CHK(set_lds(k_sym_inv_batched<T, BP>, lds));
-  hipLaunchKernelGGL((k_sym_inv_batched<T, BP>), dim3((unsigned)count), dim3(kBlock), lds, c->stream, base, d_desc,
-                     d_stat);
-  HIPCHK(hipGetLastError());
-  return MBDDC_OK;
+  if (sizeof(T) == 8 && maxn <= kSymRegMax) {   // the whole triangle fits in one workgroup's registers
+    CHK(set_lds(k_sym_inv_reg, kSymRegLds));
+    hipLaunchKernelGGL(k_sym_inv_reg, dim3((unsigned)count), dim3(kSymRegThreads), kSymRegLds, c->stream,
+                       reinterpret_cast<double*>(base), d_desc, d_stat);
+    HIPCHK(hipGetLastError());
+    return MBDDC_OK;
+  }
+  if ((size_t)2 * maxn * 33 * sizeof(T) <= 159 * 1024) return launch_sym<T, 32, false>(c, base, d_desc, count, maxn, d_stat);
+  return launch_sym<T, 16, false>(c, base, d_desc, count, maxn, d_stat);
 }
 
 int check_status(mbddc_ctx* c, int64_t count, const std::vector<GjDesc>& descs, int* bad) {
