@@ -12,7 +12,6 @@ constexpr int kMaxRhs = 8;           // right-hand sides handled per call
 constexpr int kGjMax = 512;          // largest matrix of the one-workgroup Gauss-Jordan kernel
 constexpr int kCoarseBlock = 64;     // diagonal block of the multi-workgroup coarse inversion
 constexpr int kCoarseChunk = 256;    // columns per workgroup in the coarse product
-constexpr int kMaxLocalConstraints = 96;  // primal constraints per subdomain on the symmetric path
 
 // Per-subdomain device descriptor. Offsets are element counts into the
 // per-precision work buffers. Dense work matrices are row-major; apply

@@ -353,7 +353,7 @@ int build_layout(mbddc_ctx* c) {
     c->gj_kii.push_back({d.oK, (int32_t)nI, (int32_t)ni, d.oPiv, (int32_t)s, 0});
     c->gj_p.push_back({d.oP, (int32_t)m, (int32_t)m, d.oPiv + nI, (int32_t)s, 0});
     c->gj_x.push_back({d.oP, (int32_t)nG, (int32_t)nG, 0, (int32_t)s, 0});
-    if (c->sym && nc > kMaxLocalConstraints)   // T = C X C^T inverted by the batched sweep
+    if (c->sym)   // T = C X C^T, inverted by the batched sweep
       c->gj_t.push_back({d.oP + nG * nG + 2 * nG * nc, (int32_t)nc, (int32_t)nc, 0, (int32_t)s, 0});
     // G = K_GI K_II^-1, H = K_II^-1 K_IG, S = K_GG - G K_IG
     GemmDesc g{};
@@ -1039,28 +1039,19 @@ int factor_impl(mbddc_ctx* c) {
     }
     {
       ProfScope ps(c, F_EXTRACT, 0.0, 0.0);
-      hipLaunchKernelGGL((k_constrained_small<T>), dim3(nsub), dim3(kBlock), 0, c->stream, c->d_subs,
-                         c->d_cons_ptr, c->d_cons_idx, c->d_cons_w, c->d_rho, W, c->d_Kcl, c->d_status);
-      if (!c->gj_t.empty()) {   // T^-1 of the subdomains with many constraints
-        HIPCHK(hipGetLastError());
-        st = check_status(c, (int64_t)c->gj_x.size(), c->gj_x, &bad);
-        if (st) {
-          c->last_bad = bad;
-          return st;
-        }
-        int maxt = 1;
-        for (const GjDesc& g : c->gj_t) maxt = std::max(maxt, g.n);
-        CHK(run_sym<T>(c, W, c->d_gj_t, (int64_t)c->gj_t.size(), maxt, c->d_status));
-        st = check_status(c, (int64_t)c->gj_t.size(), c->gj_t, &bad);
-        if (st) {
-          c->last_bad = bad;
-          return st;
-        }
-        hipLaunchKernelGGL((k_tinv_finish<T>), dim3((unsigned)c->gj_t.size()), dim3(kBlock), 0, c->stream, c->d_subs,
-                           c->d_gj_t, c->d_rho, W, c->d_Kcl);
-        // the statuses of the first launch were read; clear them for the check after extraction
-        hipLaunchKernelGGL(k_fill_i32, dim3(nblk(nsub)), dim3(kBlock), 0, c->stream, c->d_status, (int64_t)nsub, 0);
+      hipLaunchKernelGGL((k_constraint_products<T>), dim3(nsub), dim3(kBlock), 0, c->stream, c->d_subs,
+                         c->d_cons_ptr, c->d_cons_idx, c->d_cons_w, W);
+      HIPCHK(hipGetLastError());
+      int maxt = 1;
+      for (const GjDesc& g : c->gj_t) maxt = std::max(maxt, g.n);
+      CHK(run_sym<T>(c, W, c->d_gj_t, (int64_t)c->gj_t.size(), maxt, c->d_status));
+      st = check_status(c, (int64_t)c->gj_t.size(), c->gj_t, &bad);
+      if (st) {
+        c->last_bad = bad;
+        return st;
       }
+      hipLaunchKernelGGL((k_tinv_finish<T>), dim3((unsigned)c->gj_t.size()), dim3(kBlock), 0, c->stream, c->d_subs,
+                         c->d_gj_t, c->d_rho, W, c->d_Kcl);
       if (!c->gemm_items_phi.empty())
         hipLaunchKernelGGL((k_gemm_batched<T>), dim3((unsigned)c->gemm_items_phi.size()), dim3(kBlock), 0,
                            c->stream, c->d_gemm_desc, c->d_gemm_phi, W, W, W, W);
@@ -1071,11 +1062,6 @@ int factor_impl(mbddc_ctx* c) {
                          Op);
     }
     HIPCHK(hipGetLastError());
-    st = check_status(c, (int64_t)c->gj_x.size(), c->gj_x, &bad);
-    if (st) {
-      c->last_bad = bad;
-      return st;
-    }
   } else {
     {
       ProfScope ps(c, F_CONSTRAINTS, 0.0, 0.0);
