@@ -281,7 +281,7 @@ def _guccione(mat, F):
                                               + 0.5 * (np.einsum("ab,ac,bd->abcd", b, I, I)
                                                        + np.einsum("ab,ad,bc->abcd", b, I, I))[None])
     S = np.einsum("mai,mab,mbj->mij", Q, S_f, Q)
-    CC = np.einsum("mai,mbj,mck,mdl,mabcd->mijkl", Q, Q, Q, Q, Cf)
+    CC = np.einsum("mai,mbj,mck,mdl,mabcd->mijkl", Q, Q, Q, Q, Cf, optimize=True)
     # volumetric part W(J) = B/2 (J-1) ln J:  S_vol = J W'(J) C^-1
     J = np.linalg.det(F)
     if np.any(J <= 0):
@@ -507,6 +507,153 @@ def batched_instances(n_inst: int = 64, seed: int = 100, dof_min: float = 5e3, d
         out.append(Problem(f"inst{i}", mesh, part, nsub, dirichlet, mu * Kmu + lam * Klam, rhs, 3,
                            {"order": order, "n": ne, "mu": mu, "kappa": kappa}))
     return out
+
+
+# ----------------------------------------------------------------------------
+# ventricle-like shell: mapped truncated half-ellipsoid, fibre frames, RCB partition
+# ----------------------------------------------------------------------------
+VENT_BASE, VENT_ENDO, VENT_EPI, VENT_APEX = 1, 2, 4, 8
+
+
+def ventricle_mesh(n_t: int, n_theta: int, n_phi: int, order: int = 2, wall: float = 0.3,
+                   a_endo: float = 1.0, c_endo: float = 2.5, phi0_deg: float = 10.0):
+    """Thick-walled truncated half-ellipsoid (endocardial semi-axes a, a, c; wall thickness
+    `wall` along each axis), mapped isoparametrically from the parametric box
+    (t, theta, phi) in [0,1] x [0, 2 pi) x [phi0, pi/2]:
+        X = ((a + wall t) sin(phi) cos(theta), (a + wall t) sin(phi) sin(theta), -(c + wall t) cos(phi)).
+    theta is periodic; the base is the plane z = 0 (phi = pi/2), a small apical opening at
+    phi0 avoids degenerate elements. Node tags: base, endocardium (t = 0), epicardium
+    (t = 1), apex rim. Returns the mesh and the parametric node coordinates
+    (t, theta / 2 pi, meridian fraction)."""
+    p = order
+    Nt, Nth, Nph = p * n_t + 1, p * n_theta, p * n_phi + 1
+    phi0 = np.deg2rad(phi0_deg)
+    it, ith, iph = np.meshgrid(np.arange(Nt), np.arange(Nth), np.arange(Nph), indexing="ij")
+    it, ith, iph = it.ravel(order="F"), ith.ravel(order="F"), iph.ravel(order="F")
+    # node id = it + Nt (ith + Nth iph)
+    order_ids = it + Nt * (ith + Nth * iph)
+    t = np.empty(Nt * Nth * Nph)
+    th = np.empty_like(t)
+    ph = np.empty_like(t)
+    t[order_ids] = it / (Nt - 1)
+    th[order_ids] = 2.0 * np.pi * ith / Nth
+    ph[order_ids] = phi0 + (0.5 * np.pi - phi0) * iph / (Nph - 1)
+    r_xy = a_endo + wall * t
+    r_z = c_endo + wall * t
+    coords = np.stack([r_xy * np.sin(ph) * np.cos(th), r_xy * np.sin(ph) * np.sin(th), -r_z * np.cos(ph)], axis=1)
+    IT = np.empty(Nt * Nth * Nph, dtype=np.int64)
+    IPH = np.empty_like(IT)
+    IT[order_ids] = it
+    IPH[order_ids] = iph
+    tags = ((IPH == Nph - 1) * VENT_BASE | (IT == 0) * VENT_ENDO | (IT == Nt - 1) * VENT_EPI
+            | (IPH == 0) * VENT_APEX).astype(np.uint32)
+    ep, eth, et = np.meshgrid(np.arange(n_phi), np.arange(n_theta), np.arange(n_t), indexing="ij")
+    et, eth, ep = et.ravel(), eth.ravel(), ep.ravel()
+    p1 = p + 1
+    en = np.empty((n_t * n_theta * n_phi, p1 ** 3), dtype=np.int64)
+    for c in range(p1):
+        for b in range(p1):
+            for a in range(p1):
+                en[:, a + p1 * b + p1 * p1 * c] = ((p * et + a) + Nt * (((p * eth + b) % Nth) + Nth * (p * ep + c)))
+    mesh = Mesh(coords=coords, elem_nodes=en.astype(np.int32), order=order, node_tags=tags,
+                shape=(n_t, n_theta, n_phi))
+    param = np.stack([t, th / (2.0 * np.pi), (ph - phi0) / (0.5 * np.pi - phi0)], axis=1)
+    return mesh, param
+
+
+def ventricle_elem_param(mesh: Mesh) -> np.ndarray:
+    """Parametric centroid (t, theta / 2 pi, meridian fraction) of every element, from the
+    structured element numbering (element = et + n_t (eth + n_theta ep)), so that elements
+    on the periodic seam are not averaged across it."""
+    n_t, n_th, n_ph = mesh.shape
+    e = np.arange(mesh.n_elems)
+    et, eth, ep = e % n_t, (e // n_t) % n_th, e // (n_t * n_th)
+    return np.stack([(et + 0.5) / n_t, (eth + 0.5) / n_th, (ep + 0.5) / n_ph], axis=1)
+
+
+def ventricle_frames(mesh: Mesh, param: np.ndarray, helix_endo_deg: float = 60.0, helix_epi_deg: float = -60.0):
+    """Per-element fibre frames (rows f, s, n) at the element centroid: helix angle linear in
+    the transmural coordinate from helix_endo at t = 0 to helix_epi at t = 1; f = cos(a) e_theta
+    + sin(a) e_phi, s the transmural direction made orthogonal to f, n = f x s."""
+    pc = ventricle_elem_param(mesh)
+    Xc = mesh.coords[mesh.elem_nodes].mean(axis=1)
+    theta = np.arctan2(Xc[:, 1], Xc[:, 0])
+    e_th = np.stack([-np.sin(theta), np.cos(theta), np.zeros_like(theta)], axis=1)
+    # transmural and meridian directions from the element's own geometry
+    npe = mesh.npe
+    p1 = mesh.order + 1
+    Xe = mesh.coords[mesh.elem_nodes]
+    a_hi = [i for i in range(npe) if i % p1 == p1 - 1]
+    a_lo = [i for i in range(npe) if i % p1 == 0]
+    c_hi = [i for i in range(npe) if i // (p1 * p1) == p1 - 1]
+    c_lo = [i for i in range(npe) if i // (p1 * p1) == 0]
+    e_t = Xe[:, a_hi].mean(axis=1) - Xe[:, a_lo].mean(axis=1)
+    e_ph = Xe[:, c_hi].mean(axis=1) - Xe[:, c_lo].mean(axis=1)
+    e_ph -= np.sum(e_ph * e_th, axis=1, keepdims=True) * e_th
+    e_ph /= np.linalg.norm(e_ph, axis=1, keepdims=True)
+    alpha = np.deg2rad(helix_endo_deg + (helix_epi_deg - helix_endo_deg) * pc[:, 0])
+    f = np.cos(alpha)[:, None] * e_th + np.sin(alpha)[:, None] * e_ph
+    f /= np.linalg.norm(f, axis=1, keepdims=True)
+    s = e_t - np.sum(e_t * f, axis=1, keepdims=True) * f
+    s /= np.linalg.norm(s, axis=1, keepdims=True)
+    n = np.cross(f, s)
+    return np.stack([f, s, n], axis=1)
+
+
+def rcb_partition(mesh: Mesh, param: np.ndarray, target_dofs: int, seed: int = 3,
+                  scale=(0.3, 7.2, 2.5)) -> tuple[np.ndarray, int]:
+    """Recursive coordinate bisection of the element centroids in scaled parametric
+    coordinates (transmural, circumferential, meridian extents): the longest extent of a part
+    is split at a seeded quantile q ~ U[0.2, 0.8] (elements with equal coordinates on the
+    same side, so every part is a box of the structured parameter grid) until a part has at
+    most target_dofs DOFs (3 x its distinct nodes). Parts are numbered in recursion order
+    (neighbours get neighbouring ids). Returns (elem_part, n_parts)."""
+    rng = np.random.default_rng(seed)
+    cen = ventricle_elem_param(mesh) * np.asarray(scale)[None, :]
+    part = np.zeros(mesh.n_elems, dtype=np.int32)
+    stack = [np.arange(mesh.n_elems)]
+    leaves = []
+    while stack:
+        el = stack.pop()
+        ndof = 3 * len(np.unique(mesh.elem_nodes[el]))
+        if ndof <= target_dofs or len(el) < 2:
+            leaves.append(el)
+            continue
+        ext = cen[el].max(axis=0) - cen[el].min(axis=0)
+        d = int(np.argmax(ext))
+        q = rng.uniform(0.2, 0.8)
+        key = cen[el, d]
+        cut = np.quantile(key, q)
+        if cut >= key.max():                     # all elements with equal coordinates stay together
+            cut = key[key < key.max()].max() if np.any(key < key.max()) else cut
+        lo, hi = el[key <= cut], el[key > cut]
+        if len(lo) == 0 or len(hi) == 0:
+            leaves.append(el)
+            continue
+        stack.append(hi)
+        stack.append(lo)
+    for i, el in enumerate(leaves):
+        part[el] = i
+    return part, len(leaves)
+
+
+def ventricle(n_t: int = 4, n_theta: int = 96, n_phi: int = 96, order: int = 2, target_dofs: int = 6000,
+              nrhs: int = 1, amplitude: float = 0.015, field_seed: int = 2, part_seed: int = 3,
+              rhs_seed: int = 5, primal: int = 7, name: str = "ventricle") -> Problem:
+    """Guccione tangent (C = 0.88, bf = 8, bt = bfs = 2, B = 50) on the ventricle-like shell,
+    fibres rotating from +60 to -60 degrees transmurally, linearised at the seeded isochoric
+    8-mode field of the physical coordinates (max |u| = amplitude = 0.05 x wall thickness),
+    base clamped, RCB partition into parts of at most target_dofs DOFs."""
+    mesh, param = ventricle_mesh(n_t, n_theta, n_phi, order)
+    part, nsub = rcb_partition(mesh, param, target_dofs, part_seed)
+    dirichlet = clamp_dofs(mesh, VENT_BASE)
+    u = isochoric_field(mesh.coords, field_seed, amplitude)
+    frames = ventricle_frames(mesh, param)
+    Ke = element_tangents(mesh, guccione(), u, frames_fn=lambda elems, q: frames[elems])
+    rhs = _loads(mesh, dirichlet, nrhs, rhs_seed)
+    return Problem(name, mesh, part, nsub, dirichlet, Ke, rhs, primal,
+                   {"material": "guccione", "n": (n_t, n_theta, n_phi), "order": order,
+                    "target_dofs": target_dofs, "amplitude": amplitude})
 
 
 def config_small() -> Problem:

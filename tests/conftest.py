@@ -39,6 +39,8 @@ def problem(name: str):
         Ke = W.element_tangents(mesh, W.linear_elastic(1.0, 0.3))
         rhs = W._loads(mesh, dirichlet, 1, 11)
         return Problem("l3_ragged", mesh, part, nsub, dirichlet, Ke, rhs, 1, {})
+    if name == "vent":             # Q2 ventricle-like shell, Guccione fibres, RCB parts <= 480 DOFs
+        return W.ventricle(2, 16, 8, 2, target_dofs=480, nrhs=2, primal=7, name="vent")
     if name == "ragged":           # 6x5x7 Q1 box, blocks of 4 -> uneven subdomains
         from paper_2208_06191_amd.workloads import Problem
         mesh = W.box_mesh(6, 5, 7, 1)
@@ -54,3 +56,23 @@ def problem(name: str):
 @pytest.fixture
 def get_problem():
     return problem
+
+
+@functools.lru_cache(maxsize=None)
+def apply_noise_floor(name: str, primal: int, levels: int = 2, group: int = 8, primal2: int = 7) -> float:
+    """How far the oracle's own FP64 preconditioner application moves when every element
+    tangent entry is perturbed by a relative 2.2e-16 (seeded): no FP64 implementation of the
+    same operator can be held closer to the oracle than this (the apply's condition)."""
+    import numpy as np
+    from oracle import bddc
+    P = problem(name)
+    dec = bddc.Decomposition(P.mesh.elem_nodes, P.mesh.n_nodes, P.elem_part, P.n_sub, P.dirichlet,
+                             P.mesh.node_tags, primal=primal)
+    E = np.random.default_rng(1).standard_normal(P.Ke.shape)
+    E = 0.5 * (E + E.transpose(0, 2, 1))
+    r = np.random.default_rng(3).standard_normal(P.n_dofs)[dec.free]
+    out = []
+    for Ke in (P.Ke, P.Ke * (1.0 + 2.2e-16 * E)):
+        B = bddc.BDDC(dec, P.mesh.elem_nodes, Ke, levels=levels, coarse_group=group, level2_primal=primal2)
+        out.append(B.apply(r))
+    return float(np.linalg.norm(out[0] - out[1]) / np.linalg.norm(out[0]))

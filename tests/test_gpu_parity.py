@@ -3,7 +3,9 @@
 Checkpoints (paper §3.2 objects):
 * P1  assembled operator (3x3 blocks) and K x            FP64 <= 1e-14
 * P4  coarse matrix S_PiPi                               FP64 <= 1e-12, mixed <= 1e-4
-* P5  one preconditioner application z = M^-1 r          FP64 <= 1e-12, mixed <= 1e-5
+* P5  one preconditioner application z = M^-1 r          FP64 <= max(1e-12, 100 x the oracle's own
+                                                          change under a relative-eps perturbation
+                                                          of K_e), mixed <= 1e-5
 * P6  GMRES iterations                                   FP64: oracle +-1, mixed: <= oracle + 2
 *     solution (both at rtol 1e-12)                      FP64 <= 1e-8, mixed <= 1e-6
 * P7  true residual                                       <= rtol
@@ -18,7 +20,7 @@ import pytest
 from oracle import bddc, fem, gmres
 from paper_2208_06191_amd import mbddc
 from paper_2208_06191_amd import workloads as W
-from tests.conftest import problem
+from tests.conftest import apply_noise_floor, problem
 
 pytestmark = pytest.mark.gpu
 
@@ -56,7 +58,7 @@ def rel(a, b):
     return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
 
 
-CASES = [("small", 1), ("small_ve", 3), ("tiny_q2", 7), ("ragged", 3), ("tiny_nh", 3), ("small_ve", 6)]
+CASES = [("small", 1), ("small_ve", 3), ("tiny_q2", 7), ("ragged", 3), ("tiny_nh", 3), ("small_ve", 6), ("vent", 7)]
 
 
 @pytest.mark.parametrize("name,primal", CASES[:4])
@@ -100,7 +102,7 @@ def test_coarse_matrix_and_apply(name, primal, precision, sym):
     clamped = np.setdiff1d(np.arange(P.n_dofs), dec.free)
     print(f"{name} primal={primal} prec={precision} sym={sym}: coarse {err_c:.2e} apply {max(errs):.2e}")
     assert err_c <= TOL_COARSE[precision]
-    assert max(errs) <= TOL_APPLY[precision]
+    assert max(errs) <= max(TOL_APPLY[precision], 100.0 * apply_noise_floor(name, primal))
     assert np.abs(z[:, clamped]).max() == 0.0
 
 

@@ -16,7 +16,7 @@ import pytest
 
 from oracle import bddc, gmres
 from paper_2208_06191_amd import mbddc
-from tests.conftest import problem
+from tests.conftest import apply_noise_floor, problem
 
 pytestmark = pytest.mark.gpu
 
@@ -24,8 +24,8 @@ TOL_APPLY = {mbddc.MBDDC_FP64: 1e-12, mbddc.MBDDC_MIXED: 1e-5}
 VEF = 7
 
 # (problem, fine primal, coarse group, level-2 primal)
-CASES = [("l3_nh", 3, 8, VEF), ("l3_nh", 1, 8, VEF), ("l3_ragged", 1, 5, VEF), ("l3_ragged", 3, 7, 3),
-         ("small_ve", 3, 3, VEF)]
+CASES = [("l3_nh", 3, 8, VEF), ("l3_nh", 1, 8, VEF), ("l3_ragged", 1, 5, VEF), ("vent", VEF, 8, VEF),
+         ("l3_ragged", 3, 7, 3), ("small_ve", 3, 3, VEF)]
 
 
 @functools.lru_cache(maxsize=None)
@@ -82,14 +82,14 @@ def test_three_level_apply(name, primal, group, primal2, precision, sym):
     clamped = np.setdiff1d(np.arange(P.n_dofs), dec.free)
     print(f"{name} primal={primal} group={group} primal2={primal2} prec={precision} sym={sym}: "
           f"apply {max(errs):.2e}")
-    assert max(errs) <= TOL_APPLY[precision]
+    assert max(errs) <= max(TOL_APPLY[precision], 100.0 * apply_noise_floor(name, primal, 3, group, primal2))
     assert np.abs(z[:, clamped]).max() == 0.0
     s.close()
 
 
 @pytest.mark.parametrize("sym", [0, 1])
 @pytest.mark.parametrize("precision", [mbddc.MBDDC_FP64, mbddc.MBDDC_MIXED])
-@pytest.mark.parametrize("name,primal,group,primal2", CASES[:3])
+@pytest.mark.parametrize("name,primal,group,primal2", CASES[:4])
 def test_three_level_solve(name, primal, group, primal2, precision, sym):
     P = problem(name)
     dec, B = oracle3(name, primal, group, primal2)

@@ -116,3 +116,70 @@ def test_guccione_tangent_is_derivative_of_internal_force():
             Qs[key] = np.linalg.qr(A)[0].transpose(0, 2, 1)
         return Qs[key]
     assert _fd_check(mesh, W.guccione(), u, frames_fn=frames) < 1e-7
+
+
+# ---------------------------------------------------------------- ventricle-like shell
+def _shell_volume(a=1.0, c=2.5, w=0.3, phi0=np.deg2rad(10.0)):
+    """Closed form of the mapped shell's volume: the map's Jacobian is
+    w r1 sin(phi) (r3 sin^2(phi) + r1 cos^2(phi)) with r1 = a + w t, r3 = c + w t."""
+    cp = np.cos(phi0)
+    return 2 * np.pi * w * ((a * c + (a + c) * w / 2 + w * w / 3) * (cp - cp ** 3 / 3)
+                            + (a * a + a * w + w * w / 3) * cp ** 3 / 3)
+
+
+def test_ventricle_volume_tags_and_clamp():
+    mesh, param = W.ventricle_mesh(2, 16, 8, 2)
+    f = np.zeros((mesh.n_nodes, 3))
+    f[:, 2] = 1.0
+    vol = W.body_force_load(mesh, f).reshape(-1, 3)[:, 2].sum()   # sum of N_a |J| = volume
+    assert abs(vol - _shell_volume()) < 2e-4 * _shell_volume()
+    base = (mesh.node_tags & W.VENT_BASE) != 0
+    assert np.allclose(mesh.coords[base, 2], 0.0, atol=1e-14) and base.sum() == 5 * 32
+    endo = (mesh.node_tags & W.VENT_ENDO) != 0
+    X = mesh.coords[endo]
+    assert np.allclose((X[:, 0] ** 2 + X[:, 1] ** 2) / 1.0 + X[:, 2] ** 2 / 2.5 ** 2, 1.0)
+    # periodic seam: every element's nodes are distinct and theta wraps around
+    assert all(len(set(e)) == 27 for e in mesh.elem_nodes)
+
+
+def test_ventricle_fibre_frames():
+    mesh, param = W.ventricle_mesh(3, 12, 6, 2)
+    Q = W.ventricle_frames(mesh, param)
+    assert np.abs(np.einsum("eai,ebi->eab", Q, Q) - np.eye(3)).max() < 1e-12
+    assert np.all(np.linalg.det(Q) > 0)
+    # helix angle: +60 deg at the endocardial side decreasing to -60 deg, linear in t
+    tc = W.ventricle_elem_param(mesh)[:, 0]
+    Xc = mesh.coords[mesh.elem_nodes].mean(axis=1)
+    th = np.arctan2(Xc[:, 1], Xc[:, 0])
+    e_th = np.stack([-np.sin(th), np.cos(th), np.zeros_like(th)], axis=1)
+    cos_a = np.einsum("ei,ei->e", Q[:, 0], e_th)
+    assert np.allclose(cos_a, np.cos(np.deg2rad(60.0 - 120.0 * tc)), atol=1e-12)
+    # the fibre turns from "upward" (towards the base) at the endocardium to downward outside
+    up = Q[:, 0, 2]
+    assert np.all(up[tc < 0.2] > 0) and np.all(up[tc > 0.8] < 0)
+
+
+def test_rcb_parts_are_bounded_connected_and_cover():
+    mesh, param = W.ventricle_mesh(2, 16, 8, 2)
+    part, nsub = W.rcb_partition(mesh, param, 480, 3)
+    assert part.min() == 0 and part.max() == nsub - 1
+    for i in range(nsub):
+        el = np.nonzero(part == i)[0]
+        assert 3 * len(np.unique(mesh.elem_nodes[el])) <= 480
+        # connectivity through shared nodes
+        seen, front = {el[0]}, [el[0]]
+        nodes_of = {e: set(mesh.elem_nodes[e]) for e in el}
+        while front:
+            e = front.pop()
+            for f_ in el:
+                if f_ not in seen and nodes_of[e] & nodes_of[f_]:
+                    seen.add(f_)
+                    front.append(f_)
+        assert len(seen) == len(el)
+
+
+def test_ventricle_guccione_tangent_is_derivative_of_internal_force():
+    mesh, param = W.ventricle_mesh(1, 4, 2, 2)
+    Q = W.ventricle_frames(mesh, param)
+    u = W.isochoric_field(mesh.coords, 2, 0.015)
+    assert _fd_check(mesh, W.guccione(), u, frames_fn=lambda e, q: Q[e]) < 1e-7
