@@ -12,6 +12,7 @@ constexpr int kMaxRhs = 8;           // right-hand sides handled per call
 constexpr int kGjMax = 512;          // largest matrix of the one-workgroup Gauss-Jordan kernel
 constexpr int kCoarseBlock = 64;     // diagonal block of the multi-workgroup coarse inversion
 constexpr int kCoarseChunk = 256;    // columns per workgroup in the coarse product
+constexpr int kApplyChunk = 1024;    // input columns staged in LDS at a time by the local apply
 
 // Per-subdomain device descriptor. Offsets are element counts into the
 // per-precision work buffers. Dense work matrices are row-major; apply
@@ -36,6 +37,15 @@ struct GjDesc {
   int32_t n, ld;
   int64_t piv_off;
   int32_t id;                          // reported in the status array on a zero pivot
+  int32_t pad;
+};
+
+// Large symmetric matrix of the batched blocked sweep: base + off, n x n, row stride ld
+// (lower triangle used); panel buffers W and U (n x 128 each, U after W) at pbuf + pw.
+struct BigSym {
+  int64_t off, pw;
+  int32_t n, ld;
+  int32_t stat;                        // status slot
   int32_t pad;
 };
 

@@ -95,6 +95,74 @@ struct Profiler {
 
 }  // namespace
 
+namespace mbddc {
+
+// Largest matrix of the one-workgroup symmetric sweeps: both 16-index panel buffers in LDS.
+template <typename T>
+constexpr int sym_onewg_max() { return (int)((159 * 1024) / (2 * 17 * sizeof(T))); }
+
+// One family of symmetric inversions (K_II, S + rho C^T C or T over all subdomains).
+// FP64 matrices larger than the register-resident sweep take the batched blocked
+// sweep; the others take the one-workgroup kernels. Status slots: the one-workgroup
+// matrices first (slot = position), then the blocked ones (sorted by size, descending).
+struct SymSet {
+  std::vector<GjDesc> all;          // descriptors in status-slot order
+  int64_t n_small = 0;
+  int small_maxn = 1;
+  std::vector<BigSym> big;
+  std::vector<int2> items;          // (matrix, lower 64-tile) of the update and finish
+  std::vector<int64_t> item_off;    // [big.size() + 1]
+  std::vector<GemmDesc> gd;         // U = W Dinv per matrix
+  std::vector<GemmItem> gitems;
+  std::vector<int64_t> gitem_off;   // [big.size() + 1]
+  int64_t pbuf_elems = 0;
+  GjDesc* d_all = nullptr;
+  BigSym* d_big = nullptr;
+  int2* d_items = nullptr;
+  GemmDesc* d_gd = nullptr;
+  GemmItem* d_gitems = nullptr;
+
+  void build(const std::vector<GjDesc>& src, bool allow_big) {
+    all.clear(); big.clear(); items.clear(); gd.clear(); gitems.clear();
+    item_off.assign(1, 0);
+    gitem_off.assign(1, 0);
+    std::vector<GjDesc> large;
+    small_maxn = 1;
+    for (const GjDesc& g : src) {
+      if (allow_big && g.n > kSymRegMax) {
+        large.push_back(g);
+      } else {
+        all.push_back(g);
+        small_maxn = std::max(small_maxn, g.n);
+      }
+    }
+    n_small = (int64_t)all.size();
+    std::stable_sort(large.begin(), large.end(), [](const GjDesc& a, const GjDesc& b) { return a.n > b.n; });
+    pbuf_elems = 0;
+    for (const GjDesc& g : large) {
+      const int32_t j = (int32_t)big.size();
+      BigSym b{};
+      b.off = g.off; b.n = g.n; b.ld = g.ld; b.stat = (int32_t)(n_small + j); b.pw = pbuf_elems;
+      pbuf_elems += 2LL * g.n * kSymCB;
+      big.push_back(b);
+      all.push_back(g);
+      const int nt = (g.n + kUpdTile - 1) / kUpdTile;
+      for (int t = 0; t < nt * (nt + 1) / 2; ++t) items.push_back(make_int2(j, t));
+      item_off.push_back((int64_t)items.size());
+      GemmDesc m{};
+      m.M = g.n; m.N = kSymCB; m.K = kSymCB; m.lda = kSymCB; m.ldb = kSymCB; m.ldc = kSymCB; m.ldci = kSymCB;
+      m.tiles_n = kSymCB / 64; m.alpha = 1.0; m.beta = 0.0;
+      m.oA = b.pw; m.oB = (int64_t)j * kSymCB * kSymCB; m.oC = b.pw + (int64_t)g.n * kSymCB; m.oCi = 0;
+      gd.push_back(m);
+      for (int a = 0; a < (g.n + 63) / 64; ++a)
+        for (int bb = 0; bb < m.tiles_n; ++bb) gitems.push_back({j, a, bb, 0});
+      gitem_off.push_back((int64_t)gitems.size());
+    }
+  }
+};
+
+}  // namespace mbddc
+
 struct mbddc_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -117,6 +185,8 @@ struct mbddc_ctx {
   std::vector<GemmItem> gemm_items_gh, gemm_items_s, gemm_items_g, gemm_items_ssym, gemm_items_phi, gemm_items_stil;
   std::vector<GjDesc> gj_x;                          // (S + rho C^T C) blocks of the symmetric path
   std::vector<GjDesc> gj_t;                          // T = C X C^T blocks too large for LDS (symmetric path)
+  SymSet set_kii, set_x, set_t;                      // symmetric path: the three inversion families
+  int64_t big_pbuf = 0, big_count = 0;               // batched blocked sweep: panel elements, matrices
   bool sym = false;                                  // symmetric (SPD) factor path
   std::vector<ApplyItem> itA, itC, itE, itF, itH;
   std::vector<int64_t> inst_coarse_off, inst_kc_off;
@@ -171,6 +241,7 @@ struct mbddc_ctx {
   double *d_cDinv = nullptr, *d_cY = nullptr, *d_cCcol = nullptr;
   double* d_amax = nullptr;
   int64_t status_len = 0;
+  double *d_bpanel = nullptr, *d_bdinv = nullptr, *d_bthr = nullptr;   // batched blocked sweep
 
   // per-call buffers (sized for R right-hand sides)
   int R_alloc = 0;
@@ -334,7 +405,10 @@ int build_layout(mbddc_ctx* c) {
     d.n_elems = L.n_elems; d.ldK = L.ni();
     d.dof_off = L.dof_off; d.if_off = L.if_off; d.c_off = L.c_off; d.elem_off = L.elem_off; d.cons_off = L.cons_off;
     const int64_t ni = L.ni(), nI = L.nI, nG = L.nG, nc = L.nc, m = L.mP();
-    if (std::max<int64_t>(nI, m) > kGjMax) return MBDDC_ERR_UNSUPPORTED;
+    // the pivoting path inverts in one workgroup; the symmetric path sweeps larger FP64
+    // matrices with the batched blocked kernels, larger FP32 ones not at all
+    if (!c->sym && std::max<int64_t>(nI, m) > kGjMax) return MBDDC_ERR_UNSUPPORTED;
+    if (c->sym && c->fact32 && std::max(std::max(nI, nG), nc) > sym_onewg_max<float>()) return MBDDC_ERR_UNSUPPORTED;
     d.oK = w; w += round_up(ni * ni, 64);
     d.oG = w; w += round_up(nG * nI, 64);
     d.oH = w; w += round_up(nI * nG, 64);
@@ -424,6 +498,13 @@ int build_layout(mbddc_ctx* c) {
   add_items(dSs, c->gemm_items_ssym);
   add_items(dPhi, c->gemm_items_phi);
   add_items(dStil, c->gemm_items_stil);
+  if (c->sym) {
+    c->set_kii.build(c->gj_kii, !c->fact32);
+    c->set_x.build(c->gj_x, !c->fact32);
+    c->set_t.build(c->gj_t, !c->fact32);
+  }
+  c->big_pbuf = std::max(std::max(c->set_kii.pbuf_elems, c->set_x.pbuf_elems), c->set_t.pbuf_elems);
+  c->big_count = (int64_t)std::max(std::max(c->set_kii.big.size(), c->set_x.big.size()), c->set_t.big.size());
   c->w_elems = w;
   c->op_elems = op;
   c->kcl_elems = kcl;
@@ -574,6 +655,13 @@ int upload_plan(mbddc_ctx* c) {
   CHK(upload(c, &c->d_gemm_stil, c->gemm_items_stil));
   CHK(upload(c, &c->d_gj_x, c->gj_x));
   CHK(upload(c, &c->d_gj_t, c->gj_t));
+  for (SymSet* S : {&c->set_kii, &c->set_x, &c->set_t}) {
+    CHK(upload(c, &S->d_all, S->all));
+    CHK(upload(c, &S->d_big, S->big));
+    CHK(upload(c, &S->d_items, S->items));
+    CHK(upload(c, &S->d_gd, S->gd));
+    CHK(upload(c, &S->d_gitems, S->gitems));
+  }
   CHK(dalloc(c, &c->d_rho, std::max<int64_t>(P.n_sub, 1)));
   CHK(upload(c, &c->d_itA, c->itA));
   CHK(upload(c, &c->d_itC, c->itC));
@@ -620,6 +708,11 @@ int upload_plan(mbddc_ctx* c) {
     CHK(upload(c, &c->d_csym_items, items));
   }
   CHK(dalloc(c, &c->d_amax, 1));
+  if (c->big_count > 0) {
+    CHK(dalloc(c, &c->d_bpanel, c->big_pbuf));
+    CHK(dalloc(c, &c->d_bdinv, c->big_count * kSymCB * kSymCB));
+    CHK(dalloc(c, &c->d_bthr, c->big_count));
+  }
   HIPCHK(hipStreamSynchronize(c->stream));
   return MBDDC_OK;
 }
@@ -736,6 +829,10 @@ double device_bytes_estimate(const mbddc_ctx* c, bool krylov) {
     const double cb = std::max(kCoarseBlock, kSymCB), ld = round_up(c->coarse_max_nc, 4);
     b += 8.0 * (2 * cb * cb + 2 * cb * ld);
   }
+  if (c->big_count > 0) b += 8.0 * (c->big_pbuf + c->big_count * ((double)kSymCB * kSymCB + 1));
+  for (const SymSet* S : {&c->set_kii, &c->set_x, &c->set_t})
+    b += 32.0 * S->all.size() + 24.0 * S->big.size() + 8.0 * S->items.size() + 64.0 * S->gd.size() +
+         16.0 * S->gitems.size();
   b += 8.0 * R * (2.0 * P.n_slots + std::max<int64_t>(P.n_cslots, 1) + c->nchunk_max * std::max<int64_t>(P.n_coarse, 1));
   b += 8.0 * R * P.n_dofs * (krylov ? (3 + 2 * J + 4) : 3);
   if (c->child) b += device_bytes_estimate(c->child, false) + 8.0 * (P.n_coarse + P.n_cslots);
@@ -814,6 +911,36 @@ int run_sym(mbddc_ctx* c, T* base, const GjDesc* d_desc, int64_t count, int maxn
   }
   if ((size_t)2 * maxn * 33 * sizeof(T) <= 159 * 1024) return launch_sym<T, 32, false>(c, base, d_desc, count, maxn, d_stat);
   return launch_sym<T, 16, false>(c, base, d_desc, count, maxn, d_stat);
+}
+
+// Inverts every matrix of a symmetric family in place (lower triangle read, full
+// inverse written); statuses land in the set's slots.
+template <typename T>
+int run_symset(mbddc_ctx* c, T* base, const SymSet& S) {
+  if (S.n_small > 0) CHK(run_sym<T>(c, base, S.d_all, S.n_small, S.small_maxn, c->d_status));
+  if (S.big.empty()) return MBDDC_OK;
+  if (sizeof(T) != 8) return MBDDC_ERR_UNSUPPORTED;
+  double* A = reinterpret_cast<double*>(base);
+  const unsigned nb = (unsigned)S.big.size();
+  hipLaunchKernelGGL(k_bsym_prep, dim3(nb), dim3(kBlock), 0, c->stream, S.d_big, A, c->d_bthr, c->d_status);
+  CHK(set_lds(k_bsym_diag, kDiagLds));
+  const int nmax = S.big[0].n;
+  const unsigned gx = std::min<unsigned>(64, nblk((int64_t)nmax * kSymCB));
+  unsigned active = nb;
+  for (int k0 = 0; k0 < nmax; k0 += kSymCB) {
+    while (active > 0 && S.big[active - 1].n <= k0) --active;
+    hipLaunchKernelGGL(k_bsym_diag, dim3(active), dim3(kBlock), kDiagLds, c->stream, S.d_big, A, c->d_bdinv,
+                       c->d_bthr, c->d_status, k0);
+    hipLaunchKernelGGL(k_bsym_gather, dim3(gx, active), dim3(kBlock), 0, c->stream, S.d_big, A, c->d_bpanel, k0);
+    hipLaunchKernelGGL((k_gemm_batched<double>), dim3((unsigned)S.gitem_off[active]), dim3(kBlock), 0, c->stream,
+                       S.d_gd, S.d_gitems, c->d_bpanel, c->d_bdinv, c->d_bpanel, c->d_bpanel);
+    hipLaunchKernelGGL(k_bsym_update, dim3((unsigned)S.item_off[active]), dim3(kBlock), 0, c->stream, S.d_big,
+                       S.d_items, A, c->d_bpanel, c->d_bdinv, k0);
+  }
+  hipLaunchKernelGGL(k_bsym_finish, dim3((unsigned)S.item_off[nb]), dim3(kBlock), 0, c->stream, S.d_big, S.d_items,
+                     A);
+  HIPCHK(hipGetLastError());
+  return MBDDC_OK;
 }
 
 int check_status(mbddc_ctx* c, int64_t count, const std::vector<GjDesc>& descs, int* bad) {
@@ -989,20 +1116,20 @@ int factor_impl(mbddc_ctx* c) {
                        c->d_sub_elems, c->d_ke_off, c->d_elem_npe, c->d_elem_ldof, c->d_elem_ldof_off, W);
   }
   HIPCHK(hipGetLastError());
-  int maxI = 1, maxP = 1, maxG = 1;
+  int maxI = 1, maxP = 1;
   for (const SubDev& d : c->subs) {
     maxI = std::max(maxI, d.nI);
     maxP = std::max(maxP, d.nG + d.nc);
-    maxG = std::max(maxG, d.nG);
   }
   int bad = 0, st = 0;
   // K_II^-1 (interior / Dirichlet problems, §3.2 block factorisation)
   {
     ProfScope ps(c, F_GJ_KII, 0.0, c->fam_flops[F_GJ_KII]);
-    if (c->sym) CHK(run_sym<T>(c, W, c->d_gj_kii, (int64_t)c->gj_kii.size(), maxI, c->d_status));
+    if (c->sym) CHK(run_symset<T>(c, W, c->set_kii));
     else CHK(run_gj<T>(c, W, c->d_gj_kii, (int64_t)c->gj_kii.size(), maxI, c->d_status, c->d_piv));
   }
-  st = check_status(c, (int64_t)c->gj_kii.size(), c->gj_kii, &bad);
+  st = c->sym ? check_status(c, (int64_t)c->set_kii.all.size(), c->set_kii.all, &bad)
+              : check_status(c, (int64_t)c->gj_kii.size(), c->gj_kii, &bad);
   if (st) {
     c->last_bad = bad;
     return st;
@@ -1030,9 +1157,9 @@ int factor_impl(mbddc_ctx* c) {
     }
     {
       ProfScope ps(c, F_GJ_P, 0.0, c->fam_flops[F_GJ_P]);
-      CHK(run_sym<T>(c, W, c->d_gj_x, (int64_t)c->gj_x.size(), maxG, c->d_status));
+      CHK(run_symset<T>(c, W, c->set_x));
     }
-    st = check_status(c, (int64_t)c->gj_x.size(), c->gj_x, &bad);
+    st = check_status(c, (int64_t)c->set_x.all.size(), c->set_x.all, &bad);
     if (st) {
       c->last_bad = bad;
       return st;
@@ -1042,16 +1169,14 @@ int factor_impl(mbddc_ctx* c) {
       hipLaunchKernelGGL((k_constraint_products<T>), dim3(nsub), dim3(kBlock), 0, c->stream, c->d_subs,
                          c->d_cons_ptr, c->d_cons_idx, c->d_cons_w, W);
       HIPCHK(hipGetLastError());
-      int maxt = 1;
-      for (const GjDesc& g : c->gj_t) maxt = std::max(maxt, g.n);
-      CHK(run_sym<T>(c, W, c->d_gj_t, (int64_t)c->gj_t.size(), maxt, c->d_status));
-      st = check_status(c, (int64_t)c->gj_t.size(), c->gj_t, &bad);
+      CHK(run_symset<T>(c, W, c->set_t));
+      st = check_status(c, (int64_t)c->set_t.all.size(), c->set_t.all, &bad);
       if (st) {
         c->last_bad = bad;
         return st;
       }
-      hipLaunchKernelGGL((k_tinv_finish<T>), dim3((unsigned)c->gj_t.size()), dim3(kBlock), 0, c->stream, c->d_subs,
-                         c->d_gj_t, c->d_rho, W, c->d_Kcl);
+      hipLaunchKernelGGL((k_tinv_finish<T>), dim3((unsigned)c->set_t.all.size()), dim3(kBlock), 0, c->stream,
+                         c->d_subs, c->set_t.d_all, c->d_rho, W, c->d_Kcl);
       if (!c->gemm_items_phi.empty())
         hipLaunchKernelGGL((k_gemm_batched<T>), dim3((unsigned)c->gemm_items_phi.size()), dim3(kBlock), 0,
                            c->stream, c->d_gemm_desc, c->d_gemm_phi, W, W, W, W);
@@ -1154,7 +1279,8 @@ int apply_impl(mbddc_ctx* c, const double* r, double* z) {
   a.inst_nchunk = c->d_inst_nchunk; a.op = c->d_Op; a.kcinv = c->d_Kc; a.inst_kc_off = c->d_inst_kc_off;
   a.inst_kc_ld = c->d_inst_kc_ld; a.inst_coarse_off = c->d_inst_coarse_off; a.inst_nc = c->d_inst_nc;
   a.r = r; a.z = z; a.tb = c->d_tb; a.wb = c->d_wb; a.cc = c->d_cc; a.ep = c->d_ep; a.n_coarse = P.n_coarse;
-  const size_t lds_local = (size_t)(4 * 256 * R + (size_t)c->max_cols * R) * sizeof(double);
+  a.xchunk = std::min(c->max_cols, kApplyChunk);
+  const size_t lds_local = (size_t)(4 * 256 * R + (size_t)a.xchunk * R) * sizeof(double);
   static std::once_flag attr_once;   // one attribute setting per instantiation, thread-safe
   static int attr_st = MBDDC_OK;
   std::call_once(attr_once, [] {

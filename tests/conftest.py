@@ -41,6 +41,19 @@ def problem(name: str):
         return Problem("l3_ragged", mesh, part, nsub, dirichlet, Ke, rhs, 1, {})
     if name == "vent":             # Q2 ventricle-like shell, Guccione fibres, RCB parts <= 480 DOFs
         return W.ventricle(2, 16, 8, 2, target_dofs=480, nrhs=2, primal=7, name="vent")
+    if name == "large_q1":         # 16^3 Q1, 2x2x2 subdomains of 8^3: local blocks of 600-1536 DOFs
+        return W.linear_box(16, 8, 1, nrhs=2, primal=3, name="large_q1")
+    if name == "large_mixed":      # 14x10x12 Q1 neo-Hookean, blocks of 8: interiors of 144-1344 DOFs
+        from paper_2208_06191_amd.workloads import Problem
+        mesh = W.box_mesh(14, 10, 12, 1)
+        part, nsub = W.block_partition(mesh, 8)
+        dirichlet = W.clamp_dofs(mesh, 1)
+        u = W.isochoric_field(mesh.coords, 4, 0.02)
+        Ke = W.element_tangents(mesh, W.neo_hookean(1.0, 50.0), u)
+        rhs = W._loads(mesh, dirichlet, 2, 7)
+        return Problem("large_mixed", mesh, part, nsub, dirichlet, Ke, rhs, 3, {})
+    if name == "vent_large":       # Q2 ventricle-like shell, RCB parts <= 2500 DOFs
+        return W.ventricle(2, 16, 8, 2, target_dofs=2500, nrhs=1, primal=7, name="vent_large")
     if name == "ragged":           # 6x5x7 Q1 box, blocks of 4 -> uneven subdomains
         from paper_2208_06191_amd.workloads import Problem
         mesh = W.box_mesh(6, 5, 7, 1)
