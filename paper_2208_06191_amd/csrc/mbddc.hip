@@ -411,7 +411,8 @@ int build_layout(mbddc_ctx* c) {
     if (c->sym && c->fact32 && std::max(std::max(nI, nG), nc) > sym_onewg_max<float>()) return MBDDC_ERR_UNSUPPORTED;
     d.oK = w; w += round_up(ni * ni, 64);
     d.oG = w; w += round_up(nG * nI, 64);
-    d.oH = w; w += round_up(nI * nG, 64);
+    d.oH = w;
+    if (!c->sym) w += round_up(nI * nG, 64);   // H = G^T on the symmetric path, never formed
     d.oP = w; w += round_up(m * m, 64);
     d.ld1 = (int32_t)round_up(nI + nG, 4);
     d.ld2 = (int32_t)round_up(nG + nc, 4);

@@ -54,6 +54,8 @@ def problem(name: str):
         return Problem("large_mixed", mesh, part, nsub, dirichlet, Ke, rhs, 3, {})
     if name == "vent_large":       # Q2 ventricle-like shell, RCB parts <= 2500 DOFs
         return W.ventricle(2, 16, 8, 2, target_dofs=2500, nrhs=1, primal=7, name="vent_large")
+    if name == "vent_parts6k":     # the shell at 1/16 of the full mesh, RCB parts of 2k-5.7k DOFs as at full size
+        return W.ventricle(4, 24, 24, 2, target_dofs=6000, nrhs=1, primal=7, name="vent_parts6k")
     if name == "ragged":           # 6x5x7 Q1 box, blocks of 4 -> uneven subdomains
         from paper_2208_06191_amd.workloads import Problem
         mesh = W.box_mesh(6, 5, 7, 1)

@@ -22,7 +22,9 @@ pytestmark = pytest.mark.gpu
 TOL_APPLY = {mbddc.MBDDC_FP64: 1e-12, mbddc.MBDDC_MIXED: 1e-5}
 TOL_COARSE = 1e-12
 PRECS = [mbddc.MBDDC_FP64, mbddc.MBDDC_MIXED]
-CASES = [("large_q1", 3), ("large_mixed", 3), ("vent_large", 7)]
+# vent_parts6k: the Q2 shell at 1/16 of the full mesh (63.5k DOFs) whose RCB parts have the
+# full-size shape (2k-5.7k DOFs, interiors up to 4.4k)
+CASES = [("large_q1", 3), ("large_mixed", 3), ("vent_large", 7), ("vent_parts6k", 7)]
 ONE_WG_MAX = 304          # largest matrix of the register-resident sweep
 
 
@@ -58,6 +60,8 @@ def test_local_blocks_exceed_one_workgroup(name, primal):
     assert nI.max() > ONE_WG_MAX and nG.max() > ONE_WG_MAX
     if name == "large_q1":
         assert nI.max() > 1024            # more than one staged chunk in the apply
+    if name == "vent_parts6k":
+        assert nI.max() > 4000 and (nI + nG).max() > 5000
     if name == "large_mixed":             # both sweeps in one factorisation
         assert nI.min() <= ONE_WG_MAX and nG.min() <= ONE_WG_MAX
 
