@@ -102,6 +102,11 @@ typedef struct {
                                     the fine subdomains with their matrices Phi_i^T A^(i) Phi_i;
                                     level-2 globs use the fine glob's first-node boundary tags.
                                     Level 2 and 3 are always computed in FP64. */
+  int32_t graph_apply;           /* 1 (default): GMRES replays the preconditioner application (every
+                                    phase, all levels) as an instantiated HIP graph captured on the
+                                    handle's stream at the first iteration for each right-hand-side
+                                    width; recaptured when the handle's apply buffers move. Applies
+                                    whose families are being profiled run eagerly. 0: eager launches */
 } mbddc_options;
 
 typedef struct {
@@ -112,6 +117,8 @@ typedef struct {
   double rel_res_true;           /* max over systems of ||b - K x|| / ||b|| (FP64) */
   double rel_res_est;
   double ms_setup, ms_factor, ms_solve;
+  int32_t applies;               /* preconditioner applications of the call */
+  int32_t applies_graphed;       /* of which replayed from a captured HIP graph */
 } mbddc_info;
 
 typedef struct {

@@ -249,6 +249,11 @@ struct mbddc_ctx {
   int Y_R = 0;                   // layout (R) of the apply output block currently in d_Y
   double* d_ep = nullptr;
   double *d_X = nullptr, *d_Y = nullptr, *d_io = nullptr;
+  int64_t apply_gen = 0;                 // bumped whenever the apply's buffers move
+  hipStream_t cap_stream = nullptr;      // capture stream of the apply graphs (default priority)
+  hipGraphExec_t apply_exec[4] = {};     // captured d_X -> d_Y applies per width R = 1, 2, 4, 8
+  int64_t apply_exec_gen[4] = {};
+  int32_t n_applies = 0, n_applies_graphed = 0;
   // Krylov buffers
   int R_kry = 0, restart_kry = 0;
   double *d_V = nullptr, *d_Z = nullptr, *d_Wv = nullptr, *d_B = nullptr, *d_x = nullptr, *d_r = nullptr;
@@ -318,6 +323,12 @@ void free_all(mbddc_ctx* c) {
   c->prof.pending.clear();
   for (hipEvent_t e : c->prof.pool) (void)hipEventDestroy(e);
   c->prof.pool.clear();
+  for (hipGraphExec_t& g : c->apply_exec) {
+    if (g) (void)hipGraphExecDestroy(g);
+    g = nullptr;
+  }
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+  c->cap_stream = nullptr;
   if (c->ev_a) (void)hipEventDestroy(c->ev_a);
   if (c->ev_b) (void)hipEventDestroy(c->ev_b);
   if (c->aux) (void)hipStreamDestroy(c->aux);
@@ -862,6 +873,7 @@ int ensure_apply_buffers(mbddc_ctx* c, int R) {
   HIPCHK(hipMemsetAsync(c->d_Y, 0, P.n_dofs * R * sizeof(double), c->stream));
   c->R_alloc = R;
   c->Y_R = R;
+  c->apply_gen++;
   return MBDDC_OK;
 }
 
@@ -1184,7 +1196,8 @@ int factor_impl(mbddc_ctx* c) {
       if (!c->gemm_items_stil.empty())
         hipLaunchKernelGGL((k_gemm_batched<T>), dim3((unsigned)c->gemm_items_stil.size()), dim3(kBlock), 0,
                            c->stream, c->d_gemm_desc, c->d_gemm_stil, W, W, W, W);
-      hipLaunchKernelGGL((k_extract_sym<T, To>), dim3(nsub), dim3(kBlock), 0, c->stream, c->d_subs, c->d_slot_w, W,
+      const unsigned parts = (unsigned)std::min(64, std::max(1, (c->max_cols + 127) / 128));
+      hipLaunchKernelGGL((k_extract_sym<T, To>), dim3(parts, nsub), dim3(kBlock), 0, c->stream, c->d_subs, c->d_slot_w, W,
                          Op);
     }
     HIPCHK(hipGetLastError());
@@ -1271,6 +1284,9 @@ int factor_impl(mbddc_ctx* c) {
 // preconditioner application and operator product on interleaved blocks
 // ----------------------------------------------------------------------------
 template <typename To, int R>
+int apply_attrs();
+
+template <typename To, int R>
 int apply_impl(mbddc_ctx* c, const double* r, double* z) {
   const Plan& P = c->plan;
   ApplyArgs a{};
@@ -1282,18 +1298,7 @@ int apply_impl(mbddc_ctx* c, const double* r, double* z) {
   a.r = r; a.z = z; a.tb = c->d_tb; a.wb = c->d_wb; a.cc = c->d_cc; a.ep = c->d_ep; a.n_coarse = P.n_coarse;
   a.xchunk = std::min(c->max_cols, kApplyChunk);
   const size_t lds_local = (size_t)(4 * 256 * R + (size_t)a.xchunk * R) * sizeof(double);
-  static std::once_flag attr_once;   // one attribute setting per instantiation, thread-safe
-  static int attr_st = MBDDC_OK;
-  std::call_once(attr_once, [] {
-    const size_t mx = 160 * 1024;
-    int st = set_lds(k_apply_local<To, R, 0>, mx);
-    if (!st) st = set_lds(k_apply_local<To, R, 1>, mx);
-    if (!st) st = set_lds(k_apply_local<To, R, 3>, mx);
-    if (!st) st = set_lds(k_apply_local<To, R, 4>, mx);
-    if (!st) st = set_lds(k_apply_coarse<To, R>, mx);
-    attr_st = st;
-  });
-  CHK(attr_st);
+  CHK((apply_attrs<To, R>()));
   if (lds_local > 160 * 1024) return MBDDC_ERR_UNSUPPORTED;
   {
     ProfScope ps(c, F_APPLY_A, c->op_bytes[F_APPLY_A] + 8.0 * R * c->vec_words[F_APPLY_A], 2.0 * R * c->fam_flops[F_APPLY_A]);
@@ -1356,6 +1361,83 @@ int apply_dispatch(mbddc_ctx* c, int R, const double* r, double* z) {
     case 4: return apply_impl<double, 4>(c, r, z);
     default: return apply_impl<double, 8>(c, r, z);
   }
+}
+
+// LDS attributes of the apply kernels for width R (set once per instantiation; outside
+// any stream capture)
+template <typename To, int R>
+int apply_attrs() {
+  static std::once_flag once;
+  static int st = MBDDC_OK;
+  std::call_once(once, [] {
+    const size_t mx = 160 * 1024;
+    int e = set_lds(k_apply_local<To, R, 0>, mx);
+    if (!e) e = set_lds(k_apply_local<To, R, 1>, mx);
+    if (!e) e = set_lds(k_apply_local<To, R, 3>, mx);
+    if (!e) e = set_lds(k_apply_local<To, R, 4>, mx);
+    if (!e) e = set_lds(k_apply_coarse<To, R>, mx);
+    st = e;
+  });
+  return st;
+}
+
+int apply_attrs_all(int R) {
+  switch (R) {
+    case 1: CHK((apply_attrs<float, 1>())); return apply_attrs<double, 1>();
+    case 2: CHK((apply_attrs<float, 2>())); return apply_attrs<double, 2>();
+    case 4: CHK((apply_attrs<float, 4>())); return apply_attrs<double, 4>();
+    default: CHK((apply_attrs<float, 8>())); return apply_attrs<double, 8>();
+  }
+}
+
+constexpr uint32_t kApplyFamilies = (1u << F_APPLY_A) | (1u << F_APPLY_C) | (1u << F_APPLY_E) | (1u << F_APPLY_F) |
+                                    (1u << F_APPLY_H) | (1u << F_LEVEL2_APPLY);
+
+// z = M^-1 r on the handle's fixed blocks d_X -> d_Y: replayed from a captured graph
+// unless graphs are off or an apply family is being profiled.
+int apply_run(mbddc_ctx* c, int R) {
+  c->n_applies++;
+  const bool profiled = (c->prof.mask & kApplyFamilies) || (c->child && (c->child->prof.mask & kApplyFamilies));
+  if (!c->opt.graph_apply || profiled) return apply_dispatch(c, R, c->d_X, c->d_Y);
+  const int slot = R == 1 ? 0 : (R == 2 ? 1 : (R == 4 ? 2 : 3));
+  const int64_t gen = c->apply_gen + (c->child ? c->child->apply_gen : 0);
+  hipGraphExec_t& ex = c->apply_exec[slot];
+  if (ex && c->apply_exec_gen[slot] != gen) {
+    HIPCHK(hipGraphExecDestroy(ex));
+    ex = nullptr;
+  }
+  if (!ex) {
+    CHK(apply_attrs_all(R));
+    // captured on a private stream (the handle's stream may be the legacy default stream,
+    // which cannot be captured); the graph is then launched on the handle's stream
+    if (!c->cap_stream) HIPCHK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    hipStream_t user = c->stream;
+    c->stream = c->cap_stream;
+    if (c->child) c->child->stream = c->cap_stream;
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal);
+    int st = MBDDC_OK;
+    if (e == hipSuccess) {
+      st = apply_dispatch(c, R, c->d_X, c->d_Y);
+      e = hipStreamEndCapture(c->cap_stream, &g);
+    }
+    c->stream = user;
+    if (c->child) c->child->stream = user;
+    if (st != MBDDC_OK || e != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return st != MBDDC_OK ? st : MBDDC_ERR_DEVICE;
+    }
+    const hipError_t e2 = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e2 != hipSuccess) {
+      ex = nullptr;
+      return MBDDC_ERR_DEVICE;
+    }
+    c->apply_exec_gen[slot] = gen;
+  }
+  HIPCHK(hipGraphLaunch(ex, c->stream));
+  c->n_applies_graphed++;
+  return MBDDC_OK;
 }
 
 int spmv_dispatch(mbddc_ctx* c, int R, const double* x, double* y) {
@@ -1502,7 +1584,7 @@ int gmres_impl(mbddc_ctx* c, int nrhs, mbddc_info* info) {
       hipLaunchKernelGGL((k_next_vector<R>), dim3(gv), dim3(kBlock), 0, c->stream, ka, c->d_V, c->d_Wv, c->d_jsys,
                          c->d_mode, c->d_hnorm, c->d_dof_inst, c->d_X);
     }
-    CHK(apply_dispatch(c, R, c->d_X, c->d_Y));
+    CHK(apply_run(c, R));
     {
       ProfScope ps(c, F_KRYLOV_VEC, 2.0 * vbytes, 0.0);
       hipLaunchKernelGGL((k_store_z<R>), dim3(gv), dim3(kBlock), 0, c->stream, ka, c->d_Y, c->d_Z, c->d_jsys,
@@ -1669,6 +1751,7 @@ int mbddc_default_options(mbddc_options* opt) {
   opt->restart = 30;
   opt->rtol = 1e-8;
   opt->max_it = 1000;
+  opt->graph_apply = 1;
   return MBDDC_OK;
 }
 
@@ -1888,7 +1971,7 @@ int mbddc_apply(mbddc_ctx* c, int nrhs, const double* r, double* z, int on_devic
   const int R = apply_R(nrhs);
   CHK(ensure_apply_buffers(c, R));
   CHK(load_block(c, r, nrhs, R, on_device, c->d_X));
-  CHK(apply_dispatch(c, R, c->d_X, c->d_Y));
+  CHK(apply_run(c, R));
   return store_block(c, c->d_Y, nrhs, R, on_device, z);
 }
 
@@ -1912,11 +1995,14 @@ int mbddc_solve(mbddc_ctx* c, int nrhs, const double* b, double* x, int on_devic
   CHK(ensure_apply_buffers(c, R));
   CHK(ensure_krylov(c, R));
   CHK(load_block(c, b, nrhs, R, on_device, c->d_B));
+  c->n_applies = c->n_applies_graphed = 0;
   int st = gmres_dispatch(c, R, nrhs, info);
   int st2 = store_block(c, c->d_x, nrhs, R, on_device, x);
   if (info) {
     info->ms_solve = now_ms() - t0;
     info->bad_subdomain = 0;
+    info->applies = c->n_applies;
+    info->applies_graphed = c->n_applies_graphed;
   }
   return st != MBDDC_OK ? st : st2;
 }

@@ -41,14 +41,15 @@ class mbddc_options(ctypes.Structure):
     _fields_ = [("primal", ctypes.c_uint32), ("levels", ctypes.c_int32), ("coarse_group", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("restart", ctypes.c_int32), ("rtol", ctypes.c_double),
                 ("max_it", ctypes.c_int32), ("symmetric_hint", ctypes.c_int32), ("tune_table", ctypes.c_char_p),
-                ("keep_coarse_matrix", ctypes.c_int32), ("coarse_primal", ctypes.c_uint32)]
+                ("keep_coarse_matrix", ctypes.c_int32), ("coarse_primal", ctypes.c_uint32),
+                ("graph_apply", ctypes.c_int32)]
 
 
 class mbddc_info(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int32), ("restarts", ctypes.c_int32), ("status", ctypes.c_int32),
                 ("bad_subdomain", ctypes.c_int32), ("rel_res_true", ctypes.c_double),
                 ("rel_res_est", ctypes.c_double), ("ms_setup", ctypes.c_double), ("ms_factor", ctypes.c_double),
-                ("ms_solve", ctypes.c_double)]
+                ("ms_solve", ctypes.c_double), ("applies", ctypes.c_int32), ("applies_graphed", ctypes.c_int32)]
 
 
 class mbddc_sizes(ctypes.Structure):

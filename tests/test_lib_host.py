@@ -36,6 +36,7 @@ def test_default_options():
     o = mbddc.default_options()
     assert (o.primal, o.levels, o.precision, o.restart, o.rtol, o.max_it) == (3, 2, 1, 30, 1e-8, 1000)
     assert (o.coarse_group, o.coarse_primal) == (8, 7)
+    assert o.graph_apply == 1
 
 
 def _compare_plan(P, primal):
