@@ -93,7 +93,9 @@ typedef struct {
                                     local problems, coarse problems SPD or mildly indefinite;
                                     0: general path with partial pivoting (the paper's symmetry
                                     flag, §4 and §6.1) */
-  const char* tune_table;        /* reserved, may be NULL */
+  const char* tune_table;        /* path of a tuning table written by mbddc_autotune (read during
+                                    mbddc_setup_symbolic; MBDDC_ERR_ARG if unreadable or malformed),
+                                    or NULL for the built-in choices */
   int32_t keep_coarse_matrix;    /* 1: keep S_PiPi for mbddc_get_coarse_matrix (8 n_c^2 bytes) */
   uint32_t coarse_primal;        /* levels = 3: primal globs of the level-2 decomposition
                                     (MBDDC_PRIMAL_* bitmask; default V|E|F). Level-2 nodes are the
@@ -235,6 +237,22 @@ int mbddc_set_profiling(mbddc_ctx* ctx, uint32_t family_mask);
 /* Name of profiler family f (bit f of the mask), NULL past the last one. */
 const char* mbddc_profile_family_name(int family);
 int mbddc_get_profile(mbddc_ctx* ctx, mbddc_kernel_stat* out, int max_entries, int* n_entries);
+
+/* Autotuner (kernel variants per size bucket, chosen on this handle's own matrices).
+ * For every size bucket that occurs among the local symmetric inversions (n <= 128, <= 304,
+ * <= 598, larger) each kernel variant that can take the bucket's matrices is timed by a full
+ * numeric factorisation (best of two): 0 register-resident sweep (FP64, n <= 304), 1 one-
+ * workgroup sweep with 16-index panels in LDS, 2 the same with 32-index panels, 3 batched
+ * blocked sweep (FP64); then the number of input columns the apply stages in LDS (128, 256,
+ * 512 or 1024) by timing applies of four right-hand sides. Needs a tangent (state >= set_tangent)
+ * and leaves the handle factorised with the chosen table. table_out (may be NULL): JSON file
+ *   {"mbddc_tune": 1, "sym_fp64": [v0, v1, v2, v3], "sym_fp32": [v0, v1, v2, v3], "apply_xchunk": C}
+ * (plus informative keys), to be passed as options.tune_table to later handles. A table variant
+ * that cannot take some matrix (size or precision) falls back to one that can. Errors as
+ * mbddc_factor; MBDDC_ERR_ARG if table_out cannot be written. */
+int mbddc_autotune(mbddc_ctx* ctx, const char* table_out);
+/* The handle's table: sym_fp64[4], sym_fp32[4] (may be NULL), apply_xchunk (may be NULL). */
+int mbddc_get_tuning(const mbddc_ctx* ctx, int32_t* sym_fp64, int32_t* sym_fp32, int32_t* apply_xchunk);
 
 /* Subdomain of the last MBDDC_ERR_SINGULAR (-1: coarse problem; see mbddc_factor). */
 int mbddc_last_bad_subdomain(const mbddc_ctx* ctx);

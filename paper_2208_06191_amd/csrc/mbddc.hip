@@ -97,18 +97,59 @@ struct Profiler {
 
 namespace mbddc {
 
-// Largest matrix of the one-workgroup symmetric sweeps: both 16-index panel buffers in LDS.
+// Largest matrix of the one-workgroup symmetric sweeps with panels of BP indices (both
+// panel buffers in LDS).
 template <typename T>
-constexpr int sym_onewg_max() { return (int)((159 * 1024) / (2 * 17 * sizeof(T))); }
+constexpr int sym_onewg_max(int bp = 16) { return (int)((159 * 1024) / (2 * (bp + 1) * sizeof(T))); }
 
-// One family of symmetric inversions (K_II, S + rho C^T C or T over all subdomains).
-// FP64 matrices larger than the register-resident sweep take the batched blocked
-// sweep; the others take the one-workgroup kernels. Status slots: the one-workgroup
-// matrices first (slot = position), then the blocked ones (sorted by size, descending).
+// Kernels for one symmetric inversion: register-resident (FP64, n <= 304), one workgroup
+// with 16- or 32-index panels in LDS, or the batched blocked sweep (FP64).
+enum SymVariant { SV_REG = 0, SV_BP16 = 1, SV_BP32 = 2, SV_BLOCKED = 3, SV_COUNT = 4 };
+const char* const kSymVariantName[SV_COUNT] = {"register", "lds16", "lds32", "blocked"};
+// Size buckets of the tuning table: n <= 128, <= 304, <= 598, larger.
+constexpr int kSymBuckets = 4;
+constexpr int kSymBucketMax[kSymBuckets] = {128, 304, 598, 1 << 30};
+inline int sym_bucket(int n) {
+  int b = 0;
+  while (b < kSymBuckets - 1 && n > kSymBucketMax[b]) ++b;
+  return b;
+}
+
+// Tuning table: per precision and size bucket the inversion variant, and the number of
+// input columns the apply stages in LDS at a time.
+struct Tuning {
+  int32_t sym[2][kSymBuckets];      // [0] FP64, [1] FP32
+  int32_t xchunk;
+  Tuning() {
+    const int d64[kSymBuckets] = {SV_REG, SV_REG, SV_BLOCKED, SV_BLOCKED};
+    const int d32[kSymBuckets] = {SV_BP32, SV_BP32, SV_BP16, SV_BP16};
+    for (int b = 0; b < kSymBuckets; ++b) {
+      sym[0][b] = d64[b];
+      sym[1][b] = d32[b];
+    }
+    xchunk = kApplyChunk;
+  }
+};
+
+// Whether variant v can invert every matrix of size n in the given precision.
+inline bool sym_variant_ok(int v, int n, bool fp32) {
+  switch (v) {
+    case SV_REG: return !fp32 && n <= kSymRegMax;
+    case SV_BP16: return n <= (fp32 ? sym_onewg_max<float>(16) : sym_onewg_max<double>(16));
+    case SV_BP32: return n <= (fp32 ? sym_onewg_max<float>(32) : sym_onewg_max<double>(32));
+    case SV_BLOCKED: return !fp32;
+    default: return false;
+  }
+}
+
+// One family of symmetric inversions (K_II, S + rho C^T C or T over all subdomains),
+// grouped by kernel variant. Status slots follow the descriptor order of `all`: the
+// one-workgroup groups (register, lds16, lds32), then the blocked matrices (sorted by
+// size, descending, so that those still active at a step form a prefix).
 struct SymSet {
   std::vector<GjDesc> all;          // descriptors in status-slot order
-  int64_t n_small = 0;
-  int small_maxn = 1;
+  int64_t grp_off[SV_COUNT + 1] = {};   // [grp_off[v], grp_off[v+1]) of `all` use variant v
+  int grp_maxn[SV_COUNT] = {};
   std::vector<BigSym> big;
   std::vector<int2> items;          // (matrix, lower 64-tile) of the update and finish
   std::vector<int64_t> item_off;    // [big.size() + 1]
@@ -122,30 +163,40 @@ struct SymSet {
   GemmDesc* d_gd = nullptr;
   GemmItem* d_gitems = nullptr;
 
-  void build(const std::vector<GjDesc>& src, bool allow_big) {
+  // Returns false when some matrix has no usable variant (FP32 beyond the LDS kernels).
+  bool build(const std::vector<GjDesc>& src, bool fp32, const Tuning& tune) {
     all.clear(); big.clear(); items.clear(); gd.clear(); gitems.clear();
     item_off.assign(1, 0);
     gitem_off.assign(1, 0);
-    std::vector<GjDesc> large;
-    small_maxn = 1;
+    std::vector<GjDesc> grp[SV_COUNT];
     for (const GjDesc& g : src) {
-      if (allow_big && g.n > kSymRegMax) {
-        large.push_back(g);
-      } else {
+      int v = tune.sym[fp32 ? 1 : 0][sym_bucket(g.n)];
+      if (!sym_variant_ok(v, g.n, fp32)) {   // the table's choice cannot take this one
+        v = -1;
+        for (int u : {SV_REG, SV_BP32, SV_BP16, SV_BLOCKED})
+          if (sym_variant_ok(u, g.n, fp32)) { v = u; break; }
+        if (v < 0) return false;
+      }
+      grp[v].push_back(g);
+    }
+    std::stable_sort(grp[SV_BLOCKED].begin(), grp[SV_BLOCKED].end(),
+                     [](const GjDesc& a, const GjDesc& b) { return a.n > b.n; });
+    for (int v = 0; v < SV_COUNT; ++v) {
+      grp_off[v] = (int64_t)all.size();
+      grp_maxn[v] = 1;
+      for (const GjDesc& g : grp[v]) {
         all.push_back(g);
-        small_maxn = std::max(small_maxn, g.n);
+        grp_maxn[v] = std::max(grp_maxn[v], g.n);
       }
     }
-    n_small = (int64_t)all.size();
-    std::stable_sort(large.begin(), large.end(), [](const GjDesc& a, const GjDesc& b) { return a.n > b.n; });
+    grp_off[SV_COUNT] = (int64_t)all.size();
     pbuf_elems = 0;
-    for (const GjDesc& g : large) {
+    for (const GjDesc& g : grp[SV_BLOCKED]) {
       const int32_t j = (int32_t)big.size();
       BigSym b{};
-      b.off = g.off; b.n = g.n; b.ld = g.ld; b.stat = (int32_t)(n_small + j); b.pw = pbuf_elems;
+      b.off = g.off; b.n = g.n; b.ld = g.ld; b.stat = (int32_t)(grp_off[SV_BLOCKED] + j); b.pw = pbuf_elems;
       pbuf_elems += 2LL * g.n * kSymCB;
       big.push_back(b);
-      all.push_back(g);
       const int nt = (g.n + kUpdTile - 1) / kUpdTile;
       for (int t = 0; t < nt * (nt + 1) / 2; ++t) items.push_back(make_int2(j, t));
       item_off.push_back((int64_t)items.size());
@@ -158,6 +209,7 @@ struct SymSet {
         for (int bb = 0; bb < m.tiles_n; ++bb) gitems.push_back({j, a, bb, 0});
       gitem_off.push_back((int64_t)gitems.size());
     }
+    return true;
   }
 };
 
@@ -186,6 +238,7 @@ struct mbddc_ctx {
   std::vector<GjDesc> gj_x;                          // (S + rho C^T C) blocks of the symmetric path
   std::vector<GjDesc> gj_t;                          // T = C X C^T blocks too large for LDS (symmetric path)
   SymSet set_kii, set_x, set_t;                      // symmetric path: the three inversion families
+  Tuning tune;                                       // kernel variants (tuning table or defaults)
   int64_t big_pbuf = 0, big_count = 0;               // batched blocked sweep: panel elements, matrices
   bool sym = false;                                  // symmetric (SPD) factor path
   std::vector<ApplyItem> itA, itC, itE, itF, itH;
@@ -419,7 +472,6 @@ int build_layout(mbddc_ctx* c) {
     // the pivoting path inverts in one workgroup; the symmetric path sweeps larger FP64
     // matrices with the batched blocked kernels, larger FP32 ones not at all
     if (!c->sym && std::max<int64_t>(nI, m) > kGjMax) return MBDDC_ERR_UNSUPPORTED;
-    if (c->sym && c->fact32 && std::max(std::max(nI, nG), nc) > sym_onewg_max<float>()) return MBDDC_ERR_UNSUPPORTED;
     d.oK = w; w += round_up(ni * ni, 64);
     d.oG = w; w += round_up(nG * nI, 64);
     d.oH = w;
@@ -510,11 +562,9 @@ int build_layout(mbddc_ctx* c) {
   add_items(dSs, c->gemm_items_ssym);
   add_items(dPhi, c->gemm_items_phi);
   add_items(dStil, c->gemm_items_stil);
-  if (c->sym) {
-    c->set_kii.build(c->gj_kii, !c->fact32);
-    c->set_x.build(c->gj_x, !c->fact32);
-    c->set_t.build(c->gj_t, !c->fact32);
-  }
+  if (c->sym && !(c->set_kii.build(c->gj_kii, c->fact32, c->tune) && c->set_x.build(c->gj_x, c->fact32, c->tune) &&
+                  c->set_t.build(c->gj_t, c->fact32, c->tune)))
+    return MBDDC_ERR_UNSUPPORTED;
   c->big_pbuf = std::max(std::max(c->set_kii.pbuf_elems, c->set_x.pbuf_elems), c->set_t.pbuf_elems);
   c->big_count = (int64_t)std::max(std::max(c->set_kii.big.size(), c->set_x.big.size()), c->set_t.big.size());
   c->w_elems = w;
@@ -804,6 +854,7 @@ int build_level2_host(mbddc_ctx* c, const std::vector<MeshIn>& fine) {
   ch->mixed = false;
   ch->fact32 = false;
   ch->sym = c->sym;
+  ch->tune = c->tune;
   if (!build_plan(m2, ch->opt.primal, ch->plan).empty()) return MBDDC_ERR_ARG;
   return build_layout(ch);
 }
@@ -930,7 +981,23 @@ int run_sym(mbddc_ctx* c, T* base, const GjDesc* d_desc, int64_t count, int maxn
 // inverse written); statuses land in the set's slots.
 template <typename T>
 int run_symset(mbddc_ctx* c, T* base, const SymSet& S) {
-  if (S.n_small > 0) CHK(run_sym<T>(c, base, S.d_all, S.n_small, S.small_maxn, c->d_status));
+  for (int v : {SV_REG, SV_BP16, SV_BP32}) {
+    const int64_t cnt = S.grp_off[v + 1] - S.grp_off[v];
+    if (cnt == 0) continue;
+    const GjDesc* d = S.d_all + S.grp_off[v];
+    int32_t* st = c->d_status + S.grp_off[v];
+    if (v == SV_REG) {
+      if (sizeof(T) != 8) return MBDDC_ERR_UNSUPPORTED;
+      CHK(set_lds(k_sym_inv_reg, kSymRegLds));
+      hipLaunchKernelGGL(k_sym_inv_reg, dim3((unsigned)cnt), dim3(kSymRegThreads), kSymRegLds, c->stream,
+                         reinterpret_cast<double*>(base), d, st);
+      HIPCHK(hipGetLastError());
+    } else if (v == SV_BP16) {
+      CHK((launch_sym<T, 16, false>(c, base, d, cnt, S.grp_maxn[v], st)));
+    } else {
+      CHK((launch_sym<T, 32, false>(c, base, d, cnt, S.grp_maxn[v], st)));
+    }
+  }
   if (S.big.empty()) return MBDDC_OK;
   if (sizeof(T) != 8) return MBDDC_ERR_UNSUPPORTED;
   double* A = reinterpret_cast<double*>(base);
@@ -1296,7 +1363,7 @@ int apply_impl(mbddc_ctx* c, const double* r, double* z) {
   a.inst_nchunk = c->d_inst_nchunk; a.op = c->d_Op; a.kcinv = c->d_Kc; a.inst_kc_off = c->d_inst_kc_off;
   a.inst_kc_ld = c->d_inst_kc_ld; a.inst_coarse_off = c->d_inst_coarse_off; a.inst_nc = c->d_inst_nc;
   a.r = r; a.z = z; a.tb = c->d_tb; a.wb = c->d_wb; a.cc = c->d_cc; a.ep = c->d_ep; a.n_coarse = P.n_coarse;
-  a.xchunk = std::min(c->max_cols, kApplyChunk);
+  a.xchunk = std::min(c->max_cols, c->tune.xchunk);
   const size_t lds_local = (size_t)(4 * 256 * R + (size_t)a.xchunk * R) * sizeof(double);
   CHK((apply_attrs<To, R>()));
   if (lds_local > 160 * 1024) return MBDDC_ERR_UNSUPPORTED;
@@ -1812,8 +1879,49 @@ int parse_meshes(int n_inst, const mbddc_mesh* meshes, const mbddc_options* opt,
 }
 
 // Host part of the symbolic setup: plan, layout and (three levels) the level-2 plan.
+// Reads a tuning table written by mbddc_autotune (the format is documented in mbddc.h).
+int read_tuning(const char* path, Tuning& t) {
+  FILE* f = std::fopen(path, "rb");
+  if (!f) return MBDDC_ERR_ARG;
+  std::string text;
+  char buf[4096];
+  size_t k;
+  while ((k = std::fread(buf, 1, sizeof(buf), f)) > 0 && text.size() < (1u << 20)) text.append(buf, k);
+  std::fclose(f);
+  if (text.find("\"mbddc_tune\"") == std::string::npos) return MBDDC_ERR_ARG;
+  auto ints_after = [&](const char* key, int32_t* out, int n) -> bool {
+    size_t p = text.find(key);
+    if (p == std::string::npos) return false;
+    p = text.find(':', p);
+    if (p == std::string::npos) return false;
+    const char* q = text.c_str() + p + 1;
+    for (int i = 0; i < n; ++i) {
+      while (*q == ' ' || *q == '\t' || *q == '\n' || *q == '\r' || *q == '[' || (i > 0 && *q == ',')) ++q;
+      char* e = nullptr;
+      const long v = std::strtol(q, &e, 10);
+      if (e == q) return false;
+      out[i] = (int32_t)v;
+      q = e;
+    }
+    return true;
+  };
+  Tuning r;
+  if (!ints_after("\"sym_fp64\"", r.sym[0], kSymBuckets) || !ints_after("\"sym_fp32\"", r.sym[1], kSymBuckets) ||
+      !ints_after("\"apply_xchunk\"", &r.xchunk, 1))
+    return MBDDC_ERR_ARG;
+  for (int p = 0; p < 2; ++p)
+    for (int b = 0; b < kSymBuckets; ++b)
+      if (r.sym[p][b] < 0 || r.sym[p][b] >= SV_COUNT) return MBDDC_ERR_ARG;
+  if (r.xchunk < 64 || r.xchunk > kApplyChunk || r.xchunk % 64) return MBDDC_ERR_ARG;
+  t = r;
+  return MBDDC_OK;
+}
+
 int prepare_host(mbddc_ctx* c, const mbddc_options& o, const std::vector<MeshIn>& ms) {
+  c->tune = Tuning();
+  if (o.tune_table) CHK(read_tuning(o.tune_table, c->tune));
   c->opt = o;
+  c->opt.tune_table = nullptr;   // read once; the caller's string is not kept
   c->mixed = (o.precision != MBDDC_FP64);
   c->fact32 = (o.precision == MBDDC_MIXED_F32FACT);
   c->sym = (o.symmetric_hint != 0);
@@ -1821,6 +1929,126 @@ int prepare_host(mbddc_ctx* c, const mbddc_options& o, const std::vector<MeshIn>
   if (!err.empty()) return MBDDC_ERR_ARG;
   CHK(build_layout(c));
   if (o.levels == 3) CHK(build_level2_host(c, ms));
+  return MBDDC_OK;
+}
+
+int factor_dispatch(mbddc_ctx* c) {
+  c->last_bad = 0;
+  return c->fact32 ? factor_impl<float, float>(c)
+                   : (c->mixed ? factor_impl<double, float>(c) : factor_impl<double, double>(c));
+}
+
+// Regroups the symmetric inversions after a change of c->tune (and the level-2 child's).
+int rebuild_symsets(mbddc_ctx* c) {
+  if (c->sym) {
+    for (SymSet* S : {&c->set_kii, &c->set_x, &c->set_t}) {
+      dfree(c, S->d_all); dfree(c, S->d_big); dfree(c, S->d_items); dfree(c, S->d_gd); dfree(c, S->d_gitems);
+    }
+    if (!(c->set_kii.build(c->gj_kii, c->fact32, c->tune) && c->set_x.build(c->gj_x, c->fact32, c->tune) &&
+          c->set_t.build(c->gj_t, c->fact32, c->tune)))
+      return MBDDC_ERR_UNSUPPORTED;
+    for (SymSet* S : {&c->set_kii, &c->set_x, &c->set_t}) {
+      CHK(upload(c, &S->d_all, S->all));
+      CHK(upload(c, &S->d_big, S->big));
+      CHK(upload(c, &S->d_items, S->items));
+      CHK(upload(c, &S->d_gd, S->gd));
+      CHK(upload(c, &S->d_gitems, S->gitems));
+    }
+    const int64_t pb = std::max(std::max(c->set_kii.pbuf_elems, c->set_x.pbuf_elems), c->set_t.pbuf_elems);
+    const int64_t bc =
+        (int64_t)std::max(std::max(c->set_kii.big.size(), c->set_x.big.size()), c->set_t.big.size());
+    if (pb > c->big_pbuf || bc > c->big_count || (bc > 0 && !c->d_bpanel)) {
+      dfree(c, c->d_bpanel); dfree(c, c->d_bdinv); dfree(c, c->d_bthr);
+      c->big_pbuf = std::max(pb, c->big_pbuf);
+      c->big_count = std::max(bc, c->big_count);
+      CHK(dalloc(c, &c->d_bpanel, c->big_pbuf));
+      CHK(dalloc(c, &c->d_bdinv, c->big_count * kSymCB * kSymCB));
+      CHK(dalloc(c, &c->d_bthr, c->big_count));
+    }
+    HIPCHK(hipStreamSynchronize(c->stream));
+  }
+  c->apply_gen++;                 // the staging width is a kernel argument of the captured applies
+  if (c->child) {
+    c->child->tune = c->tune;
+    CHK(rebuild_symsets(c->child));
+  }
+  return MBDDC_OK;
+}
+
+// GPU time (ms) of fn() on the handle's stream, best of `reps`.
+template <typename F>
+int time_best(mbddc_ctx* c, int reps, F fn, double* best) {
+  hipEvent_t a = nullptr, b = nullptr;
+  HIPCHK(hipEventCreate(&a));
+  HIPCHK(hipEventCreate(&b));
+  *best = 1e300;
+  int st = MBDDC_OK;
+  for (int r = 0; r < reps && st == MBDDC_OK; ++r) {
+    (void)hipEventRecord(a, c->stream);
+    st = fn();
+    (void)hipEventRecord(b, c->stream);
+    if (hipEventSynchronize(b) != hipSuccess) st = MBDDC_ERR_DEVICE;
+    float ms = 0.0f;
+    if (st == MBDDC_OK && hipEventElapsedTime(&ms, a, b) == hipSuccess) *best = std::min(*best, (double)ms);
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  return st;
+}
+
+// Coordinate search over the tuning table on this handle's own matrices: for each size
+// bucket that occurs in the symmetric inversions, every variant that can take the
+// bucket's matrices is timed by a whole numeric factorisation (best of two); then the
+// apply staging width by the apply of four right-hand sides (best of five). The handle
+// ends factorised with the chosen table.
+int autotune_impl(mbddc_ctx* c) {
+  const int p = c->fact32 ? 1 : 0;
+  if (c->sym) {
+    int bmax[kSymBuckets] = {0, 0, 0, 0};
+    for (const std::vector<GjDesc>* v : {&c->gj_kii, &c->gj_x, &c->gj_t})
+      for (const GjDesc& g : *v)
+        if (g.n > 0) bmax[sym_bucket(g.n)] = std::max(bmax[sym_bucket(g.n)], g.n);
+    for (int b = 0; b < kSymBuckets; ++b) {
+      if (bmax[b] == 0) continue;
+      int best_v = c->tune.sym[p][b];
+      double best_t = 1e300;
+      for (int v = 0; v < SV_COUNT; ++v) {
+        if (!sym_variant_ok(v, bmax[b], p == 1)) continue;
+        c->tune.sym[p][b] = v;
+        CHK(rebuild_symsets(c));
+        double t = 0.0;
+        CHK(time_best(c, 2, [&] { return factor_dispatch(c); }, &t));
+        if (t < best_t) {
+          best_t = t;
+          best_v = v;
+        }
+      }
+      c->tune.sym[p][b] = best_v;
+      CHK(rebuild_symsets(c));
+    }
+  }
+  CHK(factor_dispatch(c));
+  // apply staging width
+  CHK(ensure_apply_buffers(c, 4));
+  hipLaunchKernelGGL(k_fill, dim3(nblk(c->plan.n_dofs * 4)), dim3(kBlock), 0, c->stream, c->d_X,
+                     c->plan.n_dofs * 4, 0.0);
+  int best_x = c->tune.xchunk;
+  double best_t = 1e300;
+  const int top = std::min(kApplyChunk, (int)round_up(std::max(c->max_cols, 1), 64));
+  for (int xc : {128, 256, 512, 1024}) {
+    if (xc > top && xc != 128) continue;
+    c->tune.xchunk = xc;
+    if (c->child) c->child->tune.xchunk = xc;
+    CHK(apply_dispatch(c, 4, c->d_X, c->d_Y));
+    double t = 0.0;
+    CHK(time_best(c, 5, [&] { return apply_dispatch(c, 4, c->d_X, c->d_Y); }, &t));
+    if (t < best_t) {
+      best_t = t;
+      best_x = xc;
+    }
+  }
+  c->tune.xchunk = best_x;
+  CHK(rebuild_symsets(c));
   return MBDDC_OK;
 }
 }  // namespace
@@ -1953,14 +2181,54 @@ int mbddc_factor(mbddc_ctx* c) {
   if (!c) return MBDDC_ERR_ARG;
   if (c->state < 2) return MBDDC_ERR_STATE;
   if (hipSetDevice(c->device) != hipSuccess) return MBDDC_ERR_DEVICE;
-  c->last_bad = 0;
-  int st = c->fact32 ? factor_impl<float, float>(c)
-                     : (c->mixed ? factor_impl<double, float>(c) : factor_impl<double, double>(c));
+  int st = factor_dispatch(c);
   if (st != MBDDC_OK) {
     c->state = 2;
     return st;
   }
   c->state = 3;
+  return MBDDC_OK;
+}
+
+int mbddc_autotune(mbddc_ctx* c, const char* table_out) {
+  if (!c) return MBDDC_ERR_ARG;
+  if (c->state < 2) return MBDDC_ERR_STATE;
+  if (hipSetDevice(c->device) != hipSuccess) return MBDDC_ERR_DEVICE;
+  const uint32_t mask = c->prof.mask;
+  c->prof.mask = 0;
+  int st = autotune_impl(c);
+  c->prof.mask = mask;
+  if (st != MBDDC_OK) {
+    c->state = 2;
+    return st;
+  }
+  c->state = 3;
+  if (table_out) {
+    FILE* f = std::fopen(table_out, "wb");
+    if (!f) return MBDDC_ERR_ARG;
+    const Tuning& t = c->tune;
+    std::fprintf(f,
+                 "{\"mbddc_tune\": 1,\n \"variants\": [\"%s\", \"%s\", \"%s\", \"%s\"],\n"
+                 " \"bucket_max_n\": [%d, %d, %d, null],\n"
+                 " \"sym_fp64\": [%d, %d, %d, %d],\n \"sym_fp32\": [%d, %d, %d, %d],\n"
+                 " \"apply_xchunk\": %d}\n",
+                 kSymVariantName[0], kSymVariantName[1], kSymVariantName[2], kSymVariantName[3], kSymBucketMax[0],
+                 kSymBucketMax[1], kSymBucketMax[2], t.sym[0][0], t.sym[0][1], t.sym[0][2], t.sym[0][3], t.sym[1][0],
+                 t.sym[1][1], t.sym[1][2], t.sym[1][3], t.xchunk);
+    const bool bad = std::ferror(f) != 0;
+    if (std::fclose(f) != 0 || bad) return MBDDC_ERR_ARG;
+  }
+  return MBDDC_OK;
+}
+
+int mbddc_get_tuning(const mbddc_ctx* c, int32_t* sym_fp64, int32_t* sym_fp32, int32_t* apply_xchunk) {
+  if (!c) return MBDDC_ERR_ARG;
+  if (c->state < 1) return MBDDC_ERR_STATE;
+  for (int b = 0; b < kSymBuckets; ++b) {
+    if (sym_fp64) sym_fp64[b] = c->tune.sym[0][b];
+    if (sym_fp32) sym_fp32[b] = c->tune.sym[1][b];
+  }
+  if (apply_xchunk) *apply_xchunk = c->tune.xchunk;
   return MBDDC_OK;
 }
 

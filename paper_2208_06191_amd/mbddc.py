@@ -100,6 +100,9 @@ _SIGNATURES = {
                                _i32p, _i32p, _i32p, _i32p],
     "mbddc_last_bad_subdomain": [ctypes.c_void_p],
     "mbddc_set_profiling": [ctypes.c_void_p, ctypes.c_uint32],
+    "mbddc_autotune": [ctypes.c_void_p, ctypes.c_char_p],
+    "mbddc_get_tuning": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                         ctypes.POINTER(ctypes.c_int32)],
     "mbddc_profile_family_name": [ctypes.c_int],
     "mbddc_get_profile": [ctypes.c_void_p, ctypes.POINTER(mbddc_kernel_stat), ctypes.c_int,
                           ctypes.POINTER(ctypes.c_int)],
@@ -176,6 +179,8 @@ def default_options(**kw) -> mbddc_options:
     o = mbddc_options()
     _check(lib().mbddc_default_options(ctypes.byref(o)), "mbddc_default_options")
     for k, v in kw.items():
+        if k == "tune_table" and isinstance(v, str):
+            v = v.encode()
         setattr(o, k, v)
     return o
 
@@ -357,6 +362,21 @@ class Solver:
         if st != MBDDC_OK and (raise_on_noconv or st != MBDDC_ERR_NOCONV):
             raise MbddcError(st, "mbddc_solve")
         return res, info
+
+    # -- tuning --------------------------------------------------------------------
+    def mbddc_autotune(self, table_out=None) -> dict:
+        """Times the kernel variants on this handle's matrices, keeps the fastest (see mbddc.h)
+        and optionally writes the table; returns it."""
+        path = None if table_out is None else str(table_out).encode()
+        _check(lib().mbddc_autotune(self._h, path), "mbddc_autotune")
+        return self.mbddc_get_tuning()
+
+    def mbddc_get_tuning(self) -> dict:
+        a64 = (ctypes.c_int32 * 4)()
+        a32 = (ctypes.c_int32 * 4)()
+        xc = ctypes.c_int32()
+        _check(lib().mbddc_get_tuning(self._h, a64, a32, ctypes.byref(xc)), "mbddc_get_tuning")
+        return {"sym_fp64": list(a64), "sym_fp32": list(a32), "apply_xchunk": xc.value}
 
     # -- profiling -----------------------------------------------------------------
     def mbddc_set_profiling(self, mask: int = 0xFFFFFFFF):

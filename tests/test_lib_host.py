@@ -104,3 +104,28 @@ def test_footprint_estimate_is_host_only_and_grows_with_size():
     assert three < two
     with pytest.raises(mbddc.MbddcError):
         mbddc.mbddc_estimate_footprint([m], mbddc.default_options(levels=5))
+
+
+def test_tuning_table_is_read_and_checked(tmp_path):
+    """Tables are read during setup (host only): valid ones are accepted, malformed,
+    missing or out-of-range ones rejected with MBDDC_ERR_ARG."""
+    from paper_2208_06191_amd import workloads as W
+    m = mbddc.mesh_from_problem(W.linear_box(4, 2, 1, nrhs=1, primal=3, name="t"))
+    good = tmp_path / "good.json"
+    good.write_text('{"mbddc_tune": 1, "sym_fp64": [0, 1, 3, 3], "sym_fp32": [2, 2, 1, 1], "apply_xchunk": 512}\n')
+    base = mbddc.mbddc_estimate_footprint([m], mbddc.default_options(symmetric_hint=1))
+    assert mbddc.mbddc_estimate_footprint([m], mbddc.default_options(symmetric_hint=1, tune_table=str(good))) > 0
+    assert base > 0
+    bad = {"garbage.json": "not a table",
+           "range.json": '{"mbddc_tune": 1, "sym_fp64": [0, 1, 7, 3], "sym_fp32": [2, 2, 1, 1], "apply_xchunk": 512}',
+           "chunk.json": '{"mbddc_tune": 1, "sym_fp64": [0, 1, 3, 3], "sym_fp32": [2, 2, 1, 1], "apply_xchunk": 100}',
+           "short.json": '{"mbddc_tune": 1, "sym_fp64": [0, 1], "apply_xchunk": 512}'}
+    for name, text in bad.items():
+        f = tmp_path / name
+        f.write_text(text)
+        with pytest.raises(mbddc.MbddcError) as e:
+            mbddc.mbddc_estimate_footprint([m], mbddc.default_options(symmetric_hint=1, tune_table=str(f)))
+        assert e.value.status == mbddc.MBDDC_ERR_ARG, name
+    with pytest.raises(mbddc.MbddcError) as e:
+        mbddc.mbddc_estimate_footprint([m], mbddc.default_options(tune_table=str(tmp_path / "missing.json")))
+    assert e.value.status == mbddc.MBDDC_ERR_ARG
