@@ -120,7 +120,9 @@ inline int sym_bucket(int n) {
 struct Tuning {
   int32_t sym[2][kSymBuckets];      // [0] FP64, [1] FP32
   int32_t xchunk;
+  int32_t apply_rows[4];            // rows per workgroup of apply phases A, C, F, H (128, 256; 0 = by size)
   Tuning() {
+    for (int k = 0; k < 4; ++k) apply_rows[k] = 0;
     const int d64[kSymBuckets] = {SV_REG, SV_REG, SV_BLOCKED, SV_BLOCKED};
     const int d32[kSymBuckets] = {SV_BP32, SV_BP32, SV_BP16, SV_BP16};
     for (int b = 0; b < kSymBuckets; ++b) {
@@ -239,6 +241,7 @@ struct mbddc_ctx {
   std::vector<GjDesc> gj_t;                          // T = C X C^T blocks too large for LDS (symmetric path)
   SymSet set_kii, set_x, set_t;                      // symmetric path: the three inversion families
   Tuning tune;                                       // kernel variants (tuning table or defaults)
+  int32_t apply_rows_eff[4] = {256, 256, 256, 256};  // rows per workgroup of apply phases A, C, F, H
   int64_t big_pbuf = 0, big_count = 0;               // batched blocked sweep: panel elements, matrices
   bool sym = false;                                  // symmetric (SPD) factor path
   std::vector<ApplyItem> itA, itC, itE, itF, itH;
@@ -444,6 +447,33 @@ size_t elem_size(bool mixed) { return mixed ? sizeof(float) : sizeof(double); }
 // ----------------------------------------------------------------------------
 // symbolic layout on top of the host plan
 // ----------------------------------------------------------------------------
+// Row blocks of the local apply phases: rows per workgroup 128 or 256 per phase, from the
+// tuning table, or (0) the size that pads the phase's row counts least (256 on ties).
+void build_apply_items(mbddc_ctx* c) {
+  c->itA.clear(); c->itC.clear(); c->itF.clear(); c->itH.clear();
+  std::vector<ApplyItem>* lists[4] = {&c->itA, &c->itC, &c->itF, &c->itH};
+  auto rows_of = [](const SubDev& d, int k) -> int64_t {
+    return k == 0 ? d.nI + d.nG : (k == 1 ? d.nG + d.nc : (k == 2 ? d.nG : d.nI));
+  };
+  for (int k = 0; k < 4; ++k) {
+    int rw = c->tune.apply_rows[k];
+    if (rw != 128 && rw != 256) {
+      int64_t pad[2] = {0, 0};
+      for (const SubDev& d : c->subs)
+        for (int q = 0; q < 2; ++q) {
+          const int64_t w = q ? 256 : 128, r = rows_of(d, k);
+          pad[q] += std::max<int64_t>(1, (r + w - 1) / w) * w - r;
+        }
+      rw = pad[0] < pad[1] ? 128 : 256;
+    }
+    c->apply_rows_eff[k] = rw;
+    for (int64_t s = 0; s < (int64_t)c->subs.size(); ++s) {
+      const int64_t nb = std::max<int64_t>(1, (rows_of(c->subs[s], k) + rw - 1) / rw);
+      for (int64_t b = 0; b < nb; ++b) lists[k]->push_back({(int32_t)s, (int32_t)(b * rw), 0, 0});
+    }
+  }
+}
+
 int build_layout(mbddc_ctx* c) {
   const Plan& P = c->plan;
   c->subs.assign(P.n_sub, SubDev{});
@@ -533,16 +563,8 @@ int build_layout(mbddc_ctx* c) {
     st.oC = d.oP; st.oCi = d.oP; st.alpha = -1.0; st.beta = 1.0; st.transB = 1;
     st.tiles_n = (int32_t)((nG + 63) / 64);
     dStil.push_back(st);
-    // apply work items
-    auto add = [](std::vector<ApplyItem>& v, int64_t sub, int64_t rows) {
-      int64_t nb = std::max<int64_t>(1, (rows + 255) / 256);
-      for (int64_t b = 0; b < nb; ++b) v.push_back({(int32_t)sub, (int32_t)(b * 256), 0, 0});
-    };
-    add(c->itA, s, nI + nG);
-    add(c->itC, s, nG + nc);
-    add(c->itF, s, nG);
-    add(c->itH, s, nI);
   }
+  build_apply_items(c);
   for (GemmDesc& sS : dS) {
     int32_t id = (int32_t)c->gemm_desc.size();
     c->gemm_desc.push_back(sS);
@@ -1353,6 +1375,18 @@ int factor_impl(mbddc_ctx* c) {
 template <typename To, int R>
 int apply_attrs();
 
+// Phase PH of the local apply (row-block list k of A, C, F, H) with that list's rows per
+// workgroup: 256 (four rows per lane) or 128 (two).
+template <typename To, int R, int PH>
+void launch_local(mbddc_ctx* c, const ApplyArgs& a, int k, size_t n_items) {
+  const int rw = c->apply_rows_eff[k];
+  const size_t lds = (size_t)(4 * rw * R + (size_t)a.xchunk * R) * sizeof(double);
+  if (rw == 128)
+    hipLaunchKernelGGL((k_apply_local<To, R, PH, 2>), dim3((unsigned)n_items), dim3(kBlock), lds, c->stream, a);
+  else
+    hipLaunchKernelGGL((k_apply_local<To, R, PH, 4>), dim3((unsigned)n_items), dim3(kBlock), lds, c->stream, a);
+}
+
 template <typename To, int R>
 int apply_impl(mbddc_ctx* c, const double* r, double* z) {
   const Plan& P = c->plan;
@@ -1364,18 +1398,17 @@ int apply_impl(mbddc_ctx* c, const double* r, double* z) {
   a.inst_kc_ld = c->d_inst_kc_ld; a.inst_coarse_off = c->d_inst_coarse_off; a.inst_nc = c->d_inst_nc;
   a.r = r; a.z = z; a.tb = c->d_tb; a.wb = c->d_wb; a.cc = c->d_cc; a.ep = c->d_ep; a.n_coarse = P.n_coarse;
   a.xchunk = std::min(c->max_cols, c->tune.xchunk);
-  const size_t lds_local = (size_t)(4 * 256 * R + (size_t)a.xchunk * R) * sizeof(double);
   CHK((apply_attrs<To, R>()));
-  if (lds_local > 160 * 1024) return MBDDC_ERR_UNSUPPORTED;
+  if ((4 * 256 * R + (size_t)a.xchunk * R) * sizeof(double) > 160 * 1024) return MBDDC_ERR_UNSUPPORTED;
   {
     ProfScope ps(c, F_APPLY_A, c->op_bytes[F_APPLY_A] + 8.0 * R * c->vec_words[F_APPLY_A], 2.0 * R * c->fam_flops[F_APPLY_A]);
     a.items = c->d_itA;
-    hipLaunchKernelGGL((k_apply_local<To, R, 0>), dim3((unsigned)c->itA.size()), dim3(kBlock), lds_local, c->stream, a);
+    launch_local<To, R, 0>(c, a, 0, c->itA.size());
   }
   {
     ProfScope ps(c, F_APPLY_C, c->op_bytes[F_APPLY_C] + 8.0 * R * c->vec_words[F_APPLY_C], 2.0 * R * c->fam_flops[F_APPLY_C]);
     a.items = c->d_itC;
-    hipLaunchKernelGGL((k_apply_local<To, R, 1>), dim3((unsigned)c->itC.size()), dim3(kBlock), lds_local, c->stream, a);
+    launch_local<To, R, 1>(c, a, 1, c->itC.size());
   }
   if (c->child) {
     mbddc_ctx* ch = c->child;
@@ -1402,12 +1435,12 @@ int apply_impl(mbddc_ctx* c, const double* r, double* z) {
   {
     ProfScope ps(c, F_APPLY_F, c->op_bytes[F_APPLY_F] + 8.0 * R * c->vec_words[F_APPLY_F], 2.0 * R * c->fam_flops[F_APPLY_F]);
     a.items = c->d_itF;
-    hipLaunchKernelGGL((k_apply_local<To, R, 3>), dim3((unsigned)c->itF.size()), dim3(kBlock), lds_local, c->stream, a);
+    launch_local<To, R, 3>(c, a, 2, c->itF.size());
   }
   {
     ProfScope ps(c, F_APPLY_H, c->op_bytes[F_APPLY_H] + 8.0 * R * c->vec_words[F_APPLY_H], 2.0 * R * c->fam_flops[F_APPLY_H]);
     a.items = c->d_itH;
-    hipLaunchKernelGGL((k_apply_local<To, R, 4>), dim3((unsigned)c->itH.size()), dim3(kBlock), lds_local, c->stream, a);
+    launch_local<To, R, 4>(c, a, 3, c->itH.size());
   }
   HIPCHK(hipGetLastError());
   return MBDDC_OK;
@@ -1438,10 +1471,14 @@ int apply_attrs() {
   static int st = MBDDC_OK;
   std::call_once(once, [] {
     const size_t mx = 160 * 1024;
-    int e = set_lds(k_apply_local<To, R, 0>, mx);
-    if (!e) e = set_lds(k_apply_local<To, R, 1>, mx);
-    if (!e) e = set_lds(k_apply_local<To, R, 3>, mx);
-    if (!e) e = set_lds(k_apply_local<To, R, 4>, mx);
+    int e = set_lds(k_apply_local<To, R, 0, 4>, mx);
+    if (!e) e = set_lds(k_apply_local<To, R, 1, 4>, mx);
+    if (!e) e = set_lds(k_apply_local<To, R, 3, 4>, mx);
+    if (!e) e = set_lds(k_apply_local<To, R, 4, 4>, mx);
+    if (!e) e = set_lds(k_apply_local<To, R, 0, 2>, mx);
+    if (!e) e = set_lds(k_apply_local<To, R, 1, 2>, mx);
+    if (!e) e = set_lds(k_apply_local<To, R, 3, 2>, mx);
+    if (!e) e = set_lds(k_apply_local<To, R, 4, 2>, mx);
     if (!e) e = set_lds(k_apply_coarse<To, R>, mx);
     st = e;
   });
@@ -1909,6 +1946,11 @@ int read_tuning(const char* path, Tuning& t) {
   if (!ints_after("\"sym_fp64\"", r.sym[0], kSymBuckets) || !ints_after("\"sym_fp32\"", r.sym[1], kSymBuckets) ||
       !ints_after("\"apply_xchunk\"", &r.xchunk, 1))
     return MBDDC_ERR_ARG;
+  if (text.find("\"apply_rows\"") != std::string::npos) {
+    if (!ints_after("\"apply_rows\"", r.apply_rows, 4)) return MBDDC_ERR_ARG;
+    for (int k = 0; k < 4; ++k)
+      if (r.apply_rows[k] != 0 && r.apply_rows[k] != 128 && r.apply_rows[k] != 256) return MBDDC_ERR_ARG;
+  }
   for (int p = 0; p < 2; ++p)
     for (int b = 0; b < kSymBuckets; ++b)
       if (r.sym[p][b] < 0 || r.sym[p][b] >= SV_COUNT) return MBDDC_ERR_ARG;
@@ -1938,7 +1980,8 @@ int factor_dispatch(mbddc_ctx* c) {
                    : (c->mixed ? factor_impl<double, float>(c) : factor_impl<double, double>(c));
 }
 
-// Regroups the symmetric inversions after a change of c->tune (and the level-2 child's).
+// Regroups the symmetric inversions and the apply row blocks after a change of c->tune
+// (and the level-2 child's).
 int rebuild_symsets(mbddc_ctx* c) {
   if (c->sym) {
     for (SymSet* S : {&c->set_kii, &c->set_x, &c->set_t}) {
@@ -1967,7 +2010,15 @@ int rebuild_symsets(mbddc_ctx* c) {
     }
     HIPCHK(hipStreamSynchronize(c->stream));
   }
-  c->apply_gen++;                 // the staging width is a kernel argument of the captured applies
+  // apply row blocks
+  dfree(c, c->d_itA); dfree(c, c->d_itC); dfree(c, c->d_itF); dfree(c, c->d_itH);
+  build_apply_items(c);
+  CHK(upload(c, &c->d_itA, c->itA));
+  CHK(upload(c, &c->d_itC, c->itC));
+  CHK(upload(c, &c->d_itF, c->itF));
+  CHK(upload(c, &c->d_itH, c->itH));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  c->apply_gen++;                 // staging width and row blocks are baked into the captured applies
   if (c->child) {
     c->child->tune = c->tune;
     CHK(rebuild_symsets(c->child));
@@ -2048,6 +2099,24 @@ int autotune_impl(mbddc_ctx* c) {
     }
   }
   c->tune.xchunk = best_x;
+  if (c->child) c->child->tune.xchunk = best_x;
+  // rows per workgroup of each local apply phase
+  for (int k = 0; k < 4; ++k) {
+    int best_r = c->apply_rows_eff[k];
+    best_t = 1e300;
+    for (int rw : {256, 128}) {
+      c->tune.apply_rows[k] = rw;
+      CHK(rebuild_symsets(c));
+      CHK(apply_dispatch(c, 4, c->d_X, c->d_Y));
+      double t = 0.0;
+      CHK(time_best(c, 5, [&] { return apply_dispatch(c, 4, c->d_X, c->d_Y); }, &t));
+      if (t < best_t) {
+        best_t = t;
+        best_r = rw;
+      }
+    }
+    c->tune.apply_rows[k] = best_r;
+  }
   CHK(rebuild_symsets(c));
   return MBDDC_OK;
 }
@@ -2211,17 +2280,19 @@ int mbddc_autotune(mbddc_ctx* c, const char* table_out) {
                  "{\"mbddc_tune\": 1,\n \"variants\": [\"%s\", \"%s\", \"%s\", \"%s\"],\n"
                  " \"bucket_max_n\": [%d, %d, %d, null],\n"
                  " \"sym_fp64\": [%d, %d, %d, %d],\n \"sym_fp32\": [%d, %d, %d, %d],\n"
-                 " \"apply_xchunk\": %d}\n",
+                 " \"apply_xchunk\": %d,\n \"apply_rows\": [%d, %d, %d, %d]}\n",
                  kSymVariantName[0], kSymVariantName[1], kSymVariantName[2], kSymVariantName[3], kSymBucketMax[0],
                  kSymBucketMax[1], kSymBucketMax[2], t.sym[0][0], t.sym[0][1], t.sym[0][2], t.sym[0][3], t.sym[1][0],
-                 t.sym[1][1], t.sym[1][2], t.sym[1][3], t.xchunk);
+                 t.sym[1][1], t.sym[1][2], t.sym[1][3], t.xchunk, c->apply_rows_eff[0], c->apply_rows_eff[1],
+                 c->apply_rows_eff[2], c->apply_rows_eff[3]);
     const bool bad = std::ferror(f) != 0;
     if (std::fclose(f) != 0 || bad) return MBDDC_ERR_ARG;
   }
   return MBDDC_OK;
 }
 
-int mbddc_get_tuning(const mbddc_ctx* c, int32_t* sym_fp64, int32_t* sym_fp32, int32_t* apply_xchunk) {
+int mbddc_get_tuning(const mbddc_ctx* c, int32_t* sym_fp64, int32_t* sym_fp32, int32_t* apply_xchunk,
+                     int32_t* apply_rows) {
   if (!c) return MBDDC_ERR_ARG;
   if (c->state < 1) return MBDDC_ERR_STATE;
   for (int b = 0; b < kSymBuckets; ++b) {
@@ -2229,6 +2300,7 @@ int mbddc_get_tuning(const mbddc_ctx* c, int32_t* sym_fp64, int32_t* sym_fp32, i
     if (sym_fp32) sym_fp32[b] = c->tune.sym[1][b];
   }
   if (apply_xchunk) *apply_xchunk = c->tune.xchunk;
+  for (int k = 0; k < 4 && apply_rows; ++k) apply_rows[k] = c->apply_rows_eff[k];
   return MBDDC_OK;
 }
 
