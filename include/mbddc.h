@@ -245,20 +245,22 @@ int mbddc_get_profile(mbddc_ctx* ctx, mbddc_kernel_stat* out, int max_entries, i
  * workgroup sweep with 16-index panels in LDS, 2 the same with 32-index panels, 3 batched
  * blocked sweep (FP64); then the number of input columns the apply stages in LDS (128, 256,
  * 512 or 1024) and the rows per workgroup of each local apply phase A, C, F, H (256: four
- * rows per lane, 128: two) by timing applies of four right-hand sides. Needs a tangent (state
+ * rows per lane, 128: two) by timing applies of four right-hand sides; FP64 factorisations
+ * also time their batched GEMMs on the vector units (0) and the matrix cores (1). Needs a tangent (state
  * >= set_tangent) and leaves the handle factorised with the chosen table. table_out (may be
  * NULL): JSON file
  *   {"mbddc_tune": 1, "sym_fp64": [v0, v1, v2, v3], "sym_fp32": [v0, v1, v2, v3], "apply_xchunk": C,
- *    "apply_rows": [A, C, F, H]}
- * (plus informative keys; "apply_rows" optional, 0 = the size that pads the row counts least),
+ *    "apply_rows": [A, C, F, H], "gemm_mfma": G}
+ * (plus informative keys; "apply_rows" optional, 0 = the size that pads the row counts least;
+ * "gemm_mfma" optional, default 0),
  * to be passed as options.tune_table to later handles. A table variant
  * that cannot take some matrix (size or precision) falls back to one that can. Errors as
  * mbddc_factor; MBDDC_ERR_ARG if table_out cannot be written. */
 int mbddc_autotune(mbddc_ctx* ctx, const char* table_out);
 /* The handle's table: sym_fp64[4], sym_fp32[4], apply_xchunk, apply_rows[4] (rows per
- * workgroup in effect for apply phases A, C, F, H); any pointer may be NULL. */
+ * workgroup in effect for apply phases A, C, F, H), gemm_mfma; any pointer may be NULL. */
 int mbddc_get_tuning(const mbddc_ctx* ctx, int32_t* sym_fp64, int32_t* sym_fp32, int32_t* apply_xchunk,
-                     int32_t* apply_rows);
+                     int32_t* apply_rows, int32_t* gemm_mfma);
 
 /* Subdomain of the last MBDDC_ERR_SINGULAR (-1: coarse problem; see mbddc_factor). */
 int mbddc_last_bad_subdomain(const mbddc_ctx* ctx);

@@ -121,7 +121,9 @@ struct Tuning {
   int32_t sym[2][kSymBuckets];      // [0] FP64, [1] FP32
   int32_t xchunk;
   int32_t apply_rows[4];            // rows per workgroup of apply phases A, C, F, H (128, 256; 0 = by size)
+  int32_t gemm_mfma;                // FP64 batched GEMMs on the matrix cores (1) or the vector units (0)
   Tuning() {
+    gemm_mfma = 0;
     for (int k = 0; k < 4; ++k) apply_rows[k] = 0;
     const int d64[kSymBuckets] = {SV_REG, SV_REG, SV_BLOCKED, SV_BLOCKED};
     const int d32[kSymBuckets] = {SV_BP32, SV_BP32, SV_BP16, SV_BP16};
@@ -331,7 +333,8 @@ struct mbddc_ctx {
   mbddc_ctx* child = nullptr;
   std::vector<int32_t> l2_dof;      // [n_coarse] level-2 DOF of each coarse DOF
   std::vector<int32_t> l2_eidx;     // [n_cslots] level-2 element-local DOF of each coarse slot
-  int32_t *d_l2_dof = nullptr, *d_l2_eidx = nullptr;
+  int32_t* d_l2_eidx = nullptr;
+  int32_t* d_l2_inv = nullptr;      // [child n_dofs] coarse DOF of each level-2 DOF, or -1
 };
 
 namespace {
@@ -885,7 +888,10 @@ int upload_level2(mbddc_ctx* c) {
   mbddc_ctx* ch = c->child;
   CHK(upload_plan(ch));
   HIPCHK(hipMemsetAsync(ch->d_Ke, 0, ch->plan.ke_total * sizeof(double), c->stream));
-  CHK(upload(c, &c->d_l2_dof, c->l2_dof));
+  std::vector<int32_t> inv(std::max<int64_t>(ch->plan.n_dofs, 1), -1);
+  for (int64_t k = 0; k < (int64_t)c->l2_dof.size(); ++k)
+    if (c->l2_dof[k] >= 0) inv[c->l2_dof[k]] = (int32_t)k;
+  CHK(upload(c, &c->d_l2_inv, inv));
   CHK(upload(c, &c->d_l2_eidx, c->l2_eidx));
   HIPCHK(hipStreamSynchronize(c->stream));
   ch->state = 2;
@@ -960,6 +966,20 @@ int set_lds(K kern, size_t bytes) {
 // ----------------------------------------------------------------------------
 // numeric setup (factor)
 // ----------------------------------------------------------------------------
+// Batched GEMM: FP64 on the matrix cores when the tuning table says so, else on the vector units.
+template <typename T>
+void launch_gemm(mbddc_ctx* c, unsigned n_items, hipStream_t st, const GemmDesc* d, const GemmItem* it, const T* A,
+                 const T* B, T* C, const T* Ci) {
+  if (n_items == 0) return;
+  if constexpr (sizeof(T) == 8) {
+    if (c->tune.gemm_mfma) {
+      hipLaunchKernelGGL(k_gemm_batched_f64, dim3(n_items), dim3(kBlock), 0, st, d, it, A, B, C, Ci);
+      return;
+    }
+  }
+  hipLaunchKernelGGL((k_gemm_batched<T>), dim3(n_items), dim3(kBlock), 0, st, d, it, A, B, C, Ci);
+}
+
 template <typename T>
 int run_gj(mbddc_ctx* c, T* base, const GjDesc* d_desc, int64_t count, int maxn, int32_t* d_stat, int32_t* d_pivs) {
   if (count == 0) return MBDDC_OK;
@@ -1034,7 +1054,7 @@ int run_symset(mbddc_ctx* c, T* base, const SymSet& S) {
     hipLaunchKernelGGL(k_bsym_diag, dim3(active), dim3(kBlock), kDiagLds, c->stream, S.d_big, A, c->d_bdinv,
                        c->d_bthr, c->d_status, k0);
     hipLaunchKernelGGL(k_bsym_gather, dim3(gx, active), dim3(kBlock), 0, c->stream, S.d_big, A, c->d_bpanel, k0);
-    hipLaunchKernelGGL((k_gemm_batched<double>), dim3((unsigned)S.gitem_off[active]), dim3(kBlock), 0, c->stream,
+    launch_gemm<double>(c, (unsigned)S.gitem_off[active], c->stream,
                        S.d_gd, S.d_gitems, c->d_bpanel, c->d_bdinv, c->d_bpanel, c->d_bpanel);
     hipLaunchKernelGGL(k_bsym_update, dim3((unsigned)S.item_off[active]), dim3(kBlock), 0, c->stream, S.d_big,
                        S.d_items, A, c->d_bpanel, c->d_bdinv, k0);
@@ -1108,7 +1128,7 @@ int coarse_sweep_large(mbddc_ctx* c, int32_t ii) {
       ProfScope ps(c, F_COARSE_PREP, 16.0 * n * kSymCB, 2.0 * n * (double)kSymCB * kSymCB);
       hipLaunchKernelGGL(k_csym_gather, dim3(gg), dim3(kBlock), 0, c->stream, A, n, ld, k0, Wg);
       if (kb > 0) HIPCHK(hipStreamWaitEvent(c->stream, c->ev_b, 0));     // Dinv of block kb (lookahead)
-      hipLaunchKernelGGL((k_gemm_batched<double>), dim3(n_items), dim3(kBlock), 0, c->stream, c->d_csym_gd,
+      launch_gemm<double>(c, (unsigned)(n_items), c->stream, c->d_csym_gd,
                          d_items, Wg, Dk, Ug, Ug);
     }
     const bool ahead = kb + 1 < nb;
@@ -1182,7 +1202,7 @@ int coarse_invert_large(mbddc_ctx* c, int32_t ii) {
     }
     {
       ProfScope ps(c, F_COARSE_GEMM, 16.0 * n * (double)n, gemm_flops);
-      hipLaunchKernelGGL((k_gemm_batched<double>), dim3((unsigned)items.size()), dim3(kBlock), 0, c->stream, d_gd,
+      launch_gemm<double>(c, (unsigned)items.size(), c->stream, d_gd,
                          d_items, c->d_cCcol, c->d_cY, A, A);
     }
     {
@@ -1241,12 +1261,12 @@ int factor_impl(mbddc_ctx* c) {
   const std::vector<GemmItem>& is = c->sym ? c->gemm_items_ssym : c->gemm_items_s;
   if (!igh.empty()) {
     ProfScope ps(c, F_GEMM_GH, 0.0, c->fam_flops[F_GEMM_GH] * (c->sym ? 0.5 : 1.0));
-    hipLaunchKernelGGL((k_gemm_batched<T>), dim3((unsigned)igh.size()), dim3(kBlock), 0, c->stream, c->d_gemm_desc,
+    launch_gemm<T>(c, (unsigned)igh.size(), c->stream, c->d_gemm_desc,
                        c->sym ? c->d_gemm_g : c->d_gemm_gh, W, W, W, W);
   }
   if (!is.empty()) {
     ProfScope ps(c, F_GEMM_S, 0.0, c->fam_flops[F_GEMM_S]);
-    hipLaunchKernelGGL((k_gemm_batched<T>), dim3((unsigned)is.size()), dim3(kBlock), 0, c->stream, c->d_gemm_desc,
+    launch_gemm<T>(c, (unsigned)is.size(), c->stream, c->d_gemm_desc,
                        c->sym ? c->d_gemm_ssym : c->d_gemm_s, W, W, W, W);
   }
   HIPCHK(hipGetLastError());
@@ -1280,10 +1300,10 @@ int factor_impl(mbddc_ctx* c) {
       hipLaunchKernelGGL((k_tinv_finish<T>), dim3((unsigned)c->set_t.all.size()), dim3(kBlock), 0, c->stream,
                          c->d_subs, c->set_t.d_all, c->d_rho, W, c->d_Kcl);
       if (!c->gemm_items_phi.empty())
-        hipLaunchKernelGGL((k_gemm_batched<T>), dim3((unsigned)c->gemm_items_phi.size()), dim3(kBlock), 0,
+        launch_gemm<T>(c, (unsigned)c->gemm_items_phi.size(),
                            c->stream, c->d_gemm_desc, c->d_gemm_phi, W, W, W, W);
       if (!c->gemm_items_stil.empty())
-        hipLaunchKernelGGL((k_gemm_batched<T>), dim3((unsigned)c->gemm_items_stil.size()), dim3(kBlock), 0,
+        launch_gemm<T>(c, (unsigned)c->gemm_items_stil.size(),
                            c->stream, c->d_gemm_desc, c->d_gemm_stil, W, W, W, W);
       const unsigned parts = (unsigned)std::min(64, std::max(1, (c->max_cols + 127) / 128));
       hipLaunchKernelGGL((k_extract_sym<T, To>), dim3(parts, nsub), dim3(kBlock), 0, c->stream, c->d_subs, c->d_slot_w, W,
@@ -1387,10 +1407,17 @@ void launch_local(mbddc_ctx* c, const ApplyArgs& a, int k, size_t n_items) {
     hipLaunchKernelGGL((k_apply_local<To, R, PH, 4>), dim3((unsigned)n_items), dim3(kBlock), lds, c->stream, a);
 }
 
+// z = M^-1 r. For the level-2 instance of a three-level handle (parent != null) the input
+// is gathered from the parent's coarse slots and the output also written to the parent's
+// coarse partial products, inside the level-2 phases.
 template <typename To, int R>
-int apply_impl(mbddc_ctx* c, const double* r, double* z) {
+int apply_impl(mbddc_ctx* c, const double* r, double* z, mbddc_ctx* parent = nullptr) {
   const Plan& P = c->plan;
   ApplyArgs a{};
+  if (parent) {
+    a.l2_inv = parent->d_l2_inv; a.l2_ptr = parent->d_coarse_ptr; a.l2_slots = parent->d_coarse_slots;
+    a.l2_cc = parent->d_cc; a.l2_ep = parent->d_ep;
+  }
   a.subs = c->d_subs; a.sub_dofs = c->d_sub_dofs; a.slot_dof = c->d_slot_dof; a.slot_ifx = c->d_slot_ifx;
   a.slot_owner = c->d_slot_owner; a.ifx_ptr = c->d_ifx_ptr; a.ifx_slots = c->d_ifx_slots;
   a.cslot_coarse = c->d_cslot_coarse; a.coarse_ptr = c->d_coarse_ptr; a.coarse_slots = c->d_coarse_slots;
@@ -1412,19 +1439,13 @@ int apply_impl(mbddc_ctx* c, const double* r, double* z) {
   }
   if (c->child) {
     mbddc_ctx* ch = c->child;
-    double b2 = 16.0 * R * P.n_coarse, f2 = 0.0;   // gather + scatter, then the level-2 phases
+    double b2 = 16.0 * R * P.n_coarse, f2 = 0.0;   // coarse gather + scatter, then the level-2 phases
     for (int f : {F_APPLY_A, F_APPLY_C, F_APPLY_E, F_APPLY_F, F_APPLY_H}) {
       b2 += ch->op_bytes[f] + 8.0 * R * ch->vec_words[f];
       f2 += 2.0 * R * ch->fam_flops[f];
     }
     ProfScope ps(c, F_LEVEL2_APPLY, b2, f2);
-    const unsigned g = nblk(P.n_coarse * R);
-    hipLaunchKernelGGL(k_l2_gather, dim3(g), dim3(kBlock), 0, c->stream, (int64_t)P.n_coarse, R, c->d_coarse_ptr,
-                       c->d_coarse_slots, c->d_cc, c->d_l2_dof, ch->d_X);
-    HIPCHK(hipGetLastError());
-    CHK((apply_impl<double, R>(ch, ch->d_X, ch->d_Y)));
-    hipLaunchKernelGGL(k_l2_scatter, dim3(g), dim3(kBlock), 0, c->stream, (int64_t)P.n_coarse, R, c->d_l2_dof, ch->d_Y,
-                       c->d_ep);
+    CHK((apply_impl<double, R>(ch, ch->d_X, ch->d_Y, c)));
   } else if (!c->itE.empty()) {
     const size_t lds_c = (size_t)(4 * 256 * R + kCoarseChunk * R) * sizeof(double);
     ProfScope ps(c, F_APPLY_E, c->op_bytes[F_APPLY_E] + 8.0 * R * c->vec_words[F_APPLY_E],
@@ -1946,6 +1967,9 @@ int read_tuning(const char* path, Tuning& t) {
   if (!ints_after("\"sym_fp64\"", r.sym[0], kSymBuckets) || !ints_after("\"sym_fp32\"", r.sym[1], kSymBuckets) ||
       !ints_after("\"apply_xchunk\"", &r.xchunk, 1))
     return MBDDC_ERR_ARG;
+  if (text.find("\"gemm_mfma\"") != std::string::npos) {
+    if (!ints_after("\"gemm_mfma\"", &r.gemm_mfma, 1) || (r.gemm_mfma != 0 && r.gemm_mfma != 1)) return MBDDC_ERR_ARG;
+  }
   if (text.find("\"apply_rows\"") != std::string::npos) {
     if (!ints_after("\"apply_rows\"", r.apply_rows, 4)) return MBDDC_ERR_ARG;
     for (int k = 0; k < 4; ++k)
@@ -2078,6 +2102,22 @@ int autotune_impl(mbddc_ctx* c) {
       CHK(rebuild_symsets(c));
     }
   }
+  if (!c->fact32) {   // FP64 GEMMs: vector units or matrix cores
+    int best_g = c->tune.gemm_mfma;
+    double best_t = 1e300;
+    for (int g = 0; g < 2; ++g) {
+      c->tune.gemm_mfma = g;
+      if (c->child) c->child->tune.gemm_mfma = g;
+      double t = 0.0;
+      CHK(time_best(c, 2, [&] { return factor_dispatch(c); }, &t));
+      if (t < best_t) {
+        best_t = t;
+        best_g = g;
+      }
+    }
+    c->tune.gemm_mfma = best_g;
+    if (c->child) c->child->tune.gemm_mfma = best_g;
+  }
   CHK(factor_dispatch(c));
   // apply staging width
   CHK(ensure_apply_buffers(c, 4));
@@ -2161,7 +2201,8 @@ int mbddc_setup_symbolic_batch(mbddc_ctx* c, int n_inst, const mbddc_mesh* meshe
   c->d_cDinv = c->d_cY = c->d_cCcol = nullptr;
   c->d_csym_gd = nullptr;
   c->d_csym_items = nullptr;
-  c->d_l2_dof = c->d_l2_eidx = nullptr;
+  c->d_l2_eidx = nullptr;
+  c->d_l2_inv = nullptr;
   c->state = 0;
   int st = prepare_host(c, o, ms);
   if (!st) st = upload_plan(c);
@@ -2280,11 +2321,11 @@ int mbddc_autotune(mbddc_ctx* c, const char* table_out) {
                  "{\"mbddc_tune\": 1,\n \"variants\": [\"%s\", \"%s\", \"%s\", \"%s\"],\n"
                  " \"bucket_max_n\": [%d, %d, %d, null],\n"
                  " \"sym_fp64\": [%d, %d, %d, %d],\n \"sym_fp32\": [%d, %d, %d, %d],\n"
-                 " \"apply_xchunk\": %d,\n \"apply_rows\": [%d, %d, %d, %d]}\n",
+                 " \"apply_xchunk\": %d,\n \"apply_rows\": [%d, %d, %d, %d],\n \"gemm_mfma\": %d}\n",
                  kSymVariantName[0], kSymVariantName[1], kSymVariantName[2], kSymVariantName[3], kSymBucketMax[0],
                  kSymBucketMax[1], kSymBucketMax[2], t.sym[0][0], t.sym[0][1], t.sym[0][2], t.sym[0][3], t.sym[1][0],
                  t.sym[1][1], t.sym[1][2], t.sym[1][3], t.xchunk, c->apply_rows_eff[0], c->apply_rows_eff[1],
-                 c->apply_rows_eff[2], c->apply_rows_eff[3]);
+                 c->apply_rows_eff[2], c->apply_rows_eff[3], t.gemm_mfma);
     const bool bad = std::ferror(f) != 0;
     if (std::fclose(f) != 0 || bad) return MBDDC_ERR_ARG;
   }
@@ -2292,7 +2333,7 @@ int mbddc_autotune(mbddc_ctx* c, const char* table_out) {
 }
 
 int mbddc_get_tuning(const mbddc_ctx* c, int32_t* sym_fp64, int32_t* sym_fp32, int32_t* apply_xchunk,
-                     int32_t* apply_rows) {
+                     int32_t* apply_rows, int32_t* gemm_mfma) {
   if (!c) return MBDDC_ERR_ARG;
   if (c->state < 1) return MBDDC_ERR_STATE;
   for (int b = 0; b < kSymBuckets; ++b) {
@@ -2301,6 +2342,7 @@ int mbddc_get_tuning(const mbddc_ctx* c, int32_t* sym_fp64, int32_t* sym_fp32, i
   }
   if (apply_xchunk) *apply_xchunk = c->tune.xchunk;
   for (int k = 0; k < 4 && apply_rows; ++k) apply_rows[k] = c->apply_rows_eff[k];
+  if (gemm_mfma) *gemm_mfma = c->tune.gemm_mfma;
   return MBDDC_OK;
 }
 

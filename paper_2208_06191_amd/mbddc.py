@@ -102,7 +102,7 @@ _SIGNATURES = {
     "mbddc_set_profiling": [ctypes.c_void_p, ctypes.c_uint32],
     "mbddc_autotune": [ctypes.c_void_p, ctypes.c_char_p],
     "mbddc_get_tuning": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
-                         ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)],
+                         ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)],
     "mbddc_profile_family_name": [ctypes.c_int],
     "mbddc_get_profile": [ctypes.c_void_p, ctypes.POINTER(mbddc_kernel_stat), ctypes.c_int,
                           ctypes.POINTER(ctypes.c_int)],
@@ -376,8 +376,10 @@ class Solver:
         a32 = (ctypes.c_int32 * 4)()
         xc = ctypes.c_int32()
         rows = (ctypes.c_int32 * 4)()
-        _check(lib().mbddc_get_tuning(self._h, a64, a32, ctypes.byref(xc), rows), "mbddc_get_tuning")
-        return {"sym_fp64": list(a64), "sym_fp32": list(a32), "apply_xchunk": xc.value, "apply_rows": list(rows)}
+        gm = ctypes.c_int32()
+        _check(lib().mbddc_get_tuning(self._h, a64, a32, ctypes.byref(xc), rows, ctypes.byref(gm)), "mbddc_get_tuning")
+        return {"sym_fp64": list(a64), "sym_fp32": list(a32), "apply_xchunk": xc.value, "apply_rows": list(rows),
+                "gemm_mfma": gm.value}
 
     # -- profiling -----------------------------------------------------------------
     def mbddc_set_profiling(self, mask: int = 0xFFFFFFFF):

@@ -664,3 +664,21 @@ def config_small() -> Problem:
 def config_nh32(nrhs: int = 4) -> Problem:
     """32^3 Q1 neo-Hookean (mu=1, kappa=50) at the 8-mode field, 512 subdomains of 4^3, primal VE."""
     return neo_hookean_box(32, 4, 1, nrhs=nrhs, primal=3, name="neo_hookean_32cube_512sub_VE")
+
+
+def ventricle_newton(target_dofs: float, n_steps: int, seed: int, part_dofs: int = 2000, amplitude: float = 0.015):
+    """One serving request on the ventricle-like shell: the mesh (two Q2 elements through the
+    wall, n_theta = n_phi chosen for about target_dofs DOFs), an RCB partition into parts of at
+    most part_dofs DOFs, and the Guccione element tangents of n_steps Newton iterates
+    u_k = u0 + (k / n_steps) du (isochoric fields of the physical coordinates, seeds seed and
+    seed + 1). Returns (mesh, part, n_sub, dirichlet, Ks [n_steps, n_el, 81, 81])."""
+    m = max(6, int(round(np.sqrt(target_dofs / 60.0))))
+    mesh, param = ventricle_mesh(2, m, m, 2)
+    part, nsub = rcb_partition(mesh, param, part_dofs, seed)
+    dirichlet = clamp_dofs(mesh, VENT_BASE)
+    frames = ventricle_frames(mesh, param)
+    u0 = isochoric_field(mesh.coords, seed, amplitude)
+    du = isochoric_field(mesh.coords, seed + 1, 0.5 * amplitude)
+    Ks = np.stack([element_tangents(mesh, guccione(), u0 + (k / n_steps) * du,
+                                    frames_fn=lambda elems, q: frames[elems]) for k in range(n_steps)])
+    return mesh, part, nsub, dirichlet, Ks

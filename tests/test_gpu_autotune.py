@@ -45,6 +45,7 @@ def test_autotuned_handle_matches_default(name, primal, precision, tmp_path):
     assert all(0 <= v <= 3 for v in table["sym_fp64"] + table["sym_fp32"])
     assert table["apply_xchunk"] in (128, 256, 512, 1024)
     assert all(r in (128, 256) for r in table["apply_rows"]) and on_disk["apply_rows"] == table["apply_rows"]
+    assert table["gemm_mfma"] in (0, 1) and on_disk["gemm_mfma"] == table["gemm_mfma"]
     xt, it = t.mbddc_solve(P.rhs)
     xd, idd = d.mbddc_solve(P.rhs)
     print(f"{name} prec={precision}: table {table}, its {it.iterations} vs {idd.iterations}")
@@ -66,8 +67,9 @@ def test_every_variant_meets_the_oracle_bounds(variant, name, primal, tmp_path):
     P = problem(name)
     path = tmp_path / "forced.json"
     rows = [128, 128, 128, 128] if variant in ("lds16", "blocked") else [256, 256, 256, 256]
+    gemm = 1 if variant in ("lds16", "blocked") else 0      # matrix-core and vector GEMMs
     path.write_text(json.dumps({"mbddc_tune": 1, "sym_fp64": FORCED[variant], "sym_fp32": [2, 2, 1, 1],
-                                "apply_xchunk": 256, "apply_rows": rows}))
+                                "apply_xchunk": 256, "apply_rows": rows, "gemm_mfma": gemm}))
     s = handle(P, primal, mbddc.MBDDC_FP64, table=path)
     dec = bddc.Decomposition(P.mesh.elem_nodes, P.mesh.n_nodes, P.elem_part, P.n_sub, P.dirichlet,
                              P.mesh.node_tags, primal=primal)

@@ -30,15 +30,19 @@ def request_case(kind: str, n: int, steps: int = 3, seed: int = 0):
         part, nsub = W.block_partition(mesh, 4 if n % 4 == 0 else 3)
         mat = W.linear_elastic(1.0, 0.3)
         primal, order = 1, 1
+    elif kind == "vent":   # Guccione shell, RCB parts of <= n DOFs (some blocks beyond 304 rows)
+        mesh, part, nsub, dirichlet, Ks = W.ventricle_newton(8e3, steps, 40 + seed, part_dofs=n)
+        primal = 7
     else:   # "q2"
         mesh = W.box_mesh(n, n, n, 2)
         part, nsub = W.block_partition(mesh, 2)
         mat = W.neo_hookean(1.0, 50.0)
         primal, order = 3, 2
-    dirichlet = W.clamp_dofs(mesh, 1)
-    u0 = W.isochoric_field(mesh.coords, seed, 0.02)
-    du = W.isochoric_field(mesh.coords, seed + 50, 0.01)
-    Ks = W.newton_tangents(mesh, mat, u0, du, steps)
+    if kind != "vent":
+        dirichlet = W.clamp_dofs(mesh, 1)
+        u0 = W.isochoric_field(mesh.coords, seed, 0.02)
+        du = W.isochoric_field(mesh.coords, seed + 50, 0.01)
+        Ks = W.newton_tangents(mesh, mat, u0, du, steps)
     rhs = np.stack([W._loads(mesh, dirichlet, 2, 10 * seed + k) for k in range(steps)])
     m = mbddc._MeshArrays(mesh.coords, mesh.elem_nodes, mesh.elem_type, part, nsub, mesh.node_tags, dirichlet)
     free = np.setdiff1d(np.arange(3 * mesh.n_nodes), dirichlet)
@@ -95,7 +99,7 @@ def test_server_request_equals_direct_handle(lagged):
 
 def test_each_result_same_alone_and_in_the_mix():
     cases = [request_case("nh", 8), request_case("lin", 12), request_case("q2", 4), request_case("nh", 12, seed=1),
-             request_case("lin", 8, seed=2), request_case("nh", 9, seed=3)]
+             request_case("lin", 8, seed=2), request_case("nh", 9, seed=3), request_case("vent", 900)]
     alone = []
     srv = mbddc.Server(0, 32 << 30, 1)
     for c in cases:

@@ -183,3 +183,17 @@ def test_ventricle_guccione_tangent_is_derivative_of_internal_force():
     Q = W.ventricle_frames(mesh, param)
     u = W.isochoric_field(mesh.coords, 2, 0.015)
     assert _fd_check(mesh, W.guccione(), u, frames_fn=lambda e, q: Q[e]) < 1e-7
+
+
+def test_ventricle_newton_request_shapes_and_first_step():
+    """A serving request on the shell: RCB parts within the bound, base clamped, and step 0's
+    tangents are those of the first iterate u0 (the steps differ)."""
+    mesh, part, nsub, dirichlet, Ks = W.ventricle_newton(1.2e4, 3, 41, part_dofs=2000)
+    assert Ks.shape == (3, mesh.n_elems, 81, 81)
+    assert part.min() == 0 and part.max() == nsub - 1
+    for i in range(nsub):
+        nodes = np.unique(mesh.elem_nodes[part == i])
+        assert 3 * len(nodes) <= 2000
+    assert len(dirichlet) > 0 and np.all(mesh.node_tags[np.asarray(dirichlet) // 3] & W.VENT_BASE)
+    assert np.allclose(Ks[0], Ks[0].transpose(0, 2, 1), atol=1e-10 * np.abs(Ks[0]).max())
+    assert np.abs(Ks[2] - Ks[0]).max() > 1e-6 * np.abs(Ks[0]).max()
