@@ -250,9 +250,10 @@ int mbddc_get_profile(mbddc_ctx* ctx, mbddc_kernel_stat* out, int max_entries, i
  * >= set_tangent) and leaves the handle factorised with the chosen table. table_out (may be
  * NULL): JSON file
  *   {"mbddc_tune": 1, "sym_fp64": [v0, v1, v2, v3], "sym_fp32": [v0, v1, v2, v3], "apply_xchunk": C,
- *    "apply_rows": [A, C, F, H], "gemm_mfma": G}
- * (plus informative keys; "apply_rows" optional, 0 = the size that pads the row counts least;
- * "gemm_mfma" optional, default 0),
+ *    "apply_rows": [A, C, F, H], "apply_rows2": [A, C, F, H], "gemm_mfma": G}
+ * (plus informative keys; "apply_rows" and "apply_rows2" (level-2 instance of three-level
+ * handles) optional, 0 = the size that pads the row counts least; "gemm_mfma" optional,
+ * default 0),
  * to be passed as options.tune_table to later handles. A table variant
  * that cannot take some matrix (size or precision) falls back to one that can. Errors as
  * mbddc_factor; MBDDC_ERR_ARG if table_out cannot be written. */

@@ -121,10 +121,11 @@ struct Tuning {
   int32_t sym[2][kSymBuckets];      // [0] FP64, [1] FP32
   int32_t xchunk;
   int32_t apply_rows[4];            // rows per workgroup of apply phases A, C, F, H (128, 256; 0 = by size)
+  int32_t apply_rows2[4];           // the same for the level-2 instance of three-level handles
   int32_t gemm_mfma;                // FP64 batched GEMMs on the matrix cores (1) or the vector units (0)
   Tuning() {
     gemm_mfma = 0;
-    for (int k = 0; k < 4; ++k) apply_rows[k] = 0;
+    for (int k = 0; k < 4; ++k) apply_rows[k] = apply_rows2[k] = 0;
     const int d64[kSymBuckets] = {SV_REG, SV_REG, SV_BLOCKED, SV_BLOCKED};
     const int d32[kSymBuckets] = {SV_BP32, SV_BP32, SV_BP16, SV_BP16};
     for (int b = 0; b < kSymBuckets; ++b) {
@@ -450,6 +451,13 @@ size_t elem_size(bool mixed) { return mixed ? sizeof(float) : sizeof(double); }
 // ----------------------------------------------------------------------------
 // symbolic layout on top of the host plan
 // ----------------------------------------------------------------------------
+// Tuning of a level-2 instance: its parent's table, with the parent's level-2 apply rows.
+Tuning child_tuning(const Tuning& t) {
+  Tuning u = t;
+  for (int k = 0; k < 4; ++k) u.apply_rows[k] = t.apply_rows2[k];
+  return u;
+}
+
 // Row blocks of the local apply phases: rows per workgroup 128 or 256 per phase, from the
 // tuning table, or (0) the size that pads the phase's row counts least (256 on ties).
 void build_apply_items(mbddc_ctx* c) {
@@ -879,7 +887,7 @@ int build_level2_host(mbddc_ctx* c, const std::vector<MeshIn>& fine) {
   ch->mixed = false;
   ch->fact32 = false;
   ch->sym = c->sym;
-  ch->tune = c->tune;
+  ch->tune = child_tuning(c->tune);
   if (!build_plan(m2, ch->opt.primal, ch->plan).empty()) return MBDDC_ERR_ARG;
   return build_layout(ch);
 }
@@ -1975,6 +1983,11 @@ int read_tuning(const char* path, Tuning& t) {
     for (int k = 0; k < 4; ++k)
       if (r.apply_rows[k] != 0 && r.apply_rows[k] != 128 && r.apply_rows[k] != 256) return MBDDC_ERR_ARG;
   }
+  if (text.find("\"apply_rows2\"") != std::string::npos) {
+    if (!ints_after("\"apply_rows2\"", r.apply_rows2, 4)) return MBDDC_ERR_ARG;
+    for (int k = 0; k < 4; ++k)
+      if (r.apply_rows2[k] != 0 && r.apply_rows2[k] != 128 && r.apply_rows2[k] != 256) return MBDDC_ERR_ARG;
+  }
   for (int p = 0; p < 2; ++p)
     for (int b = 0; b < kSymBuckets; ++b)
       if (r.sym[p][b] < 0 || r.sym[p][b] >= SV_COUNT) return MBDDC_ERR_ARG;
@@ -2044,7 +2057,7 @@ int rebuild_symsets(mbddc_ctx* c) {
   HIPCHK(hipStreamSynchronize(c->stream));
   c->apply_gen++;                 // staging width and row blocks are baked into the captured applies
   if (c->child) {
-    c->child->tune = c->tune;
+    c->child->tune = child_tuning(c->tune);
     CHK(rebuild_symsets(c->child));
   }
   return MBDDC_OK;
@@ -2156,6 +2169,23 @@ int autotune_impl(mbddc_ctx* c) {
       }
     }
     c->tune.apply_rows[k] = best_r;
+  }
+  // rows per workgroup of the level-2 apply phases
+  for (int k = 0; k < 4 && c->child; ++k) {
+    int best_r = c->child->apply_rows_eff[k];
+    best_t = 1e300;
+    for (int rw : {256, 128}) {
+      c->tune.apply_rows2[k] = rw;
+      CHK(rebuild_symsets(c));
+      CHK(apply_dispatch(c, 4, c->d_X, c->d_Y));
+      double t = 0.0;
+      CHK(time_best(c, 5, [&] { return apply_dispatch(c, 4, c->d_X, c->d_Y); }, &t));
+      if (t < best_t) {
+        best_t = t;
+        best_r = rw;
+      }
+    }
+    c->tune.apply_rows2[k] = best_r;
   }
   CHK(rebuild_symsets(c));
   return MBDDC_OK;
@@ -2321,11 +2351,13 @@ int mbddc_autotune(mbddc_ctx* c, const char* table_out) {
                  "{\"mbddc_tune\": 1,\n \"variants\": [\"%s\", \"%s\", \"%s\", \"%s\"],\n"
                  " \"bucket_max_n\": [%d, %d, %d, null],\n"
                  " \"sym_fp64\": [%d, %d, %d, %d],\n \"sym_fp32\": [%d, %d, %d, %d],\n"
-                 " \"apply_xchunk\": %d,\n \"apply_rows\": [%d, %d, %d, %d],\n \"gemm_mfma\": %d}\n",
+                 " \"apply_xchunk\": %d,\n \"apply_rows\": [%d, %d, %d, %d],\n"
+                 " \"apply_rows2\": [%d, %d, %d, %d],\n \"gemm_mfma\": %d}\n",
                  kSymVariantName[0], kSymVariantName[1], kSymVariantName[2], kSymVariantName[3], kSymBucketMax[0],
                  kSymBucketMax[1], kSymBucketMax[2], t.sym[0][0], t.sym[0][1], t.sym[0][2], t.sym[0][3], t.sym[1][0],
                  t.sym[1][1], t.sym[1][2], t.sym[1][3], t.xchunk, c->apply_rows_eff[0], c->apply_rows_eff[1],
-                 c->apply_rows_eff[2], c->apply_rows_eff[3], t.gemm_mfma);
+                 c->apply_rows_eff[2], c->apply_rows_eff[3], t.apply_rows2[0], t.apply_rows2[1], t.apply_rows2[2],
+                 t.apply_rows2[3], t.gemm_mfma);
     const bool bad = std::ferror(f) != 0;
     if (std::fclose(f) != 0 || bad) return MBDDC_ERR_ARG;
   }
