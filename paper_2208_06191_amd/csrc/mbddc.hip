@@ -1296,8 +1296,15 @@ int factor_impl(mbddc_ctx* c) {
     }
     {
       ProfScope ps(c, F_EXTRACT, 0.0, 0.0);
-      hipLaunchKernelGGL((k_constraint_products<T>), dim3(nsub), dim3(kBlock), 0, c->stream, c->d_subs,
-                         c->d_cons_ptr, c->d_cons_idx, c->d_cons_w, W);
+      {
+        int64_t maxw = 1;   // largest n_G n_c of a subdomain: rows of stage 0 spread over workgroups
+        for (const SubDev& d : c->subs) maxw = std::max<int64_t>(maxw, (int64_t)d.nG * d.nc);
+        const unsigned parts = (unsigned)std::min<int64_t>(64, (maxw + 4 * kBlock - 1) / (4 * kBlock));
+        hipLaunchKernelGGL((k_constraint_products<T, 0>), dim3(parts, nsub), dim3(kBlock), 0, c->stream, c->d_subs,
+                           c->d_cons_ptr, c->d_cons_idx, c->d_cons_w, W);
+        hipLaunchKernelGGL((k_constraint_products<T, 1>), dim3(1, nsub), dim3(kBlock), 0, c->stream, c->d_subs,
+                           c->d_cons_ptr, c->d_cons_idx, c->d_cons_w, W);
+      }
       HIPCHK(hipGetLastError());
       CHK(run_symset<T>(c, W, c->set_t));
       st = check_status(c, (int64_t)c->set_t.all.size(), c->set_t.all, &bad);
