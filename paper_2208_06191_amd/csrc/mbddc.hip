@@ -458,7 +458,7 @@ Tuning child_tuning(const Tuning& t) {
   return u;
 }
 
-// Row blocks of the local apply phases: rows per workgroup 128 or 256 per phase, from the
+// Row blocks of the local apply phases: at most 128 or 256 rows per workgroup per phase, from the
 // tuning table, or (0) the size that pads the phase's row counts least (256 on ties).
 void build_apply_items(mbddc_ctx* c) {
   c->itA.clear(); c->itC.clear(); c->itF.clear(); c->itH.clear();
@@ -478,9 +478,14 @@ void build_apply_items(mbddc_ctx* c) {
       rw = pad[0] < pad[1] ? 128 : 256;
     }
     c->apply_rows_eff[k] = rw;
+    // a subdomain's rows split into equal blocks (multiples of 4) of at most rw rows, so that
+    // the workgroups of a phase carry about the same work
     for (int64_t s = 0; s < (int64_t)c->subs.size(); ++s) {
-      const int64_t nb = std::max<int64_t>(1, (rows_of(c->subs[s], k) + rw - 1) / rw);
-      for (int64_t b = 0; b < nb; ++b) lists[k]->push_back({(int32_t)s, (int32_t)(b * rw), 0, 0});
+      const int64_t r = rows_of(c->subs[s], k);
+      const int64_t nb = std::max<int64_t>(1, (r + rw - 1) / rw);
+      const int64_t bs = std::max<int64_t>(4, round_up((r + nb - 1) / nb, 4));
+      for (int64_t b = 0; b < nb; ++b)
+        lists[k]->push_back({(int32_t)s, (int32_t)(b * bs), 0, (int32_t)std::max<int64_t>(0, std::min(bs, r - b * bs))});
     }
   }
 }
