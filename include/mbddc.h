@@ -244,16 +244,18 @@ int mbddc_get_profile(mbddc_ctx* ctx, mbddc_kernel_stat* out, int max_entries, i
  * numeric factorisation (best of two): 0 register-resident sweep (FP64, n <= 304), 1 one-
  * workgroup sweep with 16-index panels in LDS, 2 the same with 32-index panels, 3 batched
  * blocked sweep (FP64); then the number of input columns the apply stages in LDS (128, 256,
- * 512 or 1024) and the rows per workgroup of each local apply phase A, C, F, H (256: four
- * rows per lane, 128: two) by timing applies of four right-hand sides; FP64 factorisations
+ * 512 or 1024), the column grouping of the local apply and the rows per workgroup of each
+ * local apply phase A, C, F, H (256: four rows per lane, 128: two) by timing applies of four
+ * right-hand sides; FP64 factorisations
  * also time their batched GEMMs on the vector units (0) and the matrix cores (1). Needs a tangent (state
  * >= set_tangent) and leaves the handle factorised with the chosen table. table_out (may be
  * NULL): JSON file
  *   {"mbddc_tune": 1, "sym_fp64": [v0, v1, v2, v3], "sym_fp32": [v0, v1, v2, v3], "apply_xchunk": C,
- *    "apply_rows": [A, C, F, H], "apply_rows2": [A, C, F, H], "gemm_mfma": G}
+ *    "apply_rows": [A, C, F, H], "apply_rows2": [A, C, F, H], "apply_groups": P, "gemm_mfma": G}
  * (plus informative keys; "apply_rows" and "apply_rows2" (level-2 instance of three-level
- * handles) optional, 0 = the size that pads the row counts least; "gemm_mfma" optional,
- * default 0),
+ * handles) optional, 0 = the size that pads the row counts least; "apply_groups" optional,
+ * 1 = large column groups over long ranges, 0 = small groups only, -1 (default) = large when
+ * some local block has 512 columns or more; "gemm_mfma" optional, default 0),
  * to be passed as options.tune_table to later handles. A table variant
  * that cannot take some matrix (size or precision) falls back to one that can. Errors as
  * mbddc_factor; MBDDC_ERR_ARG if table_out cannot be written. */

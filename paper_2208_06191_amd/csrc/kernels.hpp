@@ -13,6 +13,7 @@ constexpr int kGjMax = 512;          // largest matrix of the one-workgroup Gaus
 constexpr int kCoarseBlock = 64;     // diagonal block of the multi-workgroup coarse inversion
 constexpr int kCoarseChunk = 256;    // columns per workgroup in the coarse product
 constexpr int kApplyChunk = 1024;    // input columns staged in LDS at a time by the local apply
+constexpr int kApplyBigCols = 512;   // local blocks this wide take the large column groups (by size)
 
 // Per-subdomain device descriptor. Offsets are element counts into the
 // per-precision work buffers. Dense work matrices are row-major; apply

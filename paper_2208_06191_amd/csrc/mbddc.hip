@@ -123,8 +123,10 @@ struct Tuning {
   int32_t apply_rows[4];            // rows per workgroup of apply phases A, C, F, H (128, 256; 0 = by size)
   int32_t apply_rows2[4];           // the same for the level-2 instance of three-level handles
   int32_t gemm_mfma;                // FP64 batched GEMMs on the matrix cores (1) or the vector units (0)
+  int32_t apply_big;                // apply column groups: 1 large first, 0 small only, -1 by size
   Tuning() {
     gemm_mfma = 0;
+    apply_big = -1;
     for (int k = 0; k < 4; ++k) apply_rows[k] = apply_rows2[k] = 0;
     const int d64[kSymBuckets] = {SV_REG, SV_REG, SV_BLOCKED, SV_BLOCKED};
     const int d32[kSymBuckets] = {SV_BP32, SV_BP32, SV_BP16, SV_BP16};
@@ -455,6 +457,7 @@ size_t elem_size(bool mixed) { return mixed ? sizeof(float) : sizeof(double); }
 Tuning child_tuning(const Tuning& t) {
   Tuning u = t;
   for (int k = 0; k < 4; ++k) u.apply_rows[k] = t.apply_rows2[k];
+  u.apply_big = -1;
   return u;
 }
 
@@ -1421,10 +1424,12 @@ template <typename To, int R, int PH>
 void launch_local(mbddc_ctx* c, const ApplyArgs& a, int k, size_t n_items) {
   const int rw = c->apply_rows_eff[k];
   const size_t lds = (size_t)(4 * rw * R + (size_t)a.xchunk * R) * sizeof(double);
-  if (rw == 128)
-    hipLaunchKernelGGL((k_apply_local<To, R, PH, 2>), dim3((unsigned)n_items), dim3(kBlock), lds, c->stream, a);
-  else
-    hipLaunchKernelGGL((k_apply_local<To, R, PH, 4>), dim3((unsigned)n_items), dim3(kBlock), lds, c->stream, a);
+  const bool big = c->tune.apply_big > 0 || (c->tune.apply_big < 0 && c->max_cols >= kApplyBigCols);
+  const dim3 g((unsigned)n_items), b(kBlock);
+  if (rw == 128 && big) hipLaunchKernelGGL((k_apply_local<To, R, PH, 2, true>), g, b, lds, c->stream, a);
+  else if (rw == 128) hipLaunchKernelGGL((k_apply_local<To, R, PH, 2, false>), g, b, lds, c->stream, a);
+  else if (big) hipLaunchKernelGGL((k_apply_local<To, R, PH, 4, true>), g, b, lds, c->stream, a);
+  else hipLaunchKernelGGL((k_apply_local<To, R, PH, 4, false>), g, b, lds, c->stream, a);
 }
 
 // z = M^-1 r. For the level-2 instance of a three-level handle (parent != null) the input
@@ -1512,15 +1517,23 @@ int apply_attrs() {
   static int st = MBDDC_OK;
   std::call_once(once, [] {
     const size_t mx = 160 * 1024;
-    int e = set_lds(k_apply_local<To, R, 0, 4>, mx);
-    if (!e) e = set_lds(k_apply_local<To, R, 1, 4>, mx);
-    if (!e) e = set_lds(k_apply_local<To, R, 3, 4>, mx);
-    if (!e) e = set_lds(k_apply_local<To, R, 4, 4>, mx);
-    if (!e) e = set_lds(k_apply_local<To, R, 0, 2>, mx);
-    if (!e) e = set_lds(k_apply_local<To, R, 1, 2>, mx);
-    if (!e) e = set_lds(k_apply_local<To, R, 3, 2>, mx);
-    if (!e) e = set_lds(k_apply_local<To, R, 4, 2>, mx);
-    if (!e) e = set_lds(k_apply_coarse<To, R>, mx);
+    int e = set_lds(k_apply_coarse<To, R>, mx);
+    if (!e) e = set_lds(k_apply_local<To, R, 0, 4, false>, mx);
+    if (!e) e = set_lds(k_apply_local<To, R, 1, 4, false>, mx);
+    if (!e) e = set_lds(k_apply_local<To, R, 3, 4, false>, mx);
+    if (!e) e = set_lds(k_apply_local<To, R, 4, 4, false>, mx);
+    if (!e) e = set_lds(k_apply_local<To, R, 0, 2, false>, mx);
+    if (!e) e = set_lds(k_apply_local<To, R, 1, 2, false>, mx);
+    if (!e) e = set_lds(k_apply_local<To, R, 3, 2, false>, mx);
+    if (!e) e = set_lds(k_apply_local<To, R, 4, 2, false>, mx);
+    if (!e) e = set_lds(k_apply_local<To, R, 0, 4, true>, mx);
+    if (!e) e = set_lds(k_apply_local<To, R, 1, 4, true>, mx);
+    if (!e) e = set_lds(k_apply_local<To, R, 3, 4, true>, mx);
+    if (!e) e = set_lds(k_apply_local<To, R, 4, 4, true>, mx);
+    if (!e) e = set_lds(k_apply_local<To, R, 0, 2, true>, mx);
+    if (!e) e = set_lds(k_apply_local<To, R, 1, 2, true>, mx);
+    if (!e) e = set_lds(k_apply_local<To, R, 3, 2, true>, mx);
+    if (!e) e = set_lds(k_apply_local<To, R, 4, 2, true>, mx);
     st = e;
   });
   return st;
@@ -1987,6 +2000,9 @@ int read_tuning(const char* path, Tuning& t) {
   if (!ints_after("\"sym_fp64\"", r.sym[0], kSymBuckets) || !ints_after("\"sym_fp32\"", r.sym[1], kSymBuckets) ||
       !ints_after("\"apply_xchunk\"", &r.xchunk, 1))
     return MBDDC_ERR_ARG;
+  if (text.find("\"apply_groups\"") != std::string::npos) {
+    if (!ints_after("\"apply_groups\"", &r.apply_big, 1) || r.apply_big < -1 || r.apply_big > 1) return MBDDC_ERR_ARG;
+  }
   if (text.find("\"gemm_mfma\"") != std::string::npos) {
     if (!ints_after("\"gemm_mfma\"", &r.gemm_mfma, 1) || (r.gemm_mfma != 0 && r.gemm_mfma != 1)) return MBDDC_ERR_ARG;
   }
@@ -2165,6 +2181,22 @@ int autotune_impl(mbddc_ctx* c) {
   }
   c->tune.xchunk = best_x;
   if (c->child) c->child->tune.xchunk = best_x;
+  {   // apply column groups of the local phases
+    int best_g = 0;
+    best_t = 1e300;
+    for (int g : {0, 1}) {
+      c->tune.apply_big = g;
+      CHK(rebuild_symsets(c));
+      CHK(apply_dispatch(c, 4, c->d_X, c->d_Y));
+      double t = 0.0;
+      CHK(time_best(c, 5, [&] { return apply_dispatch(c, 4, c->d_X, c->d_Y); }, &t));
+      if (t < best_t) {
+        best_t = t;
+        best_g = g;
+      }
+    }
+    c->tune.apply_big = best_g;
+  }
   // rows per workgroup of each local apply phase
   for (int k = 0; k < 4; ++k) {
     int best_r = c->apply_rows_eff[k];
@@ -2364,12 +2396,12 @@ int mbddc_autotune(mbddc_ctx* c, const char* table_out) {
                  " \"bucket_max_n\": [%d, %d, %d, null],\n"
                  " \"sym_fp64\": [%d, %d, %d, %d],\n \"sym_fp32\": [%d, %d, %d, %d],\n"
                  " \"apply_xchunk\": %d,\n \"apply_rows\": [%d, %d, %d, %d],\n"
-                 " \"apply_rows2\": [%d, %d, %d, %d],\n \"gemm_mfma\": %d}\n",
+                 " \"apply_rows2\": [%d, %d, %d, %d],\n \"apply_groups\": %d,\n \"gemm_mfma\": %d}\n",
                  kSymVariantName[0], kSymVariantName[1], kSymVariantName[2], kSymVariantName[3], kSymBucketMax[0],
                  kSymBucketMax[1], kSymBucketMax[2], t.sym[0][0], t.sym[0][1], t.sym[0][2], t.sym[0][3], t.sym[1][0],
                  t.sym[1][1], t.sym[1][2], t.sym[1][3], t.xchunk, c->apply_rows_eff[0], c->apply_rows_eff[1],
                  c->apply_rows_eff[2], c->apply_rows_eff[3], t.apply_rows2[0], t.apply_rows2[1], t.apply_rows2[2],
-                 t.apply_rows2[3], t.gemm_mfma);
+                 t.apply_rows2[3], t.apply_big, t.gemm_mfma);
     const bool bad = std::ferror(f) != 0;
     if (std::fclose(f) != 0 || bad) return MBDDC_ERR_ARG;
   }
