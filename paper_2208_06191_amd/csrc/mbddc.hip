@@ -327,6 +327,9 @@ struct mbddc_ctx {
   double* h_norm = nullptr;      // pinned host
   Profiler prof;
   hipStream_t aux = nullptr;     // lookahead stream of the coarse sweep (default priority)
+  hipStream_t side = nullptr;    // operator extraction overlapped with the coarse factorisation (default priority)
+  hipEvent_t ev_side = nullptr;
+  bool side_pending = false;
   hipEvent_t ev_a = nullptr, ev_b = nullptr;
   // algorithmic bytes / flops per launch, filled by build_layout
   double op_bytes[F_COUNT] = {};
@@ -391,6 +394,14 @@ void free_all(mbddc_ctx* c) {
   }
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   c->cap_stream = nullptr;
+  if (c->side) {
+    (void)hipStreamSynchronize(c->side);
+    (void)hipStreamDestroy(c->side);
+  }
+  if (c->ev_side) (void)hipEventDestroy(c->ev_side);
+  c->side = nullptr;
+  c->ev_side = nullptr;
+  c->side_pending = false;
   if (c->ev_a) (void)hipEventDestroy(c->ev_a);
   if (c->ev_b) (void)hipEventDestroy(c->ev_b);
   if (c->aux) (void)hipStreamDestroy(c->aux);
@@ -1329,8 +1340,27 @@ int factor_impl(mbddc_ctx* c) {
         launch_gemm<T>(c, (unsigned)c->gemm_items_stil.size(),
                            c->stream, c->d_gemm_desc, c->d_gemm_stil, W, W, W, W);
       const unsigned parts = (unsigned)std::min(64, std::max(1, (c->max_cols + 127) / 128));
-      hipLaunchKernelGGL((k_extract_sym<T, To>), dim3(parts, nsub), dim3(kBlock), 0, c->stream, c->d_subs, c->d_slot_w, W,
-                         Op);
+      // the apply operators are not needed by the coarse problem: unless its families or the
+      // extraction are being timed, they are written on a side stream while the coarse problem
+      // (or the level-2 setup) is factorised on the handle's stream
+      const uint32_t timed = (1u << F_EXTRACT) | (1u << F_LEVEL2_SETUP) | (1u << F_COARSE_ASSEMBLE) |
+                             (1u << F_COARSE_GJ_SMALL) | (1u << F_COARSE_DIAG) | (1u << F_COARSE_PREP) |
+                             (1u << F_COARSE_GEMM) | (1u << F_COARSE_ROWS);
+      hipStream_t es = c->stream;
+      if (P.n_coarse > 0 && !(c->prof.mask & timed)) {
+        if (!c->side) {
+          HIPCHK(hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
+          HIPCHK(hipEventCreateWithFlags(&c->ev_side, hipEventDisableTiming));
+        }
+        HIPCHK(hipEventRecord(c->ev_side, c->stream));
+        HIPCHK(hipStreamWaitEvent(c->side, c->ev_side, 0));
+        es = c->side;
+      }
+      hipLaunchKernelGGL((k_extract_sym<T, To>), dim3(parts, nsub), dim3(kBlock), 0, es, c->d_subs, c->d_slot_w, W, Op);
+      if (es != c->stream) {
+        HIPCHK(hipEventRecord(c->ev_side, c->side));
+        c->side_pending = true;
+      }
     }
     HIPCHK(hipGetLastError());
   } else {
@@ -1355,6 +1385,8 @@ int factor_impl(mbddc_ctx* c) {
                          c->d_Kcl);
     }
   }
+  // coarse problem (the extraction may still run on the side stream: joined below on every path)
+  auto coarse_part = [&]() -> int {
   if (P.n_coarse > 0 && c->child) {
     // multilevel BDDC: S_PiPi is handed to the level-2 BDDC setup unassembled
     if (c->d_Kc_keep) {
@@ -1408,6 +1440,15 @@ int factor_impl(mbddc_ctx* c) {
     }
     for (int32_t ii : c->coarse_large) CHK(c->sym ? coarse_sweep_large(c, ii) : coarse_invert_large(c, ii));
   }
+  return MBDDC_OK;
+  };
+  const int st_coarse = coarse_part();
+  if (c->side_pending) {
+    const hipError_t e = hipStreamWaitEvent(c->stream, c->ev_side, 0);
+    c->side_pending = false;
+    if (e != hipSuccess) return MBDDC_ERR_DEVICE;
+  }
+  if (st_coarse != MBDDC_OK) return st_coarse;
   HIPCHK(hipStreamSynchronize(c->stream));
   return MBDDC_OK;
 }
