@@ -2338,7 +2338,6 @@ int mbddc_footprint(const mbddc_ctx* c, size_t* device_bytes) {
   if (!c || !device_bytes) return MBDDC_ERR_ARG;
   if (c->state < 1) return MBDDC_ERR_STATE;
   const Plan& P = c->plan;
-  const size_t es = elem_size(c->mixed);
   const int R = 4, J = c->opt.restart + 1;
   // per-call buffers that a solve with 4 right-hand sides allocates, unless already held
   size_t extra = 0;

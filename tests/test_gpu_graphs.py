@@ -84,3 +84,23 @@ def test_profiled_applies_run_eagerly():
     assert i2.applies_graphed == i2.applies
     g.mbddc_set_profiling(0)
     assert np.array_equal(x1, x2)
+
+
+@pytest.mark.parametrize("levels", [2, 3])
+def test_overlapped_extraction_equals_sequential(levels):
+    """The apply operators are extracted on a side stream while the coarse problem is factorised,
+    except while the factorisation's families are profiled: both orders give identical results."""
+    P = problem("l3_nh")
+    a = handle(P, 3, levels, 1)
+    b = mbddc.Solver(0)
+    b.mbddc_setup_symbolic([mbddc.mesh_from_problem(P)],
+                           mbddc.default_options(precision=mbddc.MBDDC_MIXED, primal=3, symmetric_hint=1,
+                                                 levels=levels))
+    b.mbddc_set_tangent(P.Ke)
+    b.mbddc_set_profiling(0xFFFFFFFF)          # every family timed: sequential extraction
+    b.mbddc_factor()
+    b.mbddc_set_profiling(0)
+    b.mbddc_get_profile()
+    xa, ia = a.mbddc_solve(P.rhs)
+    xb, ib = b.mbddc_solve(P.rhs)
+    assert ia.iterations == ib.iterations and np.array_equal(xa, xb)
