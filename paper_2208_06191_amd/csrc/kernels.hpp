@@ -14,6 +14,7 @@ constexpr int kCoarseBlock = 64;     // diagonal block of the multi-workgroup co
 constexpr int kCoarseChunk = 256;    // columns per workgroup in the coarse product
 constexpr int kApplyChunk = 1024;    // input columns staged in LDS at a time by the local apply
 constexpr int kApplyBigCols = 512;   // local blocks this wide take the large column groups (by size)
+constexpr int kSpmvWideRow = 40;     // mean blocks per node row above which a node row takes 64 lanes
 
 // Per-subdomain device descriptor. Offsets are element counts into the
 // per-precision work buffers. Dense work matrices are row-major; apply

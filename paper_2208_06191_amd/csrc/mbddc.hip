@@ -1639,16 +1639,29 @@ int apply_run(mbddc_ctx* c, int R) {
   return MBDDC_OK;
 }
 
-int spmv_dispatch(mbddc_ctx* c, int R, const double* x, double* y) {
-  const int64_t nd = c->plan.n_dofs;
-  const unsigned g = nblk(nd * 16);
-  ProfScope ps(c, F_SPMV, c->op_bytes[F_SPMV] + 16.0 * R * nd, 18.0 * R * c->nblocks);
+template <int G>
+void launch_spmv(mbddc_ctx* c, int R, const double* x, double* y) {
+  const int64_t nn = c->plan.n_nodes;
+  const unsigned g = nblk(nn * G);
   switch (R) {
-    case 1: hipLaunchKernelGGL(k_spmv<1>, dim3(g), dim3(kBlock), 0, c->stream, c->d_bsr_rowptr, c->d_bsr_col, c->d_vals, nd, x, y); break;
-    case 2: hipLaunchKernelGGL(k_spmv<2>, dim3(g), dim3(kBlock), 0, c->stream, c->d_bsr_rowptr, c->d_bsr_col, c->d_vals, nd, x, y); break;
-    case 4: hipLaunchKernelGGL(k_spmv<4>, dim3(g), dim3(kBlock), 0, c->stream, c->d_bsr_rowptr, c->d_bsr_col, c->d_vals, nd, x, y); break;
-    default: hipLaunchKernelGGL(k_spmv<8>, dim3(g), dim3(kBlock), 0, c->stream, c->d_bsr_rowptr, c->d_bsr_col, c->d_vals, nd, x, y); break;
+    case 1: hipLaunchKernelGGL((k_spmv<1, G>), dim3(g), dim3(kBlock), 0, c->stream, c->d_bsr_rowptr, c->d_bsr_col, c->d_vals, nn, x, y); break;
+    case 2: hipLaunchKernelGGL((k_spmv<2, G>), dim3(g), dim3(kBlock), 0, c->stream, c->d_bsr_rowptr, c->d_bsr_col, c->d_vals, nn, x, y); break;
+    case 4: hipLaunchKernelGGL((k_spmv<4, G>), dim3(g), dim3(kBlock), 0, c->stream, c->d_bsr_rowptr, c->d_bsr_col, c->d_vals, nn, x, y); break;
+    default: hipLaunchKernelGGL((k_spmv<8, G>), dim3(g), dim3(kBlock), 0, c->stream, c->d_bsr_rowptr, c->d_bsr_col, c->d_vals, nn, x, y); break;
   }
+}
+
+int spmv_dispatch(mbddc_ctx* c, int R, const double* x, double* y) {
+  const int64_t nd = c->plan.n_dofs, nn = c->plan.n_nodes;
+  // 16-byte loads of x need a 16-byte aligned base (every block here comes from the allocator)
+  if ((reinterpret_cast<uintptr_t>(x) & 15) != 0) return MBDDC_ERR_UNSUPPORTED;
+  ProfScope ps(c, F_SPMV, c->op_bytes[F_SPMV] + 16.0 * R * nd, 18.0 * R * c->nblocks);
+  // 32 lanes (10 blocks per pass) suit rows of about 27 blocks (trilinear elements); rows of about
+  // 64 blocks and more (triquadratic elements) take a whole wave (21 blocks per pass)
+  if (c->nblocks > kSpmvWideRow * nn)
+    launch_spmv<64>(c, R, x, y);
+  else
+    launch_spmv<32>(c, R, x, y);
   HIPCHK(hipGetLastError());
   return MBDDC_OK;
 }
