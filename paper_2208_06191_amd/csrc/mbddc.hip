@@ -323,6 +323,14 @@ struct mbddc_ctx {
          *d_hnorm = nullptr, *d_y = nullptr, *d_beta = nullptr;
   int32_t *d_jsys = nullptr, *d_nk = nullptr;
   uint8_t *d_active = nullptr, *d_mode = nullptr, *d_fin = nullptr;
+  // per-system GMRES state sent in one copy when the host changes it:
+  // [jsys int32 x nsys][its int32 x nsys][active x nsys][mode x nsys]; d_jsys, d_its, d_active and
+  // d_mode point into d_kstate
+  uint8_t* d_kstate = nullptr;
+  int64_t kstate_n = 0;          // systems the state buffers were sized for (>= the current count)
+  int32_t* d_its = nullptr;
+  double* d_bnorm = nullptr;
+  uint8_t* h_kstate = nullptr;   // pinned host
   double* h_est = nullptr;       // pinned host
   double* h_norm = nullptr;      // pinned host
   Profiler prof;
@@ -412,7 +420,9 @@ void free_all(mbddc_ctx* c) {
   c->bytes = 0;
   if (c->h_est) (void)hipHostFree(c->h_est);
   if (c->h_norm) (void)hipHostFree(c->h_norm);
+  if (c->h_kstate) (void)hipHostFree(c->h_kstate);
   c->h_est = c->h_norm = nullptr;
+  c->h_kstate = nullptr;
 }
 
 template <typename T>
@@ -1699,10 +1709,14 @@ int ensure_krylov(mbddc_ctx* c, int R) {
   for (double** p : {&c->d_V, &c->d_Z, &c->d_Wv, &c->d_B, &c->d_x, &c->d_r, &c->d_part, &c->d_part2, &c->d_npart,
                      &c->d_h1, &c->d_h2, &c->d_Hs, &c->d_cs, &c->d_sn, &c->d_g, &c->d_hnorm, &c->d_y, &c->d_beta})
     dfree(c, *p);
-  dfree(c, c->d_jsys); dfree(c, c->d_nk); dfree(c, c->d_active); dfree(c, c->d_mode); dfree(c, c->d_fin);
+  dfree(c, c->d_kstate); dfree(c, c->d_nk); dfree(c, c->d_fin); dfree(c, c->d_bnorm);
+  c->d_jsys = c->d_its = nullptr;
+  c->d_active = c->d_mode = nullptr;
   if (c->h_est) (void)hipHostFree(c->h_est);
   if (c->h_norm) (void)hipHostFree(c->h_norm);
+  if (c->h_kstate) (void)hipHostFree(c->h_kstate);
   c->h_est = c->h_norm = nullptr;
+  c->h_kstate = nullptr;
   const int64_t n = c->plan.n_dofs, J = restart + 1;
   const int64_t nsys = (int64_t)c->plan.n_inst * R;
   const int64_t nch = (int64_t)c->chunk_inst.size();
@@ -1724,13 +1738,18 @@ int ensure_krylov(mbddc_ctx* c, int R) {
   CHK(dalloc(c, &c->d_hnorm, nsys));
   CHK(dalloc(c, &c->d_y, nsys * J));
   CHK(dalloc(c, &c->d_beta, nsys));
-  CHK(dalloc(c, &c->d_jsys, nsys));
+  CHK(dalloc(c, &c->d_kstate, 10 * nsys));
+  c->kstate_n = nsys;
+  c->d_jsys = reinterpret_cast<int32_t*>(c->d_kstate);
+  c->d_its = reinterpret_cast<int32_t*>(c->d_kstate + 4 * nsys);
+  c->d_active = c->d_kstate + 8 * nsys;
+  c->d_mode = c->d_kstate + 9 * nsys;
+  CHK(dalloc(c, &c->d_bnorm, nsys));
   CHK(dalloc(c, &c->d_nk, nsys));
-  CHK(dalloc(c, &c->d_active, nsys));
-  CHK(dalloc(c, &c->d_mode, nsys));
   CHK(dalloc(c, &c->d_fin, nsys));
   HIPCHK(hipHostMalloc((void**)&c->h_est, nsys * sizeof(double), hipHostMallocDefault));
   HIPCHK(hipHostMalloc((void**)&c->h_norm, nsys * sizeof(double), hipHostMallocDefault));
+  HIPCHK(hipHostMalloc((void**)&c->h_kstate, 10 * nsys, hipHostMallocDefault));
   HIPCHK(hipMemsetAsync(c->d_V, 0, J * n * R * sizeof(double), c->stream));
   HIPCHK(hipMemsetAsync(c->d_Z, 0, restart * n * R * sizeof(double), c->stream));
   c->R_kry = R;
@@ -1775,18 +1794,28 @@ int gmres_impl(mbddc_ctx* c, int nrhs, mbddc_info* info) {
   // r = b (x0 = 0): V_0 = b / ||b||, g = (||b||, 0, ...)
   HIPCHK(h2d(c->d_fin, fin.data(), nsys));
   HIPCHK(h2d(c->d_beta, bnorm.data(), nsys * sizeof(double)));
-  HIPCHK(h2d(c->d_jsys, j.data(), nsys * sizeof(int32_t)));
+  HIPCHK(h2d(c->d_bnorm, bnorm.data(), nsys * sizeof(double)));
   hipLaunchKernelGGL((k_restart<R>), dim3(gv), dim3(kBlock), 0, c->stream, ka, c->d_V, c->d_B, c->d_fin, c->d_beta,
                      c->d_dof_inst);
   hipLaunchKernelGGL(k_restart_g, dim3(gs), dim3(64), 0, c->stream, ka, nsys, c->d_fin, c->d_beta, c->d_g);
   int status = MBDDC_OK;
+  bool state_dirty = true;
+  const GmresStop stop{c->d_its, c->d_mode, c->d_bnorm, rtol, restart, max_it};
   while (true) {
     bool any = false;
     for (int s = 0; s < nsys; ++s) any |= active[s] != 0;
     if (!any) break;
-    HIPCHK(h2d(c->d_jsys, j.data(), nsys * sizeof(int32_t)));
-    HIPCHK(h2d(c->d_active, active.data(), nsys));
-    HIPCHK(h2d(c->d_mode, mode.data(), nsys));
+    // the systems' state, in one copy, when the host has changed it (the stream is idle here, so
+    // the pinned buffer is free); otherwise the Givens step has advanced it on the device already
+    if (state_dirty) {
+      const int64_t kn = c->kstate_n;   // section offsets as allocated (a narrower solve uses a prefix)
+      std::memcpy(c->h_kstate, j.data(), nsys * sizeof(int32_t));
+      std::memcpy(c->h_kstate + 4 * kn, its.data(), nsys * sizeof(int32_t));
+      std::memcpy(c->h_kstate + 8 * kn, active.data(), nsys);
+      std::memcpy(c->h_kstate + 9 * kn, mode.data(), nsys);
+      HIPCHK(h2d(c->d_kstate, c->h_kstate, 10 * kn));
+      state_dirty = false;
+    }
     int jtop = 0;
     for (int s = 0; s < nsys; ++s)
       if (active[s]) jtop = std::max(jtop, j[s]);
@@ -1838,7 +1867,7 @@ int gmres_impl(mbddc_ctx* c, int nrhs, mbddc_info* info) {
     {
       ProfScope ps(c, F_KRYLOV_SMALL, 0.0, 0.0);
       hipLaunchKernelGGL(k_givens, dim3(nsys), dim3(64), 0, c->stream, ka, nsys, c->d_h1, c->d_h2, c->d_npart,
-                         c->d_jsys, c->d_active, c->d_Hs, c->d_cs, c->d_sn, c->d_g, c->d_hnorm, c->h_est);
+                         c->d_jsys, c->d_active, c->d_Hs, c->d_cs, c->d_sn, c->d_g, c->d_hnorm, c->h_est, stop);
     }
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(c->stream));
@@ -1860,6 +1889,7 @@ int gmres_impl(mbddc_ctx* c, int nrhs, mbddc_info* info) {
       }
     }
     if (!any_fin) continue;
+    state_dirty = true;   // finished systems restart or leave: the host sends their state
     HIPCHK(h2d(c->d_fin, fin.data(), nsys));
     HIPCHK(h2d(c->d_nk, nk.data(), nsys * sizeof(int32_t)));
     hipLaunchKernelGGL(k_backsolve, dim3(gs), dim3(64), 0, c->stream, ka, nsys, c->d_fin, c->d_nk, c->d_Hs, c->d_g,
@@ -2323,8 +2353,9 @@ int mbddc_setup_symbolic_batch(mbddc_ctx* c, int n_inst, const mbddc_mesh* meshe
   c->d_V = c->d_Z = c->d_Wv = c->d_B = c->d_x = c->d_r = nullptr;
   c->d_part = c->d_part2 = c->d_npart = c->d_h1 = c->d_h2 = c->d_Hs = c->d_cs = c->d_sn = c->d_g = nullptr;
   c->d_hnorm = c->d_y = c->d_beta = nullptr;
-  c->d_jsys = c->d_nk = nullptr;
-  c->d_active = c->d_mode = c->d_fin = nullptr;
+  c->d_jsys = c->d_nk = c->d_its = nullptr;
+  c->d_active = c->d_mode = c->d_fin = c->d_kstate = nullptr;
+  c->d_bnorm = nullptr;
   c->d_Kc_keep = nullptr;
   c->d_cDinv = c->d_cY = c->d_cCcol = nullptr;
   c->d_csym_gd = nullptr;
