@@ -331,7 +331,8 @@ struct mbddc_ctx {
   int32_t* d_its = nullptr;
   double* d_bnorm = nullptr;
   uint8_t* h_kstate = nullptr;   // pinned host
-  double* h_est = nullptr;       // pinned host
+  double* h_est = nullptr;       // pinned host, two slots of kstate_n (consecutive GMRES steps)
+  hipEvent_t ev_step[2] = {nullptr, nullptr};
   double* h_norm = nullptr;      // pinned host
   Profiler prof;
   hipStream_t aux = nullptr;     // lookahead stream of the coarse sweep (default priority)
@@ -412,6 +413,10 @@ void free_all(mbddc_ctx* c) {
   c->side_pending = false;
   if (c->ev_a) (void)hipEventDestroy(c->ev_a);
   if (c->ev_b) (void)hipEventDestroy(c->ev_b);
+  for (hipEvent_t& e : c->ev_step) {
+    if (e) (void)hipEventDestroy(e);
+    e = nullptr;
+  }
   if (c->aux) (void)hipStreamDestroy(c->aux);
   c->ev_a = c->ev_b = nullptr;
   c->aux = nullptr;
@@ -1747,7 +1752,9 @@ int ensure_krylov(mbddc_ctx* c, int R) {
   CHK(dalloc(c, &c->d_bnorm, nsys));
   CHK(dalloc(c, &c->d_nk, nsys));
   CHK(dalloc(c, &c->d_fin, nsys));
-  HIPCHK(hipHostMalloc((void**)&c->h_est, nsys * sizeof(double), hipHostMallocDefault));
+  HIPCHK(hipHostMalloc((void**)&c->h_est, 2 * nsys * sizeof(double), hipHostMallocDefault));
+  for (hipEvent_t& e : c->ev_step)
+    if (!e) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   HIPCHK(hipHostMalloc((void**)&c->h_norm, nsys * sizeof(double), hipHostMallocDefault));
   HIPCHK(hipHostMalloc((void**)&c->h_kstate, 10 * nsys, hipHostMallocDefault));
   HIPCHK(hipMemsetAsync(c->d_V, 0, J * n * R * sizeof(double), c->stream));
@@ -1801,24 +1808,9 @@ int gmres_impl(mbddc_ctx* c, int nrhs, mbddc_info* info) {
   int status = MBDDC_OK;
   bool state_dirty = true;
   const GmresStop stop{c->d_its, c->d_mode, c->d_bnorm, rtol, restart, max_it};
-  while (true) {
-    bool any = false;
-    for (int s = 0; s < nsys; ++s) any |= active[s] != 0;
-    if (!any) break;
-    // the systems' state, in one copy, when the host has changed it (the stream is idle here, so
-    // the pinned buffer is free); otherwise the Givens step has advanced it on the device already
-    if (state_dirty) {
-      const int64_t kn = c->kstate_n;   // section offsets as allocated (a narrower solve uses a prefix)
-      std::memcpy(c->h_kstate, j.data(), nsys * sizeof(int32_t));
-      std::memcpy(c->h_kstate + 4 * kn, its.data(), nsys * sizeof(int32_t));
-      std::memcpy(c->h_kstate + 8 * kn, active.data(), nsys);
-      std::memcpy(c->h_kstate + 9 * kn, mode.data(), nsys);
-      HIPCHK(h2d(c->d_kstate, c->h_kstate, 10 * kn));
-      state_dirty = false;
-    }
-    int jtop = 0;
-    for (int s = 0; s < nsys; ++s)
-      if (active[s]) jtop = std::max(jtop, j[s]);
+  // One Arnoldi step of every system running on the device (CGS2, then the Givens step, which
+  // writes the residual estimates into est_slot and advances or pauses each system).
+  auto enqueue_step = [&](int jtop, double* est_slot) -> int {
     const double vbytes = 8.0 * n * R;                 // one block vector
     {
       ProfScope ps(c, F_KRYLOV_VEC, 2.0 * vbytes, 0.0);
@@ -1867,28 +1859,100 @@ int gmres_impl(mbddc_ctx* c, int nrhs, mbddc_info* info) {
     {
       ProfScope ps(c, F_KRYLOV_SMALL, 0.0, 0.0);
       hipLaunchKernelGGL(k_givens, dim3(nsys), dim3(64), 0, c->stream, ka, nsys, c->d_h1, c->d_h2, c->d_npart,
-                         c->d_jsys, c->d_active, c->d_Hs, c->d_cs, c->d_sn, c->d_g, c->d_hnorm, c->h_est, stop);
+                         c->d_jsys, c->d_active, c->d_Hs, c->d_cs, c->d_sn, c->d_g, c->d_hnorm, est_slot, stop);
     }
     HIPCHK(hipGetLastError());
-    HIPCHK(hipStreamSynchronize(c->stream));
+    return MBDDC_OK;
+  };
+  // The host's copy of the stop decision of every system that ran the step whose estimates are in
+  // est_slot (the Givens step took the same decision on the device); systems that stop are marked
+  // in fin (and paused on the device until the host has finished their cycle). fin is cleared
+  // first unless it already holds the stops of the step before (both end their cycles together).
+  std::vector<uint8_t> running(nsys, 0);
+  std::vector<double> est_prev(nsys, 0.0);
+  auto take_step = [&](const double* est_slot, bool clear_fin) {
+    if (clear_fin) std::fill(fin.begin(), fin.end(), 0);
     bool any_fin = false;
     for (int s = 0; s < nsys; ++s) {
-      fin[s] = 0;
-      if (!active[s]) continue;
+      if (!running[s]) continue;
       its[s]++;
-      est[s] = c->h_est[s];
+      est_prev[s] = est[s];
+      est[s] = est_slot[s];
       bool conv = est[s] <= rtol * bnorm[s];
       bool brk = !(est[s] == est[s]);
       if (conv || j[s] + 1 >= restart || its[s] >= max_it || brk) {
         fin[s] = 1;
         nk[s] = j[s] + 1;
+        running[s] = 0;
         any_fin = true;
       } else {
         j[s]++;
         mode[s] = 1;
       }
     }
+    return any_fin;
+  };
+  // Whether some running system will likely go on after its current step: not at the end of its
+  // cycle or of its iteration budget, and not about to converge at its present rate.
+  auto worth_next = [&](int& jnext) {
+    bool any = false;
+    jnext = 0;
+    for (int s = 0; s < nsys; ++s) {
+      if (!running[s] || j[s] + 1 >= restart || its[s] + 1 >= max_it) continue;
+      jnext = std::max(jnext, j[s] + 1);
+      const double e1 = est[s], e0 = est_prev[s];
+      const bool soon = j[s] > 0 && e0 > 0.0 && e1 * (e1 / e0) <= 4.0 * rtol * bnorm[s];
+      any |= !soon;
+    }
+    return any;
+  };
+  double* est_buf[2] = {c->h_est, c->h_est + c->kstate_n};
+  int slot = 0;
+  bool inflight = false;   // a step has been enqueued whose estimates the host has not taken yet
+  while (true) {
+    if (!inflight) {
+      bool any = false;
+      for (int s = 0; s < nsys; ++s) any |= active[s] != 0;
+      if (!any) break;
+      // the systems' state, in one copy, when the host has changed it (no step is in flight, so the
+      // pinned buffer is free); otherwise the Givens step has advanced it on the device already
+      if (state_dirty) {
+        const int64_t kn = c->kstate_n;   // section offsets as allocated (a narrower solve uses a prefix)
+        std::memcpy(c->h_kstate, j.data(), nsys * sizeof(int32_t));
+        std::memcpy(c->h_kstate + 4 * kn, its.data(), nsys * sizeof(int32_t));
+        std::memcpy(c->h_kstate + 8 * kn, active.data(), nsys);
+        std::memcpy(c->h_kstate + 9 * kn, mode.data(), nsys);
+        HIPCHK(h2d(c->d_kstate, c->h_kstate, 10 * kn));
+        state_dirty = false;
+      }
+      int jtop = 0;
+      for (int s = 0; s < nsys; ++s) {
+        running[s] = active[s];
+        if (active[s]) jtop = std::max(jtop, j[s]);
+      }
+      CHK(enqueue_step(jtop, est_buf[slot]));
+      HIPCHK(hipEventRecord(c->ev_step[slot], c->stream));
+      inflight = true;
+    }
+    // Enqueue the next step before the host waits for this one (the device advances the systems
+    // that go on and pauses those that stop), so the host's wait and launches overlap the device.
+    int jnext = 0;
+    const bool ahead = worth_next(jnext);
+    if (ahead) {
+      CHK(enqueue_step(jnext, est_buf[slot ^ 1]));
+      HIPCHK(hipEventRecord(c->ev_step[slot ^ 1], c->stream));
+    }
+    HIPCHK(hipEventSynchronize(c->ev_step[slot]));
+    bool any_fin = take_step(est_buf[slot], true);
+    slot ^= 1;
+    inflight = ahead;
     if (!any_fin) continue;
+    if (ahead) {   // finish the step already enqueued: its stops join this cycle's end
+      HIPCHK(hipEventSynchronize(c->ev_step[slot]));
+      take_step(est_buf[slot], false);
+      slot ^= 1;
+      inflight = false;
+    }
     state_dirty = true;   // finished systems restart or leave: the host sends their state
     HIPCHK(h2d(c->d_fin, fin.data(), nsys));
     HIPCHK(h2d(c->d_nk, nk.data(), nsys * sizeof(int32_t)));
