@@ -250,6 +250,7 @@ struct mbddc_ctx {
   int64_t big_pbuf = 0, big_count = 0;               // batched blocked sweep: panel elements, matrices
   bool sym = false;                                  // symmetric (SPD) factor path
   std::vector<ApplyItem> itA, itC, itE, itF, itH;
+  int coarse_rl = 4;                // rows per lane of the coarse product (64 RL rows per workgroup)
   std::vector<int64_t> inst_coarse_off, inst_kc_off;
   std::vector<int32_t> inst_nc, inst_kc_ld, inst_nchunk, coarse_inst, cslot_sub;
   std::vector<int32_t> chunk_inst, inst_chunk_off;
@@ -667,10 +668,28 @@ int build_layout(mbddc_ctx* c) {
         c->gj_coarse_small.push_back({c->inst_kc_off[ii], in.n_coarse, ld, in.coarse_off, ii, 0});
       else
         c->coarse_large.push_back(ii);
-      for (int32_t r0 = 0; r0 < in.n_coarse; r0 += 256)
-        for (int32_t c0 = 0; c0 < in.n_coarse; c0 += kCoarseChunk)
-          c->itE.push_back({ii, r0, c0, std::min(kCoarseChunk, in.n_coarse - c0)});
     }
+  }
+  // coarse product items: 64 RL rows of one column chunk each, with the longest row blocks that
+  // still give every CU two workgroups (small coarse problems take short blocks)
+  c->coarse_rl = 1;
+  for (int rl : {4, 2}) {
+    int64_t items = 0;
+    for (int32_t ii = 0; ii < P.n_inst; ++ii) {
+      const int32_t nc = P.inst[ii].n_coarse;
+      if (nc > 0 && c->opt.levels != 3) items += (int64_t)nblk(nc, 64 * rl) * nblk(nc, kCoarseChunk);
+    }
+    if (items >= 512) {
+      c->coarse_rl = rl;
+      break;
+    }
+  }
+  for (int32_t ii = 0; ii < P.n_inst; ++ii) {
+    const int32_t nc = P.inst[ii].n_coarse;
+    if (nc <= 0 || c->opt.levels == 3) continue;
+    for (int32_t r0 = 0; r0 < nc; r0 += 64 * c->coarse_rl)
+      for (int32_t c0 = 0; c0 < nc; c0 += kCoarseChunk)
+        c->itE.push_back({ii, r0, c0, std::min(kCoarseChunk, nc - c0)});
   }
   c->kc_elems = kc;
   c->coarse_inst.assign(P.n_coarse, 0);
@@ -1477,9 +1496,14 @@ int apply_attrs();
 // Phase PH of the local apply (row-block list k of A, C, F, H) with that list's rows per
 // workgroup: 256 (four rows per lane) or 128 (two).
 template <typename To, int R, int PH>
-void launch_local(mbddc_ctx* c, const ApplyArgs& a, int k, size_t n_items) {
+void launch_local(mbddc_ctx* c, ApplyArgs a, int k, size_t n_items) {
   const int rw = c->apply_rows_eff[k];
-  const size_t lds = (size_t)(4 * rw * R + (size_t)a.xchunk * R) * sizeof(double);
+  auto lds_of = [&](int x) { return (size_t)(4 * rw * R + (size_t)x * R) * sizeof(double); };
+  // every input column in one LDS chunk when that keeps as many workgroups per CU as the tuned
+  // chunk (fewer gather rounds and barriers; the narrow row blocks leave the LDS room)
+  constexpr size_t kCuLds = 160 * 1024;
+  if (c->max_cols > a.xchunk && kCuLds / lds_of(c->max_cols) >= kCuLds / lds_of(a.xchunk)) a.xchunk = c->max_cols;
+  const size_t lds = lds_of(a.xchunk);
   const bool big = c->tune.apply_big > 0 || (c->tune.apply_big < 0 && c->max_cols >= kApplyBigCols);
   const dim3 g((unsigned)n_items), b(kBlock);
   if (rw == 128 && big) hipLaunchKernelGGL((k_apply_local<To, R, PH, 2, true>), g, b, lds, c->stream, a);
@@ -1528,11 +1552,15 @@ int apply_impl(mbddc_ctx* c, const double* r, double* z, mbddc_ctx* parent = nul
     ProfScope ps(c, F_LEVEL2_APPLY, b2, f2);
     CHK((apply_impl<double, R>(ch, ch->d_X, ch->d_Y, c)));
   } else if (!c->itE.empty()) {
-    const size_t lds_c = (size_t)(4 * 256 * R + kCoarseChunk * R) * sizeof(double);
+    const int rl = c->coarse_rl;
+    const size_t lds_c = (size_t)(4 * 64 * rl * R + kCoarseChunk * R) * sizeof(double);
     ProfScope ps(c, F_APPLY_E, c->op_bytes[F_APPLY_E] + 8.0 * R * c->vec_words[F_APPLY_E],
                  2.0 * R * c->fam_flops[F_APPLY_E]);
     a.items = c->d_itE;
-    hipLaunchKernelGGL((k_apply_coarse<To, R>), dim3((unsigned)c->itE.size()), dim3(kBlock), lds_c, c->stream, a);
+    const dim3 g((unsigned)c->itE.size()), b(kBlock);
+    if (rl == 4) hipLaunchKernelGGL((k_apply_coarse<To, R, 4>), g, b, lds_c, c->stream, a);
+    else if (rl == 2) hipLaunchKernelGGL((k_apply_coarse<To, R, 2>), g, b, lds_c, c->stream, a);
+    else hipLaunchKernelGGL((k_apply_coarse<To, R, 1>), g, b, lds_c, c->stream, a);
   }
   {
     ProfScope ps(c, F_APPLY_F, c->op_bytes[F_APPLY_F] + 8.0 * R * c->vec_words[F_APPLY_F], 2.0 * R * c->fam_flops[F_APPLY_F]);
@@ -1573,7 +1601,9 @@ int apply_attrs() {
   static int st = MBDDC_OK;
   std::call_once(once, [] {
     const size_t mx = 160 * 1024;
-    int e = set_lds(k_apply_coarse<To, R>, mx);
+    int e = set_lds(k_apply_coarse<To, R, 4>, mx);
+    if (!e) e = set_lds(k_apply_coarse<To, R, 2>, mx);
+    if (!e) e = set_lds(k_apply_coarse<To, R, 1>, mx);
     if (!e) e = set_lds(k_apply_local<To, R, 0, 4, false>, mx);
     if (!e) e = set_lds(k_apply_local<To, R, 1, 4, false>, mx);
     if (!e) e = set_lds(k_apply_local<To, R, 3, 4, false>, mx);
