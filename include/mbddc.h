@@ -245,7 +245,7 @@ int mbddc_get_profile(mbddc_ctx* ctx, mbddc_kernel_stat* out, int max_entries, i
  * workgroup sweep with 16-index panels in LDS, 2 the same with 32-index panels, 3 batched
  * blocked sweep (FP64); then the number of input columns the apply stages in LDS (128, 256,
  * 512 or 1024), the column grouping of the local apply and the rows per workgroup of each
- * local apply phase A, C, F, H (256: four rows per lane, 128: two) by timing applies of four
+ * local apply phase A, C, F, H (256: four rows per lane, 128: two, 64: one) by timing applies of four
  * right-hand sides; FP64 factorisations
  * also time their batched GEMMs on the vector units (0) and the matrix cores (1). Needs a tangent (state
  * >= set_tangent) and leaves the handle factorised with the chosen table. table_out (may be

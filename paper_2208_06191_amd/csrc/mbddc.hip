@@ -120,7 +120,7 @@ inline int sym_bucket(int n) {
 struct Tuning {
   int32_t sym[2][kSymBuckets];      // [0] FP64, [1] FP32
   int32_t xchunk;
-  int32_t apply_rows[4];            // rows per workgroup of apply phases A, C, F, H (128, 256; 0 = by size)
+  int32_t apply_rows[4];            // rows per workgroup of apply phases A, C, F, H (64, 128, 256; 0 = by size)
   int32_t apply_rows2[4];           // the same for the level-2 instance of three-level handles
   int32_t gemm_mfma;                // FP64 batched GEMMs on the matrix cores (1) or the vector units (0)
   int32_t apply_big;                // apply column groups: 1 large first, 0 small only, -1 by size
@@ -488,8 +488,8 @@ Tuning child_tuning(const Tuning& t) {
   return u;
 }
 
-// Row blocks of the local apply phases: at most 128 or 256 rows per workgroup per phase, from the
-// tuning table, or (0) the size that pads the phase's row counts least (256 on ties).
+// Row blocks of the local apply phases: at most 64, 128 or 256 rows per workgroup per phase, from
+// the tuning table, or (0) the one of 128 and 256 that pads the phase's row counts least (256 on ties).
 void build_apply_items(mbddc_ctx* c) {
   c->itA.clear(); c->itC.clear(); c->itF.clear(); c->itH.clear();
   std::vector<ApplyItem>* lists[4] = {&c->itA, &c->itC, &c->itF, &c->itH};
@@ -498,7 +498,7 @@ void build_apply_items(mbddc_ctx* c) {
   };
   for (int k = 0; k < 4; ++k) {
     int rw = c->tune.apply_rows[k];
-    if (rw != 128 && rw != 256) {
+    if (rw != 64 && rw != 128 && rw != 256) {
       int64_t pad[2] = {0, 0};
       for (const SubDev& d : c->subs)
         for (int q = 0; q < 2; ++q) {
@@ -1494,7 +1494,7 @@ template <typename To, int R>
 int apply_attrs();
 
 // Phase PH of the local apply (row-block list k of A, C, F, H) with that list's rows per
-// workgroup: 256 (four rows per lane) or 128 (two).
+// workgroup: 256 (four rows per lane), 128 (two) or 64 (one).
 template <typename To, int R, int PH>
 void launch_local(mbddc_ctx* c, ApplyArgs a, int k, size_t n_items) {
   const int rw = c->apply_rows_eff[k];
@@ -1506,7 +1506,8 @@ void launch_local(mbddc_ctx* c, ApplyArgs a, int k, size_t n_items) {
   const size_t lds = lds_of(a.xchunk);
   const bool big = c->tune.apply_big > 0 || (c->tune.apply_big < 0 && c->max_cols >= kApplyBigCols);
   const dim3 g((unsigned)n_items), b(kBlock);
-  if (rw == 128 && big) hipLaunchKernelGGL((k_apply_local<To, R, PH, 2, true>), g, b, lds, c->stream, a);
+  if (rw == 64) hipLaunchKernelGGL((k_apply_local<To, R, PH, 1, false>), g, b, lds, c->stream, a);
+  else if (rw == 128 && big) hipLaunchKernelGGL((k_apply_local<To, R, PH, 2, true>), g, b, lds, c->stream, a);
   else if (rw == 128) hipLaunchKernelGGL((k_apply_local<To, R, PH, 2, false>), g, b, lds, c->stream, a);
   else if (big) hipLaunchKernelGGL((k_apply_local<To, R, PH, 4, true>), g, b, lds, c->stream, a);
   else hipLaunchKernelGGL((k_apply_local<To, R, PH, 4, false>), g, b, lds, c->stream, a);
@@ -1620,6 +1621,10 @@ int apply_attrs() {
     if (!e) e = set_lds(k_apply_local<To, R, 1, 2, true>, mx);
     if (!e) e = set_lds(k_apply_local<To, R, 3, 2, true>, mx);
     if (!e) e = set_lds(k_apply_local<To, R, 4, 2, true>, mx);
+    if (!e) e = set_lds(k_apply_local<To, R, 0, 1, false>, mx);
+    if (!e) e = set_lds(k_apply_local<To, R, 1, 1, false>, mx);
+    if (!e) e = set_lds(k_apply_local<To, R, 3, 1, false>, mx);
+    if (!e) e = set_lds(k_apply_local<To, R, 4, 1, false>, mx);
     st = e;
   });
   return st;
@@ -2187,12 +2192,14 @@ int read_tuning(const char* path, Tuning& t) {
   if (text.find("\"apply_rows\"") != std::string::npos) {
     if (!ints_after("\"apply_rows\"", r.apply_rows, 4)) return MBDDC_ERR_ARG;
     for (int k = 0; k < 4; ++k)
-      if (r.apply_rows[k] != 0 && r.apply_rows[k] != 128 && r.apply_rows[k] != 256) return MBDDC_ERR_ARG;
+      if (r.apply_rows[k] != 0 && r.apply_rows[k] != 64 && r.apply_rows[k] != 128 && r.apply_rows[k] != 256)
+        return MBDDC_ERR_ARG;
   }
   if (text.find("\"apply_rows2\"") != std::string::npos) {
     if (!ints_after("\"apply_rows2\"", r.apply_rows2, 4)) return MBDDC_ERR_ARG;
     for (int k = 0; k < 4; ++k)
-      if (r.apply_rows2[k] != 0 && r.apply_rows2[k] != 128 && r.apply_rows2[k] != 256) return MBDDC_ERR_ARG;
+      if (r.apply_rows2[k] != 0 && r.apply_rows2[k] != 64 && r.apply_rows2[k] != 128 && r.apply_rows2[k] != 256)
+        return MBDDC_ERR_ARG;
   }
   for (int p = 0; p < 2; ++p)
     for (int b = 0; b < kSymBuckets; ++b)
@@ -2379,7 +2386,7 @@ int autotune_impl(mbddc_ctx* c) {
   for (int k = 0; k < 4; ++k) {
     int best_r = c->apply_rows_eff[k];
     best_t = 1e300;
-    for (int rw : {256, 128}) {
+    for (int rw : {256, 128, 64}) {
       c->tune.apply_rows[k] = rw;
       CHK(rebuild_symsets(c));
       CHK(apply_dispatch(c, 4, c->d_X, c->d_Y));
@@ -2396,7 +2403,7 @@ int autotune_impl(mbddc_ctx* c) {
   for (int k = 0; k < 4 && c->child; ++k) {
     int best_r = c->child->apply_rows_eff[k];
     best_t = 1e300;
-    for (int rw : {256, 128}) {
+    for (int rw : {256, 128, 64}) {
       c->tune.apply_rows2[k] = rw;
       CHK(rebuild_symsets(c));
       CHK(apply_dispatch(c, 4, c->d_X, c->d_Y));

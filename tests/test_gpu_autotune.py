@@ -44,7 +44,7 @@ def test_autotuned_handle_matches_default(name, primal, precision, tmp_path):
     assert on_disk["sym_fp64"] == table["sym_fp64"] and on_disk["apply_xchunk"] == table["apply_xchunk"]
     assert all(0 <= v <= 3 for v in table["sym_fp64"] + table["sym_fp32"])
     assert table["apply_xchunk"] in (128, 256, 512, 1024)
-    assert all(r in (128, 256) for r in table["apply_rows"]) and on_disk["apply_rows"] == table["apply_rows"]
+    assert all(r in (64, 128, 256) for r in table["apply_rows"]) and on_disk["apply_rows"] == table["apply_rows"]
     assert table["gemm_mfma"] in (0, 1) and on_disk["gemm_mfma"] == table["gemm_mfma"]
     xt, it = t.mbddc_solve(P.rhs)
     xd, idd = d.mbddc_solve(P.rhs)

@@ -121,7 +121,7 @@ def test_tuning_table_is_read_and_checked(tmp_path):
            "chunk.json": '{"mbddc_tune": 1, "sym_fp64": [0, 1, 3, 3], "sym_fp32": [2, 2, 1, 1], "apply_xchunk": 100}',
            "short.json": '{"mbddc_tune": 1, "sym_fp64": [0, 1], "apply_xchunk": 512}',
            "rows.json": '{"mbddc_tune": 1, "sym_fp64": [0, 1, 3, 3], "sym_fp32": [2, 2, 1, 1], "apply_xchunk": 512, '
-                        '"apply_rows": [128, 256, 64, 0]}',
+                        '"apply_rows": [128, 256, 96, 0]}',
            "gemm.json": '{"mbddc_tune": 1, "sym_fp64": [0, 1, 3, 3], "sym_fp32": [2, 2, 1, 1], "apply_xchunk": 512, '
                         '"gemm_mfma": 2}'}
     for name, text in bad.items():
