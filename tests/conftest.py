@@ -29,6 +29,8 @@ def problem(name: str):
         return W.neo_hookean_box(8, 4, 1, nrhs=2, amplitude=0.02, primal=3, name="tiny_nh")
     if name == "tiny_q2":          # Q2 on 4^3 elements, 2x2x2 subdomains of 2^3
         return W.linear_box(4, 2, 2, nrhs=1, primal=3, name="tiny_q2")
+    if name == "q2_dense":         # Q2 on 8^3 elements: node rows of 50+ 3x3 blocks on average
+        return W.linear_box(8, 2, 2, nrhs=1, primal=3, name="q2_dense")
     if name == "l3_nh":            # neo-Hookean on 12^3, 4x4x4 subdomains of 3^3: three-level cases
         return W.neo_hookean_box(12, 3, 1, nrhs=2, amplitude=0.02, primal=3, name="l3_nh")
     if name == "l3_ragged":        # 7x6x9 Q1 box, blocks of 2 -> 4x3x5 uneven subdomains, linear elastic
