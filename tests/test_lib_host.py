@@ -116,6 +116,11 @@ def test_tuning_table_is_read_and_checked(tmp_path):
     base = mbddc.mbddc_estimate_footprint([m], mbddc.default_options(symmetric_hint=1))
     assert mbddc.mbddc_estimate_footprint([m], mbddc.default_options(symmetric_hint=1, tune_table=str(good))) > 0
     assert base > 0
+    rows = tmp_path / "rows_ok.json"   # every row block size the apply has (64, 128, 256; 0 = by size)
+    rows.write_text('{"mbddc_tune": 1, "sym_fp64": [0, 1, 3, 3], "sym_fp32": [2, 2, 1, 1], "apply_xchunk": 256, '
+                    '"apply_rows": [64, 128, 256, 0], "apply_rows2": [256, 64, 0, 128], "apply_groups": 0, '
+                    '"gemm_mfma": 1}\n')
+    assert mbddc.mbddc_estimate_footprint([m], mbddc.default_options(symmetric_hint=1, tune_table=str(rows))) > 0
     bad = {"garbage.json": "not a table",
            "range.json": '{"mbddc_tune": 1, "sym_fp64": [0, 1, 7, 3], "sym_fp32": [2, 2, 1, 1], "apply_xchunk": 512}',
            "chunk.json": '{"mbddc_tune": 1, "sym_fp64": [0, 1, 3, 3], "sym_fp32": [2, 2, 1, 1], "apply_xchunk": 100}',
