@@ -54,8 +54,11 @@ enum { MBDDC_PRIMAL_V = 1, MBDDC_PRIMAL_E = 2, MBDDC_PRIMAL_F = 4 }; /* §6.2 pr
 /* Precision policy. Global vectors, the assembled operator, the coarse problem
  * and GMRES are FP64 in every mode. MBDDC_FP64: local factorisations and the
  * per-iteration local operators in FP64. MBDDC_MIXED: local factorisations in
- * FP64, local operators stored and applied in FP32 with FP32 accumulation.
- * MBDDC_MIXED_F32FACT: local factorisations also in FP32. */
+ * FP64; the local operators are stored in FP32 (half the bytes each apply reads)
+ * and every product with them accumulates in FP64. MBDDC_MIXED_F32FACT: local
+ * factorisations in FP32 too (local blocks up to 1197 rows); this mode costs
+ * GMRES iterations (the FP32 local inverses are less accurate) and is outside
+ * the oracle + 2 iteration contract of MBDDC_MIXED. */
 enum { MBDDC_FP64 = 0, MBDDC_MIXED = 1, MBDDC_MIXED_F32FACT = 2 };
 
 typedef struct mbddc_ctx mbddc_ctx;
@@ -83,7 +86,7 @@ typedef struct {
                                     §3.2 last paragraph), whose level-3 coarse problem is exact */
   int32_t coarse_group;          /* levels = 3: fine subdomain i of an instance belongs to level-2
                                     subdomain i / coarse_group (§7 uses groups of 8) */
-  int32_t precision;             /* MBDDC_FP64 or MBDDC_MIXED */
+  int32_t precision;             /* MBDDC_FP64, MBDDC_MIXED or MBDDC_MIXED_F32FACT */
   int32_t restart;               /* GMRES restart length, 1..64 */
   double rtol;                   /* relative residual target on ||b - K x||_2 */
   int32_t max_it;                /* Arnoldi steps summed over restarts */
@@ -141,6 +144,25 @@ typedef struct {
  * hipStream_t, may be NULL for the null stream). */
 int mbddc_create(mbddc_ctx** out, int hip_device, void* hip_stream);
 
+/* Device memory provider of the handle (e.g. PyTorch's caching allocator, or a
+ * serving pool): every device buffer the handle (and its level-2 instance) holds
+ * is obtained by alloc(bytes, user) and returned by free_(ptr, user); blocks
+ * must be device memory of the handle's device, aligned to 256 bytes (a
+ * misaligned block is handed back and the allocating call fails with
+ * MBDDC_ERR_ARG), and stay valid until returned. alloc returning NULL makes the
+ * allocating call fail with MBDDC_ERR_OOM (nothing partial is kept). Blocks are
+ * returned by mbddc_release, a new setup, buffer resizes and mbddc_destroy, each
+ * after the handle's stream has finished using them. Both NULL: hipMalloc /
+ * hipFree (the default). Only before the first setup (or after mbddc_release):
+ * MBDDC_ERR_STATE otherwise; MBDDC_ERR_ARG if exactly one of the two is NULL. */
+int mbddc_set_allocator(mbddc_ctx* ctx, void* (*alloc)(size_t bytes, void* user),
+                        void (*free_)(void* ptr, void* user), void* user);
+
+/* Returns every device buffer of the handle (through the allocator) and puts it
+ * back in the created state; its streams, events and pinned host buffers are
+ * kept for the next setup. */
+int mbddc_release(mbddc_ctx* ctx);
+
 /* Fills `opt` with the defaults: primal V|E, 2 levels, group 8, MIXED, restart
  * 30, rtol 1e-8, max_it 1000, level-2 primal V|E|F. */
 int mbddc_default_options(mbddc_options* opt);
@@ -156,14 +178,15 @@ int mbddc_setup_symbolic(mbddc_ctx* ctx, const mbddc_mesh* mesh, const mbddc_opt
 int mbddc_setup_symbolic_batch(mbddc_ctx* ctx, int n_inst, const mbddc_mesh* meshes,
                                const mbddc_options* opt);
 
-/* Device bytes the handle will hold after factor (exact; call after setup). */
-int mbddc_footprint(const mbddc_ctx* ctx, size_t* device_bytes);
+/* Device bytes the handle will hold after factor and a solve of `nrhs` (1..8)
+ * right-hand sides (call after setup). */
+int mbddc_footprint(const mbddc_ctx* ctx, int nrhs, size_t* device_bytes);
 
-/* Host-only estimate of the device bytes a handle set up with these meshes and
- * options holds after factor and a solve of up to 4 right-hand sides (the
- * admission test of the serving loop; no device is touched). Same argument
- * rules and errors as mbddc_setup_symbolic_batch. */
-int mbddc_estimate_footprint(int n_inst, const mbddc_mesh* meshes, const mbddc_options* opt,
+/* Host-only estimate (an upper bound) of the device bytes a handle set up with
+ * these meshes and options holds after factor and a solve of `nrhs` (1..8)
+ * right-hand sides (the admission test of the serving loop; no device is
+ * touched). Same argument rules and errors as mbddc_setup_symbolic_batch. */
+int mbddc_estimate_footprint(int n_inst, const mbddc_mesh* meshes, const mbddc_options* opt, int nrhs,
                              size_t* device_bytes);
 
 int mbddc_get_sizes(const mbddc_ctx* ctx, mbddc_sizes* out);
@@ -171,7 +194,9 @@ int mbddc_get_sizes(const mbddc_ctx* ctx, mbddc_sizes* out);
 /* Element tangents K_e, [n_elems][3npe][3npe] row-major FP64 in element-local
  * DOF order 3a + comp (all instances concatenated). Assembles the operator
  * (§3.2, A = sum_i A^(i)) on the device; keeps factors of a previous factor
- * call (lagged preconditioner). */
+ * call (lagged preconditioner). A NaN or infinite entry (found on the device,
+ * before the operator is touched) returns MBDDC_ERR_ARG and leaves the handle's
+ * operator and factors as they were. */
 int mbddc_set_tangent(mbddc_ctx* ctx, const double* elem_K, int on_device);
 
 /* Numeric BDDC setup (§3.2): local interior and constrained-Neumann problems,
@@ -268,6 +293,11 @@ int mbddc_get_tuning(const mbddc_ctx* ctx, int32_t* sym_fp64, int32_t* sym_fp32,
 /* Subdomain of the last MBDDC_ERR_SINGULAR (-1: coarse problem; see mbddc_factor). */
 int mbddc_last_bad_subdomain(const mbddc_ctx* ctx);
 
+/* GMRES iterations of every system of the last mbddc_solve: its[inst * nrhs + k] for
+ * instance inst and right-hand side k (n_entries = n_instances * nrhs; at most
+ * max_entries are written). Zero before the first solve. */
+int mbddc_get_iterations(const mbddc_ctx* ctx, int32_t* its, int64_t max_entries, int64_t* n_entries);
+
 int mbddc_destroy(mbddc_ctx* ctx);
 
 /* ---- Serving: a request loop over independent tangent solves -------------
@@ -319,6 +349,18 @@ int mbddc_server_wait(mbddc_server* srv, int64_t ticket, mbddc_request_result* r
 
 /* Current queue length, active requests and admitted bytes (any pointer may be NULL). */
 int mbddc_server_state(mbddc_server* srv, int32_t* queued, int32_t* active, size_t* admitted_bytes);
+
+/* Device memory of the server. Each worker keeps one handle across requests, and
+ * every handle draws its buffers from one pool owned by the server (through
+ * mbddc_set_allocator): a block a request gives back is handed to a later
+ * request of a size it fits (at most twice the request), so once the pool holds
+ * blocks of the sizes in use, requests make no hipMalloc or hipFree. Cached free
+ * blocks are released (hipFree) only when a hipMalloc fails or the pool's free
+ * cache would exceed the HBM budget. Counters since mbddc_server_create: device
+ * allocations and frees made by the pool, bytes in use by handles, bytes cached
+ * free (any pointer may be NULL). */
+int mbddc_server_pool_stats(mbddc_server* srv, int64_t* device_mallocs, int64_t* device_frees,
+                            size_t* bytes_in_use, size_t* bytes_cached);
 
 /* Finishes every queued and active request, then frees the server. */
 int mbddc_server_destroy(mbddc_server* srv);

@@ -65,14 +65,14 @@ enum Family {
   F_ASSEMBLE_BSR, F_ASSEMBLE_LOCAL, F_GJ_KII, F_GEMM_GH, F_GEMM_S, F_CONSTRAINTS, F_GJ_P, F_EXTRACT,
   F_COARSE_ASSEMBLE, F_COARSE_GJ_SMALL, F_COARSE_DIAG, F_COARSE_PREP, F_COARSE_GEMM, F_COARSE_ROWS,
   F_APPLY_A, F_APPLY_C, F_APPLY_E, F_APPLY_F, F_APPLY_H, F_SPMV, F_KRYLOV_DOTS, F_KRYLOV_UPDATE,
-  F_KRYLOV_SMALL, F_KRYLOV_VEC, F_LEVEL2_SETUP, F_LEVEL2_APPLY, F_COUNT
+  F_KRYLOV_SMALL, F_KRYLOV_VEC, F_LEVEL2_SETUP, F_LEVEL2_APPLY, F_APPLY_WHOLE, F_COUNT
 };
 const char* const kFamilyName[F_COUNT] = {
   "assemble_bsr", "assemble_local", "gj_interior", "gemm_condense", "gemm_schur", "constraints", "gj_interface",
   "extract_operators", "coarse_assemble", "coarse_gj_small", "coarse_gj_diag", "coarse_gj_prep", "coarse_gj_gemm",
   "coarse_gj_rows", "apply_A_interior", "apply_C_interface", "apply_E_coarse", "apply_F_coarse_ext",
   "apply_H_average", "spmv_bsr", "krylov_dots", "krylov_update", "krylov_small", "krylov_vectors",
-  "level2_setup", "apply_E_level2"};
+  "level2_setup", "apply_E_level2", "apply_whole"};
 
 struct Profiler {
   uint32_t mask = 0;
@@ -233,6 +233,14 @@ struct mbddc_ctx {
   int last_bad = 0;
   size_t bytes = 0;              // device bytes currently held
   std::vector<DevMem> allocs;
+  // device memory provider (mbddc_set_allocator); NULL: hipMalloc / hipFree
+  void* (*alloc_fn)(size_t, void*) = nullptr;
+  void (*free_fn)(void*, void*) = nullptr;
+  void* alloc_user = nullptr;
+  int32_t* d_flag = nullptr;     // one-word result of the input checks
+  int32_t* h_flag = nullptr;     // pinned host copy of it
+  std::vector<int32_t> last_its; // iterations of each (instance, rhs) system of the last solve
+  int32_t last_nrhs = 0;
 
   // sizes
   int64_t nblocks = 0, w_elems = 0, op_elems = 0, kcl_elems = 0, piv_elems = 0, kc_elems = 0;
@@ -335,6 +343,7 @@ struct mbddc_ctx {
   double* h_est = nullptr;       // pinned host, two slots of kstate_n (consecutive GMRES steps)
   hipEvent_t ev_step[2] = {nullptr, nullptr};
   double* h_norm = nullptr;      // pinned host
+  int64_t h_cap = 0;             // systems the pinned host buffers hold
   Profiler prof;
   hipStream_t aux = nullptr;     // lookahead stream of the coarse sweep (default priority)
   hipStream_t side = nullptr;    // operator extraction overlapped with the coarse factorisation (default priority)
@@ -355,15 +364,37 @@ struct mbddc_ctx {
 
 namespace {
 
+// A block goes back to a custom allocator only after every stream of the handle is done with
+// it (the allocator may hand it to work on another stream at once; hipFree waits by itself).
+void release_block(mbddc_ctx* c, void* p) {
+  if (c->free_fn) {
+    for (hipStream_t s : {c->stream, c->side, c->aux})
+      if (s) (void)hipStreamSynchronize(s);
+    if (!c->stream) (void)hipDeviceSynchronize();
+    c->free_fn(p, c->alloc_user);
+  } else {
+    (void)hipFree(p);
+  }
+}
+
 template <typename T>
 int dalloc(mbddc_ctx* c, T** p, int64_t n) {
   size_t b = std::max<int64_t>(n, 1) * sizeof(T);
   b = round_up(b, 256);
   void* q = nullptr;
-  hipError_t e = hipMalloc(&q, b);
-  if (e != hipSuccess) {
-    (void)hipGetLastError();
-    return MBDDC_ERR_OOM;
+  if (c->alloc_fn) {
+    q = c->alloc_fn(b, c->alloc_user);
+    if (!q) return MBDDC_ERR_OOM;
+    if ((reinterpret_cast<uintptr_t>(q) & 255) != 0) {   // the kernels assume 256-byte aligned blocks
+      c->free_fn(q, c->alloc_user);
+      return MBDDC_ERR_ARG;
+    }
+  } else {
+    hipError_t e = hipMalloc(&q, b);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return MBDDC_ERR_OOM;
+    }
   }
   c->allocs.push_back({q, b});
   c->bytes += b;
@@ -374,15 +405,157 @@ int dalloc(mbddc_ctx* c, T** p, int64_t n) {
 template <typename T>
 void dfree(mbddc_ctx* c, T*& p) {
   if (!p) return;
+  // only blocks this handle holds are released: a pointer left over from buffers already
+  // released (a new setup, mbddc_release) is merely cleared
   for (size_t i = 0; i < c->allocs.size(); ++i) {
     if (c->allocs[i].p == (void*)p) {
       c->bytes -= c->allocs[i].bytes;
       c->allocs.erase(c->allocs.begin() + i);
+      release_block(c, (void*)p);
       break;
     }
   }
-  (void)hipFree((void*)p);
   p = nullptr;
+}
+
+// Device buffers (and the level-2 child); the handle's streams, events and pinned host buffers
+// stay, so that a handle set up again reuses them.
+void free_all(mbddc_ctx* c);
+void clear_pointers(mbddc_ctx* c);
+
+void release_buffers(mbddc_ctx* c) {
+  if (c->child) {   // rebuilt by every setup: torn down whole
+    free_all(c->child);
+    delete c->child;
+    c->child = nullptr;
+  }
+  for (hipGraphExec_t& g : c->apply_exec) {
+    if (g) (void)hipGraphExecDestroy(g);
+    g = nullptr;
+  }
+  for (auto& a : c->allocs) release_block(c, a.p);
+  c->allocs.clear();
+  c->bytes = 0;
+  clear_pointers(c);
+}
+
+// Clears every device pointer of the handle after its buffers were released, so that no stale
+// address (possibly handed out again by the allocator) is taken for a live buffer.
+void clear_pointers(mbddc_ctx* c) {
+  auto cl = [](auto*& p) { p = nullptr; };
+  cl(c->d_B);
+  cl(c->d_Hs);
+  cl(c->d_Kc);
+  cl(c->d_Kc_keep);
+  cl(c->d_Kcl);
+  cl(c->d_Ke);
+  cl(c->d_V);
+  cl(c->d_Wv);
+  cl(c->d_X);
+  cl(c->d_Y);
+  cl(c->d_Z);
+  cl(c->d_amax);
+  cl(c->d_bdinv);
+  cl(c->d_beta);
+  cl(c->d_bnorm);
+  cl(c->d_bpanel);
+  cl(c->d_bsr_col);
+  cl(c->d_bsr_contrib);
+  cl(c->d_bsr_cptr);
+  cl(c->d_bsr_kstride);
+  cl(c->d_bsr_rownode);
+  cl(c->d_bsr_rowptr);
+  cl(c->d_bthr);
+  cl(c->d_cCcol);
+  cl(c->d_cDinv);
+  cl(c->d_cY);
+  cl(c->d_cc);
+  cl(c->d_chunk_begin);
+  cl(c->d_chunk_inst);
+  cl(c->d_coarse_inst);
+  cl(c->d_coarse_ptr);
+  cl(c->d_coarse_slots);
+  cl(c->d_cons_idx);
+  cl(c->d_cons_ptr);
+  cl(c->d_cons_w);
+  cl(c->d_cs);
+  cl(c->d_cslot_coarse);
+  cl(c->d_cslot_sub);
+  cl(c->d_csym_gd);
+  cl(c->d_csym_items);
+  cl(c->d_dof_inst);
+  cl(c->d_elem_ldof);
+  cl(c->d_elem_ldof_off);
+  cl(c->d_elem_npe);
+  cl(c->d_ep);
+  cl(c->d_fin);
+  cl(c->d_flag);
+  cl(c->d_free);
+  cl(c->d_g);
+  cl(c->d_gemm_desc);
+  cl(c->d_gemm_g);
+  cl(c->d_gemm_gh);
+  cl(c->d_gemm_phi);
+  cl(c->d_gemm_s);
+  cl(c->d_gemm_ssym);
+  cl(c->d_gemm_stil);
+  cl(c->d_gj_cs);
+  cl(c->d_gj_kii);
+  cl(c->d_gj_p);
+  cl(c->d_gj_t);
+  cl(c->d_gj_x);
+  cl(c->d_h1);
+  cl(c->d_h2);
+  cl(c->d_hnorm);
+  cl(c->d_ifx_ptr);
+  cl(c->d_ifx_slots);
+  cl(c->d_inst_chunk_off);
+  cl(c->d_inst_coarse_off);
+  cl(c->d_inst_kc_ld);
+  cl(c->d_inst_kc_off);
+  cl(c->d_inst_nc);
+  cl(c->d_inst_nchunk);
+  cl(c->d_io);
+  cl(c->d_itA);
+  cl(c->d_itC);
+  cl(c->d_itE);
+  cl(c->d_itF);
+  cl(c->d_itH);
+  cl(c->d_ke_off);
+  cl(c->d_kstate);
+  cl(c->d_l2_eidx);
+  cl(c->d_l2_inv);
+  cl(c->d_nk);
+  cl(c->d_npart);
+  cl(c->d_part);
+  cl(c->d_part2);
+  cl(c->d_piv);
+  cl(c->d_piv_c);
+  cl(c->d_r);
+  cl(c->d_rho);
+  cl(c->d_slot_dof);
+  cl(c->d_slot_ifx);
+  cl(c->d_slot_owner);
+  cl(c->d_slot_w);
+  cl(c->d_sn);
+  cl(c->d_status);
+  cl(c->d_sub_dofs);
+  cl(c->d_sub_elems);
+  cl(c->d_subs);
+  cl(c->d_tb);
+  cl(c->d_vals);
+  cl(c->d_wb);
+  cl(c->d_x);
+  cl(c->d_y);
+  cl(c->d_W);
+  cl(c->d_Op);
+  cl(c->d_jsys);
+  cl(c->d_its);
+  cl(c->d_active);
+  cl(c->d_mode);
+  for (SymSet* S : {&c->set_kii, &c->set_x, &c->set_t}) {
+    cl(S->d_all); cl(S->d_big); cl(S->d_items); cl(S->d_gd); cl(S->d_gitems);
+  }
 }
 
 void free_all(mbddc_ctx* c) {
@@ -398,10 +571,6 @@ void free_all(mbddc_ctx* c) {
   c->prof.pending.clear();
   for (hipEvent_t e : c->prof.pool) (void)hipEventDestroy(e);
   c->prof.pool.clear();
-  for (hipGraphExec_t& g : c->apply_exec) {
-    if (g) (void)hipGraphExecDestroy(g);
-    g = nullptr;
-  }
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   c->cap_stream = nullptr;
   if (c->side) {
@@ -421,14 +590,15 @@ void free_all(mbddc_ctx* c) {
   if (c->aux) (void)hipStreamDestroy(c->aux);
   c->ev_a = c->ev_b = nullptr;
   c->aux = nullptr;
-  for (auto& a : c->allocs) (void)hipFree(a.p);
-  c->allocs.clear();
-  c->bytes = 0;
+  release_buffers(c);
   if (c->h_est) (void)hipHostFree(c->h_est);
   if (c->h_norm) (void)hipHostFree(c->h_norm);
   if (c->h_kstate) (void)hipHostFree(c->h_kstate);
+  if (c->h_flag) (void)hipHostFree(c->h_flag);
   c->h_est = c->h_norm = nullptr;
   c->h_kstate = nullptr;
+  c->h_flag = nullptr;
+  c->h_cap = 0;
 }
 
 template <typename T>
@@ -933,6 +1103,9 @@ int build_level2_host(mbddc_ctx* c, const std::vector<MeshIn>& fine) {
   c->child = ch;
   ch->device = c->device;
   ch->stream = c->stream;
+  ch->alloc_fn = c->alloc_fn;
+  ch->free_fn = c->free_fn;
+  ch->alloc_user = c->alloc_user;
   ch->opt = c->opt;
   ch->opt.levels = 2;
   ch->opt.primal = c->opt.coarse_primal;
@@ -960,11 +1133,11 @@ int upload_level2(mbddc_ctx* c) {
 }
 
 // Device bytes that a handle set up for `c`'s plan holds after factorisation and one
-// solve with 4 right-hand sides (host-side estimate for admission control).
-double device_bytes_estimate(const mbddc_ctx* c, bool krylov) {
+// solve with nrhs right-hand sides (host-side estimate for admission control).
+double device_bytes_estimate(const mbddc_ctx* c, bool krylov, int nrhs) {
   const Plan& P = c->plan;
   const double es = (double)elem_size(c->mixed), ef = (double)elem_size(c->fact32);
-  const double R = 4.0, J = c->opt.restart + 1;
+  const double R = apply_R(nrhs), J = c->opt.restart + 1;
   double b = 8.0 * P.ke_total + 72.0 * c->nblocks + ef * c->w_elems + es * c->op_elems + 8.0 * c->kcl_elems;
   b += 8.0 * (c->opt.levels == 3 ? 0 : c->kc_elems) + (c->opt.keep_coarse_matrix ? 8.0 * c->kc_elems : 0.0);
   b += 4.0 * c->piv_elems;
@@ -987,7 +1160,7 @@ double device_bytes_estimate(const mbddc_ctx* c, bool krylov) {
          16.0 * S->gitems.size();
   b += 8.0 * R * (2.0 * P.n_slots + std::max<int64_t>(P.n_cslots, 1) + c->nchunk_max * std::max<int64_t>(P.n_coarse, 1));
   b += 8.0 * R * P.n_dofs * (krylov ? (3 + 2 * J + 4) : 3);
-  if (c->child) b += device_bytes_estimate(c->child, false) + 8.0 * (P.n_coarse + P.n_cslots);
+  if (c->child) b += device_bytes_estimate(c->child, false, nrhs) + 8.0 * (P.n_coarse + P.n_cslots);
   return 1.02 * b + (1 << 20);
 }
 
@@ -1644,8 +1817,34 @@ constexpr uint32_t kApplyFamilies = (1u << F_APPLY_A) | (1u << F_APPLY_C) | (1u 
 
 // z = M^-1 r on the handle's fixed blocks d_X -> d_Y: replayed from a captured graph
 // unless graphs are off or an apply family is being profiled.
+// Algorithmic bytes and flops of one whole preconditioner application with R right-hand sides
+// (every phase, and the level-2 application when there is one).
+void apply_totals(const mbddc_ctx* c, int R, double* bytes, double* flops) {
+  double b = 0.0, f = 0.0;
+  for (int k : {F_APPLY_A, F_APPLY_C, F_APPLY_F, F_APPLY_H}) {
+    b += c->op_bytes[k] + 8.0 * R * c->vec_words[k];
+    f += 2.0 * R * c->fam_flops[k];
+  }
+  if (const mbddc_ctx* ch = c->child) {
+    b += 16.0 * R * c->plan.n_coarse;
+    for (int k : {F_APPLY_A, F_APPLY_C, F_APPLY_E, F_APPLY_F, F_APPLY_H}) {
+      b += ch->op_bytes[k] + 8.0 * R * ch->vec_words[k];
+      f += 2.0 * R * ch->fam_flops[k];
+    }
+  } else if (!c->itE.empty()) {
+    b += c->op_bytes[F_APPLY_E] + 8.0 * R * c->vec_words[F_APPLY_E];
+    f += 2.0 * R * c->fam_flops[F_APPLY_E];
+  }
+  *bytes = b;
+  *flops = f;
+}
+
 int apply_run(mbddc_ctx* c, int R) {
   c->n_applies++;
+  double ab = 0.0, af = 0.0;
+  if (c->prof.mask & (1u << F_APPLY_WHOLE)) apply_totals(c, R, &ab, &af);
+  // brackets the whole application, eager or replayed from the graph (does not force eager launches)
+  ProfScope whole(c, F_APPLY_WHOLE, ab, af);
   const bool profiled = (c->prof.mask & kApplyFamilies) || (c->child && (c->child->prof.mask & kApplyFamilies));
   if (!c->opt.graph_apply || profiled) return apply_dispatch(c, R, c->d_X, c->d_Y);
   const int slot = R == 1 ? 0 : (R == 2 ? 1 : (R == 4 ? 2 : 3));
@@ -1752,13 +1951,16 @@ int ensure_krylov(mbddc_ctx* c, int R) {
   dfree(c, c->d_kstate); dfree(c, c->d_nk); dfree(c, c->d_fin); dfree(c, c->d_bnorm);
   c->d_jsys = c->d_its = nullptr;
   c->d_active = c->d_mode = nullptr;
-  if (c->h_est) (void)hipHostFree(c->h_est);
-  if (c->h_norm) (void)hipHostFree(c->h_norm);
-  if (c->h_kstate) (void)hipHostFree(c->h_kstate);
-  c->h_est = c->h_norm = nullptr;
-  c->h_kstate = nullptr;
   const int64_t n = c->plan.n_dofs, J = restart + 1;
   const int64_t nsys = (int64_t)c->plan.n_inst * R;
+  if (nsys > c->h_cap) {   // pinned host buffers are kept while large enough (a host free syncs the device)
+    if (c->h_est) (void)hipHostFree(c->h_est);
+    if (c->h_norm) (void)hipHostFree(c->h_norm);
+    if (c->h_kstate) (void)hipHostFree(c->h_kstate);
+    c->h_est = c->h_norm = nullptr;
+    c->h_kstate = nullptr;
+    c->h_cap = 0;
+  }
   const int64_t nch = (int64_t)c->chunk_inst.size();
   CHK(dalloc(c, &c->d_V, J * n * R));
   CHK(dalloc(c, &c->d_Z, restart * n * R));
@@ -1787,11 +1989,14 @@ int ensure_krylov(mbddc_ctx* c, int R) {
   CHK(dalloc(c, &c->d_bnorm, nsys));
   CHK(dalloc(c, &c->d_nk, nsys));
   CHK(dalloc(c, &c->d_fin, nsys));
-  HIPCHK(hipHostMalloc((void**)&c->h_est, 2 * nsys * sizeof(double), hipHostMallocDefault));
+  if (!c->h_est) {
+    HIPCHK(hipHostMalloc((void**)&c->h_est, 2 * nsys * sizeof(double), hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void**)&c->h_norm, nsys * sizeof(double), hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void**)&c->h_kstate, 10 * nsys, hipHostMallocDefault));
+    c->h_cap = nsys;
+  }
   for (hipEvent_t& e : c->ev_step)
     if (!e) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-  HIPCHK(hipHostMalloc((void**)&c->h_norm, nsys * sizeof(double), hipHostMallocDefault));
-  HIPCHK(hipHostMalloc((void**)&c->h_kstate, 10 * nsys, hipHostMallocDefault));
   HIPCHK(hipMemsetAsync(c->d_V, 0, J * n * R * sizeof(double), c->stream));
   HIPCHK(hipMemsetAsync(c->d_Z, 0, restart * n * R * sizeof(double), c->stream));
   c->R_kry = R;
@@ -2030,6 +2235,10 @@ int gmres_impl(mbddc_ctx* c, int nrhs, mbddc_info* info) {
       hipLaunchKernelGGL(k_restart_g, dim3(gs), dim3(64), 0, c->stream, ka, nsys, c->d_fin, c->d_beta, c->d_g);
     }
   }
+  c->last_nrhs = nrhs;
+  c->last_its.assign((size_t)c->plan.n_inst * nrhs, 0);
+  for (int s = 0; s < nsys; ++s)
+    if ((s % R) < nrhs) c->last_its[(size_t)(s / R) * nrhs + (s % R)] = its[s];
   if (info) {
     info->iterations = 0;
     info->restarts = 0;
@@ -2109,6 +2318,19 @@ int mbddc_create(mbddc_ctx** out, int hip_device, void* hip_stream) {
   c->stream = reinterpret_cast<hipStream_t>(hip_stream);
   mbddc_default_options(&c->opt);
   *out = c;
+  return MBDDC_OK;
+}
+
+int mbddc_release(mbddc_ctx* c) {
+  if (!c) return MBDDC_ERR_ARG;
+  if (hipSetDevice(c->device) != hipSuccess) return MBDDC_ERR_DEVICE;
+  if (c->stream) HIPCHK(hipStreamSynchronize(c->stream));
+  else HIPCHK(hipDeviceSynchronize());
+  release_buffers(c);
+  c->state = 0;
+  c->R_alloc = 0; c->R_kry = 0; c->restart_kry = 0; c->Y_R = 0;
+  c->last_its.clear();
+  c->last_nrhs = 0;
   return MBDDC_OK;
 }
 
@@ -2423,15 +2645,16 @@ int autotune_impl(mbddc_ctx* c) {
 
 extern "C" {
 
-int mbddc_estimate_footprint(int n_inst, const mbddc_mesh* meshes, const mbddc_options* opt, size_t* device_bytes) {
-  if (!device_bytes) return MBDDC_ERR_ARG;
+int mbddc_estimate_footprint(int n_inst, const mbddc_mesh* meshes, const mbddc_options* opt, int nrhs,
+                             size_t* device_bytes) {
+  if (!device_bytes || nrhs < 1 || nrhs > kMaxRhs) return MBDDC_ERR_ARG;
   mbddc_options o;
   std::vector<MeshIn> ms;
   int st = parse_meshes(n_inst, meshes, opt, o, ms);
   if (st) return st;
   mbddc_ctx tmp;   // host only: no device call is made on it
   st = prepare_host(&tmp, o, ms);
-  if (!st) *device_bytes = (size_t)device_bytes_estimate(&tmp, true);
+  if (!st) *device_bytes = (size_t)device_bytes_estimate(&tmp, true, nrhs);
   if (tmp.child) {
     delete tmp.child;
     tmp.child = nullptr;
@@ -2446,8 +2669,11 @@ int mbddc_setup_symbolic_batch(mbddc_ctx* c, int n_inst, const mbddc_mesh* meshe
   std::vector<MeshIn> ms;
   CHK(parse_meshes(n_inst, meshes, opt, o, ms));
   if (c->stream) (void)hipStreamSynchronize(c->stream);
-  free_all(c);
+  else (void)hipDeviceSynchronize();
+  release_buffers(c);
   c->subs.clear();
+  c->last_its.clear();
+  c->last_nrhs = 0;
   c->R_alloc = 0; c->R_kry = 0; c->restart_kry = 0; c->Y_R = 0;
   c->d_tb = c->d_wb = c->d_cc = nullptr;
   c->d_ep = c->d_X = c->d_Y = c->d_io = nullptr;
@@ -2467,8 +2693,11 @@ int mbddc_setup_symbolic_batch(mbddc_ctx* c, int n_inst, const mbddc_mesh* meshe
   int st = prepare_host(c, o, ms);
   if (!st) st = upload_plan(c);
   if (!st && c->child) st = upload_level2(c);
+  if (!st) st = dalloc(c, &c->d_flag, 1);
+  if (!st && !c->h_flag) st = hipHostMalloc((void**)&c->h_flag, sizeof(int32_t), hipHostMallocDefault) == hipSuccess
+                                  ? MBDDC_OK : MBDDC_ERR_DEVICE;
   if (st) {
-    free_all(c);
+    release_buffers(c);
     return st;
   }
   c->state = 1;
@@ -2479,12 +2708,12 @@ int mbddc_setup_symbolic(mbddc_ctx* c, const mbddc_mesh* mesh, const mbddc_optio
   return mbddc_setup_symbolic_batch(c, 1, mesh, opt);
 }
 
-int mbddc_footprint(const mbddc_ctx* c, size_t* device_bytes) {
-  if (!c || !device_bytes) return MBDDC_ERR_ARG;
+int mbddc_footprint(const mbddc_ctx* c, int nrhs, size_t* device_bytes) {
+  if (!c || !device_bytes || nrhs < 1 || nrhs > kMaxRhs) return MBDDC_ERR_ARG;
   if (c->state < 1) return MBDDC_ERR_STATE;
   const Plan& P = c->plan;
-  const int R = 4, J = c->opt.restart + 1;
-  // per-call buffers that a solve with 4 right-hand sides allocates, unless already held
+  const int R = apply_R(nrhs), J = c->opt.restart + 1;
+  // per-call buffers that a solve with nrhs right-hand sides allocates, unless already held
   size_t extra = 0;
   if (c->R_alloc < R) {
     extra += (size_t)P.n_slots * R * 8 * 2 + (size_t)std::max<int64_t>(P.n_cslots, 1) * R * 8;
@@ -2528,12 +2757,16 @@ int mbddc_set_tangent(mbddc_ctx* c, const double* elem_K, int on_device) {
   if (c->state < 1) return MBDDC_ERR_STATE;
   if (hipSetDevice(c->device) != hipSuccess) return MBDDC_ERR_DEVICE;
   const Plan& P = c->plan;
-  if (!on_device) {
-    for (int64_t i = 0; i < P.ke_total; ++i)
-      if (!std::isfinite(elem_K[i])) return MBDDC_ERR_ARG;
-  }
   HIPCHK(hipMemcpyAsync(c->d_Ke, elem_K, P.ke_total * sizeof(double),
                         on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->stream));
+  // reject NaN / Inf before the operator is touched (one read of K_e on the device)
+  HIPCHK(hipMemsetAsync(c->d_flag, 0, sizeof(int32_t), c->stream));
+  hipLaunchKernelGGL(k_nonfinite, dim3((unsigned)std::min<int64_t>(4096, nblk(P.ke_total))), dim3(kBlock), 0,
+                     c->stream, c->d_Ke, P.ke_total, c->d_flag);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipMemcpyAsync(c->h_flag, c->d_flag, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  if (*c->h_flag) return MBDDC_ERR_ARG;
   {
     ProfScope ps(c, F_ASSEMBLE_BSR, c->op_bytes[F_ASSEMBLE_BSR], 0.0);
     hipLaunchKernelGGL(k_assemble_bsr, dim3(nblk(c->nblocks * 9)), dim3(kBlock), 0, c->stream, c->d_Ke, c->d_bsr_rowptr,
@@ -2699,6 +2932,24 @@ int mbddc_get_bsr(const mbddc_ctx* c, int32_t* rowptr, int32_t* colidx, double* 
 }
 
 int mbddc_last_bad_subdomain(const mbddc_ctx* c) { return c ? c->last_bad : 0; }
+
+int mbddc_get_iterations(const mbddc_ctx* c, int32_t* its, int64_t max_entries, int64_t* n_entries) {
+  if (!c || (!its && max_entries > 0)) return MBDDC_ERR_ARG;
+  if (c->state < 3) return MBDDC_ERR_STATE;
+  const int64_t n = (int64_t)c->last_its.size();
+  if (n_entries) *n_entries = n;
+  for (int64_t k = 0; k < std::min(n, max_entries); ++k) its[k] = c->last_its[k];
+  return MBDDC_OK;
+}
+
+int mbddc_set_allocator(mbddc_ctx* c, void* (*alloc)(size_t, void*), void (*free_)(void*, void*), void* user) {
+  if (!c || (!alloc) != (!free_)) return MBDDC_ERR_ARG;
+  if (c->state != 0 || !c->allocs.empty()) return MBDDC_ERR_STATE;
+  c->alloc_fn = alloc;
+  c->free_fn = free_;
+  c->alloc_user = alloc ? user : nullptr;
+  return MBDDC_OK;
+}
 
 const char* mbddc_profile_family_name(int family) {
   return (family >= 0 && family < F_COUNT) ? kFamilyName[family] : nullptr;

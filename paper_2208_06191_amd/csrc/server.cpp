@@ -2,9 +2,11 @@
 //
 // Host runtime above the solver library: a FIFO queue, admission by the
 // estimated device footprint, and a pool of worker threads, each driving one
-// request at a time on its own HIP stream through the public C ABI. Requests
-// that run at the same time overlap on the device; each request owns its
-// handle, so its arithmetic does not depend on what else runs.
+// request at a time on its own HIP stream and its own handle through the public
+// C ABI. Requests that run at the same time overlap on the device; a request's
+// arithmetic does not depend on what else runs. Device memory comes from one
+// caching pool (mbddc_set_allocator), so that a warm server serves requests
+// without hipMalloc / hipFree (a hipFree waits for the whole device).
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
@@ -14,6 +16,7 @@
 #include <deque>
 #include <map>
 #include <mutex>
+#include <unordered_map>
 #include <new>
 #include <thread>
 #include <vector>
@@ -39,10 +42,82 @@ struct Job {
   mbddc_request_result res{};
 };
 
+// Caching device-memory pool shared by the workers' handles. Blocks are kept by size after
+// they are returned; an allocation takes the smallest cached block of at least the requested
+// size and at most twice it, else a new hipMalloc (rounded to 2 MiB above 1 MiB). When a
+// hipMalloc fails, or the cache would hold more than `cap` bytes, cached blocks are freed.
+struct Pool {
+  int device = 0;
+  size_t cap = 0;
+  std::mutex mu;
+  std::multimap<size_t, void*> cache;          // free blocks by size
+  std::unordered_map<void*, size_t> in_use;    // block -> size
+  size_t bytes_in_use = 0, bytes_cached = 0;
+  int64_t mallocs = 0, frees = 0;
+
+  static size_t round(size_t b) {
+    const size_t big = size_t(2) << 20;
+    return b > (size_t(1) << 20) ? (b + big - 1) / big * big : (b + 4095) / 4096 * 4096;
+  }
+  // frees cached blocks, largest first, until at most `keep` bytes stay cached (lock held)
+  void trim(size_t keep) {
+    while (bytes_cached > keep && !cache.empty()) {
+      auto it = std::prev(cache.end());
+      (void)hipFree(it->second);
+      frees++;
+      bytes_cached -= it->first;
+      cache.erase(it);
+    }
+  }
+  void* alloc(size_t b) {
+    b = round(b);
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.lower_bound(b);
+    if (it != cache.end() && it->first <= 2 * b) {
+      void* p = it->second;
+      const size_t sz = it->first;
+      cache.erase(it);
+      bytes_cached -= sz;
+      in_use[p] = sz;
+      bytes_in_use += sz;
+      return p;
+    }
+    (void)hipSetDevice(device);
+    void* p = nullptr;
+    if (hipMalloc(&p, b) != hipSuccess) {
+      (void)hipGetLastError();
+      trim(0);
+      if (hipMalloc(&p, b) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+      }
+    }
+    mallocs++;
+    in_use[p] = b;
+    bytes_in_use += b;
+    return p;
+  }
+  void release(void* p) {
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = in_use.find(p);
+    if (it == in_use.end()) return;
+    const size_t sz = it->second;
+    in_use.erase(it);
+    bytes_in_use -= sz;
+    cache.emplace(sz, p);
+    bytes_cached += sz;
+    if (bytes_cached > cap) trim(cap / 2);
+  }
+};
+
+void* pool_alloc(size_t bytes, void* user) { return static_cast<Pool*>(user)->alloc(bytes); }
+void pool_free(void* p, void* user) { static_cast<Pool*>(user)->release(p); }
+
 }  // namespace
 
 struct mbddc_server {
   int device = 0;
+  Pool pool;
   size_t budget = 0;
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
@@ -62,11 +137,9 @@ struct mbddc_server {
 
 namespace {
 
-void run_job(mbddc_server* s, Job* j, hipStream_t stream) {
+void run_job(mbddc_server* s, Job* j, mbddc_ctx* h) {
   mbddc_request_result& r = j->res;
-  mbddc_ctx* h = nullptr;
-  int st = mbddc_create(&h, s->device, stream);
-  if (!st) st = mbddc_setup_symbolic(h, &j->mesh, &j->opt);
+  int st = mbddc_setup_symbolic(h, &j->mesh, &j->opt);
   for (int k = 0; !st && k < j->n_steps; ++k) {
     st = mbddc_set_tangent(h, j->K + (int64_t)k * j->ke_total, 0);
     if (!st && (k == 0 || !j->lagged)) st = mbddc_factor(h);
@@ -79,13 +152,17 @@ void run_job(mbddc_server* s, Job* j, hipStream_t stream) {
     r.n_steps = k + 1;
   }
   r.status = st;
-  if (h) mbddc_destroy(h);
+  const int st2 = mbddc_release(h);   // buffers back to the pool; the handle serves the next request
+  if (r.status == MBDDC_OK) r.status = st2;
 }
 
 void worker(mbddc_server* s) {
   (void)hipSetDevice(s->device);
   hipStream_t stream = nullptr;
-  const bool have_stream = hipStreamCreateWithFlags(&stream, hipStreamNonBlocking) == hipSuccess;
+  mbddc_ctx* h = nullptr;
+  bool ready = hipStreamCreateWithFlags(&stream, hipStreamNonBlocking) == hipSuccess;
+  ready = ready && mbddc_create(&h, s->device, stream) == MBDDC_OK;
+  ready = ready && mbddc_set_allocator(h, pool_alloc, pool_free, &s->pool) == MBDDC_OK;
   for (;;) {
     Job* j = nullptr;
     {
@@ -101,8 +178,8 @@ void worker(mbddc_server* s) {
       s->active++;
       j->res.t_admit_ms = s->now_ms();
     }
-    if (have_stream) {
-      run_job(s, j, stream);
+    if (ready) {
+      run_job(s, j, h);
     } else {
       j->res.status = MBDDC_ERR_DEVICE;
     }
@@ -116,6 +193,7 @@ void worker(mbddc_server* s) {
     s->cv_work.notify_all();
     s->cv_done.notify_all();
   }
+  if (h) mbddc_destroy(h);
   if (stream) (void)hipStreamDestroy(stream);
 }
 
@@ -133,6 +211,8 @@ int mbddc_server_create(mbddc_server** out, int hip_device, size_t hbm_budget, i
   if (!s) return MBDDC_ERR_OOM;
   s->device = hip_device;
   s->budget = hbm_budget;
+  s->pool.device = hip_device;
+  s->pool.cap = hbm_budget;
   s->t0 = std::chrono::steady_clock::now();
   for (int i = 0; i < max_active; ++i) s->workers.emplace_back(worker, s);
   *out = s;
@@ -149,7 +229,7 @@ int mbddc_server_submit(mbddc_server* s, const mbddc_request* q, int64_t* ticket
       (m.n_dirichlet > 0 && !m.dirichlet_dofs))
     return MBDDC_ERR_ARG;
   size_t fp = 0;
-  int st = mbddc_estimate_footprint(1, &m, &q->opt, &fp);
+  int st = mbddc_estimate_footprint(1, &m, &q->opt, q->nrhs, &fp);
   if (st) return st;
   if (fp > s->budget) return MBDDC_ERR_OOM;
   Job* j = new (std::nothrow) Job();
@@ -224,7 +304,24 @@ int mbddc_server_destroy(mbddc_server* s) {
   s->cv_work.notify_all();
   for (std::thread& t : s->workers) t.join();
   for (auto& kv : s->jobs) delete kv.second;
+  {
+    std::lock_guard<std::mutex> lk(s->pool.mu);
+    (void)hipSetDevice(s->device);
+    s->pool.trim(0);
+    for (auto& kv : s->pool.in_use) (void)hipFree(kv.first);   // none once every handle is gone
+  }
   delete s;
+  return MBDDC_OK;
+}
+
+int mbddc_server_pool_stats(mbddc_server* s, int64_t* device_mallocs, int64_t* device_frees, size_t* bytes_in_use,
+                            size_t* bytes_cached) {
+  if (!s) return MBDDC_ERR_ARG;
+  std::lock_guard<std::mutex> lk(s->pool.mu);
+  if (device_mallocs) *device_mallocs = s->pool.mallocs;
+  if (device_frees) *device_frees = s->pool.frees;
+  if (bytes_in_use) *bytes_in_use = s->pool.bytes_in_use;
+  if (bytes_cached) *bytes_cached = s->pool.bytes_cached;
   return MBDDC_OK;
 }
 

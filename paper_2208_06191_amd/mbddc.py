@@ -83,9 +83,13 @@ _SIGNATURES = {
     "mbddc_setup_symbolic": [ctypes.c_void_p, ctypes.POINTER(mbddc_mesh), ctypes.POINTER(mbddc_options)],
     "mbddc_setup_symbolic_batch": [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(mbddc_mesh),
                                    ctypes.POINTER(mbddc_options)],
-    "mbddc_footprint": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t)],
+    "mbddc_footprint": [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)],
     "mbddc_estimate_footprint": [ctypes.c_int, ctypes.POINTER(mbddc_mesh), ctypes.POINTER(mbddc_options),
-                                 ctypes.POINTER(ctypes.c_size_t)],
+                                 ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)],
+    "mbddc_set_allocator": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p],
+    "mbddc_release": [ctypes.c_void_p],
+    "mbddc_get_iterations": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32), ctypes.c_int64,
+                             ctypes.POINTER(ctypes.c_int64)],
     "mbddc_get_sizes": [ctypes.c_void_p, ctypes.POINTER(mbddc_sizes)],
     "mbddc_set_tangent": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int],
     "mbddc_factor": [ctypes.c_void_p],
@@ -114,7 +118,13 @@ _SIGNATURES = {
     "mbddc_server_state": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                            ctypes.POINTER(ctypes.c_size_t)],
     "mbddc_server_destroy": [ctypes.c_void_p],
+    "mbddc_server_pool_stats": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                                ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)],
 }
+
+# device memory provider callbacks of mbddc_set_allocator
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
 
 
 def lib():
@@ -217,14 +227,44 @@ def _dev_ptr(t):
     return ctypes.c_void_p(t.data_ptr())
 
 
-def mbddc_estimate_footprint(meshes: Sequence[_MeshArrays], options: Optional[mbddc_options] = None) -> int:
-    """Host-only estimate of the device bytes of a handle for these meshes (no device needed)."""
+def mbddc_estimate_footprint(meshes: Sequence[_MeshArrays], options: Optional[mbddc_options] = None,
+                             nrhs: int = 4) -> int:
+    """Host-only estimate of the device bytes of a handle for these meshes after a solve of
+    nrhs right-hand sides (no device needed)."""
     arr = (mbddc_mesh * len(meshes))(*[m.mesh for m in meshes])
     o = options if options is not None else default_options()
     b = ctypes.c_size_t()
-    _check(lib().mbddc_estimate_footprint(len(meshes), arr, ctypes.byref(o), ctypes.byref(b)),
+    _check(lib().mbddc_estimate_footprint(len(meshes), arr, ctypes.byref(o), nrhs, ctypes.byref(b)),
            "mbddc_estimate_footprint")
     return b.value
+
+
+class TorchAllocator:
+    """Device memory for a handle from PyTorch's caching allocator (mbddc_set_allocator):
+    each block is a uint8 tensor kept alive until the library returns it. Counts calls."""
+
+    def __init__(self, device: int = 0):
+        import torch
+        self._torch = torch
+        self.device = device
+        self.blocks = {}
+        self.n_alloc = 0
+        self.n_free = 0
+        self.c_alloc = ALLOC_FN(self._alloc)
+        self.c_free = FREE_FN(self._free)
+
+    def _alloc(self, nbytes, _user):
+        try:
+            t = self._torch.empty(int(nbytes), dtype=self._torch.uint8, device=f"cuda:{self.device}")
+        except RuntimeError:
+            return None
+        self.blocks[t.data_ptr()] = t
+        self.n_alloc += 1
+        return t.data_ptr()
+
+    def _free(self, ptr, _user):
+        self.n_free += 1
+        self.blocks.pop(int(ptr), None)
 
 
 class Server:
@@ -256,6 +296,12 @@ class Server:
         _, _, _, x = self._keep.pop(ticket)
         return r, x
 
+    def pool_stats(self) -> dict:
+        m, f, u, c = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_size_t(), ctypes.c_size_t()
+        _check(lib().mbddc_server_pool_stats(self._s, ctypes.byref(m), ctypes.byref(f), ctypes.byref(u),
+                                             ctypes.byref(c)), "mbddc_server_pool_stats")
+        return {"device_mallocs": m.value, "device_frees": f.value, "bytes_in_use": u.value, "bytes_cached": c.value}
+
     def state(self):
         q, a, b = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_size_t()
         _check(lib().mbddc_server_state(self._s, ctypes.byref(q), ctypes.byref(a), ctypes.byref(b)),
@@ -278,10 +324,17 @@ class Server:
 class Solver:
     """One handle: setup_symbolic -> set_tangent -> factor -> solve/apply/matvec."""
 
-    def __init__(self, device: int = 0, stream=None):
+    def __init__(self, device: int = 0, stream=None, allocator: Optional[TorchAllocator] = None):
+        """allocator: e.g. TorchAllocator(device) to take every device buffer from PyTorch's
+        caching allocator (mbddc_set_allocator); None: the library's hipMalloc."""
         self._h = ctypes.c_void_p()
         s = None if stream is None else ctypes.c_void_p(int(stream))
         _check(lib().mbddc_create(ctypes.byref(self._h), device, s), "mbddc_create")
+        self.allocator = allocator
+        if allocator is not None:
+            _check(lib().mbddc_set_allocator(self._h, ctypes.cast(allocator.c_alloc, ctypes.c_void_p),
+                                             ctypes.cast(allocator.c_free, ctypes.c_void_p), None),
+                   "mbddc_set_allocator")
         self._meshes = []
         self.n_dofs = 0
 
@@ -289,6 +342,9 @@ class Solver:
         if self._h:
             lib().mbddc_destroy(self._h)
             self._h = ctypes.c_void_p()
+
+    def mbddc_release(self):
+        _check(lib().mbddc_release(self._h), "mbddc_release")
 
     def __del__(self):
         try:
@@ -309,10 +365,19 @@ class Solver:
         _check(lib().mbddc_get_sizes(self._h, ctypes.byref(s)), "mbddc_get_sizes")
         return s
 
-    def mbddc_footprint(self) -> int:
+    def mbddc_footprint(self, nrhs: int = 4) -> int:
         b = ctypes.c_size_t()
-        _check(lib().mbddc_footprint(self._h, ctypes.byref(b)), "mbddc_footprint")
+        _check(lib().mbddc_footprint(self._h, nrhs, ctypes.byref(b)), "mbddc_footprint")
         return b.value
+
+    def mbddc_get_iterations(self) -> np.ndarray:
+        """GMRES iterations of each system of the last solve, [n_instances, nrhs]."""
+        n = ctypes.c_int64()
+        _check(lib().mbddc_get_iterations(self._h, None, 0, ctypes.byref(n)), "mbddc_get_iterations")
+        out = np.zeros(max(n.value, 1), np.int32)
+        _check(lib().mbddc_get_iterations(self._h, _ptr(out, ctypes.c_int32), n.value, ctypes.byref(n)),
+               "mbddc_get_iterations")
+        return out[:n.value].reshape(self.sizes().n_instances, -1)
 
     def mbddc_set_tangent(self, Ke):
         if isinstance(Ke, np.ndarray):

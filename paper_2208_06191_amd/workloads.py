@@ -28,6 +28,9 @@ import dataclasses
 import math
 from typing import Optional
 
+import concurrent.futures
+import os
+
 import numpy as np
 
 HEX8 = 1
@@ -325,7 +328,8 @@ def element_tangents(mesh: Mesh, material, u: Optional[np.ndarray] = None,
     nd = 3 * npe
     out = np.zeros((mesh.n_elems, nd, nd))
     I = _eye3()
-    for e0 in range(0, mesh.n_elems, chunk):
+
+    def one_chunk(e0):
         elems = np.arange(e0, min(mesh.n_elems, e0 + chunk))
         ue = None if u is None else u[mesh.elem_nodes[elems]]   # [e, npe, 3]
         Ke = np.zeros((len(elems), npe, 3, npe, 3))
@@ -350,6 +354,17 @@ def element_tangents(mesh: Mesh, material, u: Optional[np.ndarray] = None,
             Kq = np.matmul(Bm, dNX.transpose(0, 2, 1)).reshape(m, npe, 3, 3, npe)
             Ke += wdet[:, None, None, None, None] * Kq.transpose(0, 1, 2, 4, 3)
         out[elems] = Ke.reshape(len(elems), nd, nd)
+
+    # chunks are independent (each writes its own elements): run them on a thread pool, the
+    # arithmetic of every chunk is the same as in a sequential loop
+    starts = list(range(0, mesh.n_elems, chunk))
+    workers = min(len(starts), max(1, min(16, os.cpu_count() or 1)))
+    if workers > 1:
+        with concurrent.futures.ThreadPoolExecutor(workers) as ex:
+            list(ex.map(one_chunk, starts))
+    else:
+        for e0 in starts:
+            one_chunk(e0)
     return out
 
 

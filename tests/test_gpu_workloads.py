@@ -1,0 +1,205 @@
+"""GPU parity against the FP64 oracle on the shapes of the benchmark workloads.
+
+* The ventricle-like Q2 shell at 1/16 of the full mesh (63.5k DOFs) whose RCB parts have the
+  full-size shape (2k-5.7k DOFs, interiors up to 4.4k), with three levels (groups of 8, V+E+F at
+  both levels, §3.2 last paragraph, §7): one preconditioner application, GMRES iterations
+  (FP64: oracle +-1; mixed: <= oracle + 2) and the solution (FP64 1e-8, mixed 1e-6, both solves
+  to rtol 1e-10), as at full size.
+* Independent instances in one handle (Q1 and Q2 neo-Hookean boxes of different sizes and
+  materials, 4 right-hand sides each, subdomains numbered in 2x2x2 clusters), two and three
+  levels, MIXED and FP64: each instance's block of one application against its own oracle,
+  each (instance, right-hand side) system's iteration count and solution against the oracle's.
+* FP32 local factorisations (MBDDC_MIXED_F32FACT): the FP64 outer GMRES still reaches the FP64
+  residual; its iteration overhead over the oracle is bounded and reported (the mode is outside
+  MBDDC_MIXED's oracle + 2 contract).
+"""
+import functools
+
+import numpy as np
+import pytest
+
+from oracle import bddc, gmres
+from paper_2208_06191_amd import mbddc
+from paper_2208_06191_amd import workloads as W
+from tests.conftest import apply_noise_floor, problem
+
+pytestmark = pytest.mark.gpu
+
+PRECS = [mbddc.MBDDC_FP64, mbddc.MBDDC_MIXED]
+TOL_APPLY = {mbddc.MBDDC_FP64: 1e-12, mbddc.MBDDC_MIXED: 1e-5}
+TOL_SOL = {mbddc.MBDDC_FP64: 1e-8, mbddc.MBDDC_MIXED: 1e-6}
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def its_ok(precision, got, ref):
+    if precision == mbddc.MBDDC_FP64:
+        return abs(got - ref) <= 1
+    return got <= ref + 2
+
+
+# ----------------------------------------------------------------------------- shell, 3 levels
+@functools.lru_cache(maxsize=None)
+def vent3_oracle():
+    P = problem("vent_parts6k")
+    dec = bddc.Decomposition(P.mesh.elem_nodes, P.mesh.n_nodes, P.elem_part, P.n_sub, P.dirichlet,
+                             P.mesh.node_tags, primal=7)
+    return dec, bddc.BDDC(dec, P.mesh.elem_nodes, P.Ke, levels=3, coarse_group=8, level2_primal=7)
+
+
+@functools.lru_cache(maxsize=None)
+def vent3_ref(rtol):
+    P = problem("vent_parts6k")
+    dec, B = vent3_oracle()
+    return gmres.gmres(lambda v: B.A @ v, B.apply, P.rhs[0][dec.free], rtol, 30, 1000)
+
+
+@pytest.mark.parametrize("precision", PRECS)
+def test_shell_full_size_parts_three_levels(precision):
+    P = problem("vent_parts6k")
+    dec, B = vent3_oracle()
+    assert len(B.L2.spaces) >= 2                      # several level-2 subdomains
+    nI = np.array([s.n_interior for s in dec.subdomains])
+    assert nI.max() > 4000
+    s = mbddc.Solver(0)
+    s.mbddc_setup_symbolic([mbddc.mesh_from_problem(P)],
+                           mbddc.default_options(precision=precision, primal=7, levels=3, coarse_group=8,
+                                                 coarse_primal=7, symmetric_hint=1, keep_coarse_matrix=1))
+    s.mbddc_set_tangent(P.Ke)
+    s.mbddc_factor()
+    assert s.sizes().n_sub2 == len(B.L2.spaces) and s.sizes().n_coarse2 == B.L2.n_coarse
+    assert rel(s.mbddc_get_coarse_matrix(0, dec.n_coarse), B.Kc) <= 1e-12
+    r = np.random.default_rng(11).standard_normal((2, P.n_dofs))
+    r[:, P.dirichlet] = 0.0
+    z = s.mbddc_apply(r)
+    err = max(rel(z[k][dec.free], B.apply(r[k][dec.free])) for k in range(2))
+    bound = max(TOL_APPLY[precision], 100.0 * apply_noise_floor("vent_parts6k", 7, 3, 8, 7))
+    ref = vent3_ref(1e-8)
+    x, info = s.mbddc_solve(P.rhs[0])
+    print(f"shell 3 levels prec={precision}: apply {err:.2e} (bound {bound:.1e}), its {info.iterations} "
+          f"(oracle {ref.iterations}), res {info.rel_res_true:.2e}")
+    assert err <= bound
+    assert info.rel_res_true <= 1e-8
+    assert its_ok(precision, info.iterations, ref.iterations)
+    # the solution, both sides to rtol 1e-10
+    s2 = mbddc.Solver(0)
+    s2.mbddc_setup_symbolic([mbddc.mesh_from_problem(P)],
+                            mbddc.default_options(precision=precision, primal=7, levels=3, coarse_group=8,
+                                                  coarse_primal=7, symmetric_hint=1, rtol=1e-10))
+    s2.mbddc_set_tangent(P.Ke)
+    s2.mbddc_factor()
+    xt, _ = s2.mbddc_solve(P.rhs[0])
+    e = rel(xt[dec.free], vent3_ref(1e-10).x)
+    print(f"  solution error at rtol 1e-10: {e:.2e}")
+    assert e <= TOL_SOL[precision]
+    s.close()
+    s2.close()
+
+
+# ------------------------------------------------------------------------- batched instances
+@functools.lru_cache(maxsize=None)
+def batch():
+    """Six instances, Q1 and Q2, 2.2k-15k DOFs, (mu, kappa) = (1, 50) x U[0.5, 2] factors."""
+    probs = W.batched_instances(6, seed=300, dof_min=3e3, dof_max=2e4, nrhs=4)
+    assert {P.mesh.order for P in probs} == {1, 2}
+    return probs
+
+
+@functools.lru_cache(maxsize=None)
+def batch_oracles(levels):
+    out = []
+    for P in batch():
+        dec = bddc.Decomposition(P.mesh.elem_nodes, P.mesh.n_nodes, P.elem_part, P.n_sub, P.dirichlet,
+                                 P.mesh.node_tags, primal=3)
+        B = bddc.BDDC(dec, P.mesh.elem_nodes, P.Ke, levels=levels, coarse_group=8, level2_primal=7)
+        refs = [gmres.gmres(lambda v, B=B: B.A @ v, B.apply, P.rhs[k][dec.free], 1e-8, 30, 1000)
+                for k in range(P.rhs.shape[0])]
+        out.append((dec, B, refs))
+    return out
+
+
+@pytest.mark.parametrize("levels", [2, 3])
+@pytest.mark.parametrize("precision", PRECS)
+def test_batched_instances_against_each_oracle(precision, levels):
+    probs = batch()
+    orc = batch_oracles(levels)
+    s = mbddc.Solver(0)
+    s.mbddc_setup_symbolic([mbddc.mesh_from_problem(P) for P in probs],
+                           mbddc.default_options(precision=precision, primal=3, levels=levels, symmetric_hint=1))
+    s.mbddc_set_tangent(np.concatenate([P.Ke.ravel() for P in probs]))
+    s.mbddc_factor()
+    offs = np.cumsum([0] + [P.n_dofs for P in probs])
+    rng = np.random.default_rng(5)
+    r = rng.standard_normal((4, offs[-1]))
+    for P, o in zip(probs, offs):
+        r[:, o + P.dirichlet] = 0.0
+    z = s.mbddc_apply(r)
+    b = np.concatenate([P.rhs for P in probs], axis=1)
+    x, info = s.mbddc_solve(b)
+    its = s.mbddc_get_iterations()
+    assert its.shape == (len(probs), 4)
+    worst = dict(apply=0.0, its=-99, sol=0.0)
+    for i, (P, (dec, B, refs)) in enumerate(zip(probs, orc)):
+        sl = slice(offs[i], offs[i + 1])
+        for k in range(4):
+            ea = rel(z[k, sl][dec.free], B.apply(r[k, sl][dec.free]))
+            assert ea <= TOL_APPLY[precision], (i, k, ea)
+            xk = x[k, sl][dec.free]
+            bk = P.rhs[k][dec.free]
+            assert np.linalg.norm(bk - B.A @ xk) <= 1e-8 * np.linalg.norm(bk)
+            assert its_ok(precision, its[i, k], refs[k].iterations), (i, k, its[i, k], refs[k].iterations)
+            es = rel(xk, refs[k].x)
+            assert es <= TOL_SOL[precision] * 10, (i, k, es)   # both sides stopped at rtol 1e-8
+            worst = dict(apply=max(worst["apply"], ea), its=max(worst["its"], its[i, k] - refs[k].iterations),
+                         sol=max(worst["sol"], es))
+    print(f"batched prec={precision} levels={levels}: worst apply {worst['apply']:.2e}, "
+          f"iterations - oracle <= {worst['its']}, solution {worst['sol']:.2e}")
+    s.close()
+
+
+@pytest.mark.parametrize("precision", PRECS)
+def test_batched_solution_parity_tight_tolerance(precision):
+    """Solutions of every (instance, right-hand side) system against the oracle's, both to rtol 1e-11."""
+    probs = batch()
+    s = mbddc.Solver(0)
+    s.mbddc_setup_symbolic([mbddc.mesh_from_problem(P) for P in probs],
+                           mbddc.default_options(precision=precision, primal=3, symmetric_hint=1, rtol=1e-11))
+    s.mbddc_set_tangent(np.concatenate([P.Ke.ravel() for P in probs]))
+    s.mbddc_factor()
+    offs = np.cumsum([0] + [P.n_dofs for P in probs])
+    x, _ = s.mbddc_solve(np.concatenate([P.rhs for P in probs], axis=1))
+    worst = 0.0
+    for i, (P, (dec, B, _)) in enumerate(zip(probs, batch_oracles(2))):
+        for k in (0, 3):
+            ref = gmres.gmres(lambda v: B.A @ v, B.apply, P.rhs[k][dec.free], 1e-11, 30, 1000)
+            e = rel(x[k, offs[i]:offs[i + 1]][dec.free], ref.x)
+            worst = max(worst, e)
+            assert e <= TOL_SOL[precision], (i, k, e)
+    print(f"batched prec={precision}: worst solution error at rtol 1e-11: {worst:.2e}")
+    s.close()
+
+
+# ------------------------------------------------------------------- FP32 local factorisations
+@pytest.mark.parametrize("sym", [0, 1])
+@pytest.mark.parametrize("name,primal", [("small", 1), ("small_ve", 3), ("tiny_nh", 3), ("ragged", 3)])
+def test_fp32_factorisation_iteration_overhead(name, primal, sym):
+    P = problem(name)
+    dec = bddc.Decomposition(P.mesh.elem_nodes, P.mesh.n_nodes, P.elem_part, P.n_sub, P.dirichlet,
+                             P.mesh.node_tags, primal=primal)
+    B = bddc.BDDC(dec, P.mesh.elem_nodes, P.Ke)
+    s = mbddc.Solver(0)
+    s.mbddc_setup_symbolic([mbddc.mesh_from_problem(P)],
+                           mbddc.default_options(precision=mbddc.MBDDC_MIXED_F32FACT, primal=primal, symmetric_hint=sym))
+    s.mbddc_set_tangent(P.Ke)
+    s.mbddc_factor()
+    deltas = []
+    for k in range(P.rhs.shape[0]):
+        ref = gmres.gmres(lambda v: B.A @ v, B.apply, P.rhs[k][dec.free], 1e-8, 30, 1000)
+        x, info = s.mbddc_solve(P.rhs[k])
+        assert info.rel_res_true <= 1e-8
+        deltas.append(info.iterations - ref.iterations)
+        assert rel(x[dec.free], ref.x) <= 1e-5
+    print(f"{name} sym={sym}: FP32-factor iterations - oracle = {deltas}")
+    assert max(deltas) <= 6
