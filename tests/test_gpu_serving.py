@@ -126,7 +126,7 @@ def test_each_result_same_alone_and_in_the_mix():
 
 def test_admission_respects_the_footprint_budget():
     cases = [request_case("nh", 12), request_case("nh", 12, seed=1), request_case("lin", 12)]
-    fps = [mbddc.mbddc_estimate_footprint([c[0]], options(c[1])) for c in cases]
+    fps = [mbddc.mbddc_estimate_footprint([c[0]], options(c[1]), c[3].shape[1]) for c in cases]
     budget = max(fps) + min(fps) // 2          # never two at a time
     srv = mbddc.Server(0, budget, 3)
     tickets = [srv.submit(c[0], options(c[1]), c[2], c[3]) for c in cases]
