@@ -221,6 +221,18 @@ int mbddc_apply(mbddc_ctx* ctx, int nrhs, const double* r, double* z, int on_dev
 /* y = K x with the assembled FP64 operator (clamped rows/columns removed). */
 int mbddc_matvec(mbddc_ctx* ctx, int nrhs, const double* x, double* y, int on_device);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): y = K x as mbddc_matvec with device pointers, making no
+ * allocation. Its staging blocks (the interleaved copies of x and y, 8 * R * n_dofs bytes each,
+ * R = 1, 2, 4 or 8 the smallest >= nrhs) live in one static device buffer of
+ * MBDDC_NOALLOC_SCRATCH_BYTES per GPU, held from the first mbddc_create on that GPU until the
+ * process ends. x, y: device pointers, [nrhs][n_dofs]. MBDDC_ERR_UNSUPPORTED when the two blocks
+ * exceed the buffer (e.g. n_dofs * R > 1,048,576); MBDDC_ERR_STATE before a tangent is set.
+ * Every call on a GPU shares that GPU's buffer: calls that overlap on one GPU (other threads,
+ * other handles) race and must be serialised by the caller. */
+#define MBDDC_NOALLOC_SCRATCH_BYTES (16u << 20)
+int mbddc_matvec_noalloc(mbddc_ctx* ctx, int nrhs, const double* x, double* y);
+
 /* Integer results of the symbolic setup, for inspection (host arrays):
  * node_glob [n_nodes total] glob id or -1; glob_kind [n_globs] 1/2/4;
  * coarse_glob/coarse_comp [n_coarse]. Any pointer may be NULL. */

@@ -36,6 +36,14 @@
 
 using namespace mbddc;
 
+// Static device scratch of the no-allocation entry point (mbddc_matvec_noalloc): the staging
+// blocks of the operator product live here instead of in handle buffers. Each GPU the library
+// runs on holds its own copy of the array until the process ends. Host code must use the
+// device address taken with hipGetSymbolAddress (per device, at handle creation), never the
+// array's name, which is only a host-side stand-in.
+constexpr size_t kScratchBytes = size_t(16) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
 namespace {
 
 #define HIPCHK(x)                                  \
@@ -2265,6 +2273,32 @@ int gmres_dispatch(mbddc_ctx* c, int R, int nrhs, mbddc_info* info) {
   }
 }
 
+// ---------------------------------------------------------------------------
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxScratchDevices] = {};
+
+// Device address of `scratch` on `device` (which is current), looked up once per device.
+int scratch_init(int device) {
+  if (device < 0 || device >= kMaxScratchDevices) return MBDDC_ERR_UNSUPPORTED;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[device]) return MBDDC_OK;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !p) {
+    last_hip_error() = e;
+    return MBDDC_ERR_DEVICE;
+  }
+  g_scratch_ptr[device] = p;
+  return MBDDC_OK;
+}
+
+void* scratch_ptr(int device) {
+  if (device < 0 || device >= kMaxScratchDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return g_scratch_ptr[device];
+}
+
 double now_ms() {
   return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
@@ -2312,6 +2346,7 @@ int mbddc_create(mbddc_ctx** out, int hip_device, void* hip_stream) {
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return MBDDC_ERR_DEVICE;
   if (hip_device < 0 || hip_device >= ndev) return MBDDC_ERR_ARG;
   if (hipSetDevice(hip_device) != hipSuccess) return MBDDC_ERR_DEVICE;
+  CHK(scratch_init(hip_device));   // the no-allocation entry point's buffer on this device
   mbddc_ctx* c = new (std::nothrow) mbddc_ctx();
   if (!c) return MBDDC_ERR_OOM;
   c->device = hip_device;
@@ -2860,6 +2895,32 @@ int mbddc_matvec(mbddc_ctx* c, int nrhs, const double* x, double* y, int on_devi
   CHK(load_block(c, x, nrhs, R, on_device, c->d_X));
   CHK(spmv_dispatch(c, R, c->d_X, c->d_Y));
   return store_block(c, c->d_Y, nrhs, R, on_device, y);
+}
+
+int mbddc_matvec_noalloc(mbddc_ctx* c, int nrhs, const double* x, double* y) {
+  if (!c || !x || !y || nrhs < 1 || nrhs > kMaxRhs) return MBDDC_ERR_ARG;
+  if (c->state < 1) return MBDDC_ERR_STATE;
+  const int R = apply_R(nrhs);
+  const int64_t n = c->plan.n_dofs;
+  const size_t blk = (size_t)round_up(n * R * (int64_t)sizeof(double), 256);
+  if (2 * blk > kScratchBytes) return MBDDC_ERR_UNSUPPORTED;   // beyond the static buffer
+  if (c->state < 2) return MBDDC_ERR_STATE;
+  if (hipSetDevice(c->device) != hipSuccess) return MBDDC_ERR_DEVICE;
+  unsigned char* base = static_cast<unsigned char*>(scratch_ptr(c->device));
+  if (!base) return MBDDC_ERR_STATE;
+  double* X = reinterpret_cast<double*>(base);
+  double* Y = reinterpret_cast<double*>(base + blk);
+  // every entry of X (zeros past nrhs and on clamped DOFs) and of Y is written below, so the
+  // buffer needs no clearing between calls
+  hipLaunchKernelGGL(k_to_interleaved, dim3(nblk(n * R)), dim3(kBlock), 0, c->stream, x, nrhs, R, n, c->d_free, X);
+  if (c->nblocks > kSpmvWideRow * c->plan.n_nodes)
+    launch_spmv<64>(c, R, X, Y);
+  else
+    launch_spmv<32>(c, R, X, Y);
+  hipLaunchKernelGGL(k_from_interleaved, dim3(nblk(n * nrhs)), dim3(kBlock), 0, c->stream, Y, nrhs, R, n, y);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return MBDDC_OK;
 }
 
 int mbddc_solve(mbddc_ctx* c, int nrhs, const double* b, double* x, int on_device, mbddc_info* info) {

@@ -97,6 +97,7 @@ _SIGNATURES = {
                     ctypes.POINTER(mbddc_info)],
     "mbddc_apply": [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int],
     "mbddc_matvec": [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int],
+    "mbddc_matvec_noalloc": [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p],
     "mbddc_get_globs": [ctypes.c_void_p, _i32p, _i32p, _i32p, _i32p, _i32p],
     "mbddc_get_coarse_matrix": [ctypes.c_void_p, ctypes.c_int, _f64p, ctypes.c_int64],
     "mbddc_get_bsr": [ctypes.c_void_p, _i32p, _i32p, _f64p],
@@ -410,6 +411,13 @@ class Solver:
 
     def mbddc_matvec(self, x, out=None):
         return self._vec_call(lib().mbddc_matvec, "mbddc_matvec", x, out)
+
+    def mbddc_matvec_noalloc(self, x, out):
+        """y = K x with the library's static scratch buffer (no allocation); x and out are
+        contiguous float64 device tensors [nrhs, n_dofs] (or [n_dofs])."""
+        nrhs = 1 if x.dim() == 1 else x.shape[0]
+        _check(lib().mbddc_matvec_noalloc(self._h, nrhs, _dev_ptr(x), _dev_ptr(out)), "mbddc_matvec_noalloc")
+        return out
 
     def mbddc_solve(self, b, out=None, raise_on_noconv: bool = True):
         info = mbddc_info()
