@@ -199,6 +199,42 @@ int mbddc_get_sizes(const mbddc_ctx* ctx, mbddc_sizes* out);
  * operator and factors as they were. */
 int mbddc_set_tangent(mbddc_ctx* ctx, const double* elem_K, int on_device);
 
+/* Hyperelastic materials of the element kernels (§2): per instance, the strain energy whose
+ * second Piola-Kirchhoff stress S = dPsi/dE and tangent CC = d2Psi/dE2 define the element
+ * tangents. p[] holds: MBDDC_MAT_SVK (Saint Venant-Kirchhoff, Psi = lambda/2 (tr E)^2 + mu E:E,
+ * the linear-elastic law written on E): lambda, mu. MBDDC_MAT_NEO_HOOKEAN (compressible,
+ * Psi = mu/2 (I1 - 3) - mu ln J + lambda/2 (ln J)^2): mu, lambda. MBDDC_MAT_GUCCIONE (§2,
+ * transversely isotropic exponential law Psi = C/2 (e^Q - 1) + B/2 (J - 1) ln J with
+ * Q = b_f E_ff^2 + b_t (E_ss^2 + E_nn^2 + 2 E_sn^2) + b_fs (2 E_fs^2 + 2 E_fn^2) in the fibre
+ * frame (f, s, n)): C, b_f, b_t, b_fs, B. */
+enum { MBDDC_MAT_SVK = 1, MBDDC_MAT_NEO_HOOKEAN = 2, MBDDC_MAT_GUCCIONE = 3 };
+typedef struct {
+  int32_t kind;
+  double p[5];
+} mbddc_material;
+
+/* Sets the material of every instance (mats[n_instances]) for the element kernels. Needs the
+ * node coordinates of every mesh (mbddc_mesh.coords at setup; MBDDC_ERR_ARG otherwise).
+ * frames: [n_elems][3][3] row-major, rows the fibre, sheet and sheet-normal unit vectors of each
+ * element (all instances concatenated; read for Guccione instances, which require it), or NULL
+ * when no instance is Guccione. Copies everything to the device; state >= setup. */
+int mbddc_set_material(mbddc_ctx* ctx, const mbddc_material* mats, const double* frames);
+
+/* The Newton tangent at displacement u (full DOF vector [n_dofs], host or device per
+ * on_device), computed on the device (§2 "tangent problem"): for every element and Gauss point
+ * of the tensor rule with p+1 points per direction on the reference cube, F = I + grad u,
+ * K_e = sum_q w |J| grad N^T A grad N with A_iJkL = delta_ik S_JL + F_iI F_kK CC_IJKL; then the
+ * operator is assembled as by mbddc_set_tangent (factors of an earlier factor call are kept).
+ * With f_int != NULL the internal forces f_int = sum_e int P : grad N (P = F S; [n_dofs], 0 on
+ * clamped DOFs; host or device per f_on_device) are written too. MBDDC_ERR_ARG on a
+ * non-positive Jacobian (of the element map, or J = det F for the logarithmic laws) or a
+ * non-finite value: the operator and factors are then left as they were, and a new tangent
+ * must be set before the next mbddc_factor. Needs mbddc_set_material (MBDDC_ERR_STATE). */
+int mbddc_set_displacement(mbddc_ctx* ctx, const double* u, int on_device, double* f_int, int f_on_device);
+
+/* Copies the element matrices of the current operator ([n_elems][3npe][3npe], host or device). */
+int mbddc_get_element_tangents(const mbddc_ctx* ctx, double* elem_K, int on_device);
+
 /* Numeric BDDC setup (§3.2): local interior and constrained-Neumann problems,
  * coarse basis Phi, coarse matrix S_PiPi and its FP64 factorisation. With
  * levels = 3 S_PiPi is not factorised: the level-2 BDDC setup on the coarse
@@ -332,11 +368,22 @@ typedef struct {
   mbddc_mesh mesh;               /* the mesh arrays are copied at submit */
   mbddc_options opt;
   int32_t n_steps;               /* Newton steps, 1..16 */
-  int32_t nrhs;                  /* right-hand sides per step, 1..8 */
+  int32_t nrhs;                  /* right-hand sides per step, 1..8 (1 for on-device Newton) */
   int32_t lagged;                /* 1: factor at step 0 only; 0: factor at every step */
-  const double* elem_K;          /* [n_steps][n_elems][3npe][3npe] host; read while the request runs */
-  const double* rhs;             /* [n_steps][nrhs][n_dofs] host; read while the request runs */
-  double* x;                     /* [n_steps][nrhs][n_dofs] host output, written while the request runs */
+  const double* elem_K;          /* [n_steps][n_elems][3npe][3npe] host; read while the request runs;
+                                    NULL: on-device Newton (below) */
+  const double* rhs;             /* [n_steps][nrhs][n_dofs] host; read while the request runs (unused
+                                    by on-device Newton) */
+  double* x;                     /* [n_steps][nrhs][n_dofs] host output, written while the request runs
+                                    (on-device Newton: the iterates u_1 .. u_n_steps) */
+  /* On-device Newton (elem_K == NULL; the mesh must carry coordinates): step k computes the
+     tangent K(u_k) and the internal forces f_int(u_k) with the element kernels
+     (mbddc_set_displacement), solves K(u_k) du = f_ext - f_int(u_k) and sets u_{k+1} = u_k + du.
+     All host arrays, read while the request runs. */
+  const mbddc_material* material; /* [1] */
+  const double* frames;          /* [n_elems][9] for a Guccione material, else NULL */
+  const double* u0;              /* [n_dofs] initial displacement */
+  const double* f_ext;           /* [n_dofs] external load */
 } mbddc_request;
 
 typedef struct {
@@ -344,6 +391,7 @@ typedef struct {
   int32_t n_steps;
   int32_t iterations[16];        /* GMRES iterations per step (max over its right-hand sides) */
   double rel_res_true;           /* max over steps and right-hand sides (FP64 true residual) */
+  double newton_res[16];         /* on-device Newton: ||f_ext - f_int(u_k)||_2 on the free DOFs per step */
   double t_submit_ms, t_admit_ms, t_done_ms;   /* server clock (ms since mbddc_server_create) */
   size_t footprint;              /* admitted device bytes (estimate) */
 } mbddc_request_result;

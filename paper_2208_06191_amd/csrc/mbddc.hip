@@ -33,6 +33,7 @@
 #include "kernels.hpp"
 #include "kernels_setup.inc"
 #include "kernels_apply.inc"
+#include "kernels_element.inc"
 
 using namespace mbddc;
 
@@ -73,14 +74,14 @@ enum Family {
   F_ASSEMBLE_BSR, F_ASSEMBLE_LOCAL, F_GJ_KII, F_GEMM_GH, F_GEMM_S, F_CONSTRAINTS, F_GJ_P, F_EXTRACT,
   F_COARSE_ASSEMBLE, F_COARSE_GJ_SMALL, F_COARSE_DIAG, F_COARSE_PREP, F_COARSE_GEMM, F_COARSE_ROWS,
   F_APPLY_A, F_APPLY_C, F_APPLY_E, F_APPLY_F, F_APPLY_H, F_SPMV, F_KRYLOV_DOTS, F_KRYLOV_UPDATE,
-  F_KRYLOV_SMALL, F_KRYLOV_VEC, F_LEVEL2_SETUP, F_LEVEL2_APPLY, F_APPLY_WHOLE, F_COUNT
+  F_KRYLOV_SMALL, F_KRYLOV_VEC, F_LEVEL2_SETUP, F_LEVEL2_APPLY, F_APPLY_WHOLE, F_ELEMENT, F_COUNT
 };
 const char* const kFamilyName[F_COUNT] = {
   "assemble_bsr", "assemble_local", "gj_interior", "gemm_condense", "gemm_schur", "constraints", "gj_interface",
   "extract_operators", "coarse_assemble", "coarse_gj_small", "coarse_gj_diag", "coarse_gj_prep", "coarse_gj_gemm",
   "coarse_gj_rows", "apply_A_interior", "apply_C_interface", "apply_E_coarse", "apply_F_coarse_ext",
   "apply_H_average", "spmv_bsr", "krylov_dots", "krylov_update", "krylov_small", "krylov_vectors",
-  "level2_setup", "apply_E_level2", "apply_whole"};
+  "level2_setup", "apply_E_level2", "apply_whole", "element_tangents"};
 
 struct Profiler {
   uint32_t mask = 0;
@@ -368,6 +369,24 @@ struct mbddc_ctx {
   std::vector<int32_t> l2_eidx;     // [n_cslots] level-2 element-local DOF of each coarse slot
   int32_t* d_l2_eidx = nullptr;
   int32_t* d_l2_inv = nullptr;      // [child n_dofs] coarse DOF of each level-2 DOF, or -1
+  // element kernels (mbddc_set_material / mbddc_set_displacement)
+  std::vector<double> h_coords;     // [n_nodes*3] all instances, empty if some mesh came without
+  bool have_material = false;
+  bool ke_valid = false;            // d_Ke holds the element matrices of the current operator
+  std::vector<int32_t> el_list[2];  // elements of order 1 / 2
+  double* d_coords = nullptr;
+  double* d_u = nullptr;
+  double* d_frames = nullptr;
+  double* d_fe = nullptr;
+  double* d_fint = nullptr;
+  int32_t* d_elem_nodes = nullptr;
+  int64_t* d_elem_node_off = nullptr;
+  int32_t* d_elem_mat = nullptr;
+  MatDev* d_mats = nullptr;
+  int32_t* d_el_list[2] = {nullptr, nullptr};
+  int64_t* d_fe_off = nullptr;
+  int32_t* d_ne_ptr = nullptr;
+  int64_t* d_ne_ent = nullptr;
 };
 
 namespace {
@@ -564,6 +583,10 @@ void clear_pointers(mbddc_ctx* c) {
   for (SymSet* S : {&c->set_kii, &c->set_x, &c->set_t}) {
     cl(S->d_all); cl(S->d_big); cl(S->d_items); cl(S->d_gd); cl(S->d_gitems);
   }
+  cl(c->d_coords); cl(c->d_u); cl(c->d_frames); cl(c->d_fe); cl(c->d_fint); cl(c->d_elem_nodes);
+  cl(c->d_elem_node_off); cl(c->d_elem_mat); cl(c->d_mats); cl(c->d_el_list[0]); cl(c->d_el_list[1]);
+  cl(c->d_fe_off); cl(c->d_ne_ptr); cl(c->d_ne_ent);
+  c->have_material = false;
 }
 
 void free_all(mbddc_ctx* c) {
@@ -2299,6 +2322,65 @@ void* scratch_ptr(int device) {
   return g_scratch_ptr[device];
 }
 
+// 1D tables of the Lagrange basis of order p (equispaced nodes on [0,1]) at the p+1 point
+// Gauss-Legendre rule on [0,1].
+ElemTables elem_tables(int order) {
+  ElemTables t{};
+  const int n = order + 1;
+  double g[3], w[3];
+  if (order == 1) {
+    const double h = 0.5 / std::sqrt(3.0);
+    g[0] = 0.5 - h; g[1] = 0.5 + h; w[0] = w[1] = 0.5;
+  } else {
+    const double h = 0.5 * std::sqrt(0.6);
+    g[0] = 0.5 - h; g[1] = 0.5; g[2] = 0.5 + h;
+    w[0] = w[2] = 5.0 / 18.0; w[1] = 8.0 / 18.0;
+  }
+  for (int q = 0; q < n; ++q) {
+    const double x = g[q];
+    t.w1[q] = w[q];
+    if (order == 1) {
+      t.N1[q][0] = 1.0 - x; t.N1[q][1] = x;
+      t.D1[q][0] = -1.0; t.D1[q][1] = 1.0;
+    } else {
+      t.N1[q][0] = 2.0 * (x - 0.5) * (x - 1.0); t.N1[q][1] = -4.0 * x * (x - 1.0); t.N1[q][2] = 2.0 * x * (x - 0.5);
+      t.D1[q][0] = 4.0 * x - 3.0; t.D1[q][1] = -8.0 * x + 4.0; t.D1[q][2] = 4.0 * x - 1.0;
+    }
+  }
+  return t;
+}
+
+// Element tangents (and element forces when fe) at the displacement in d_u, into d_Ke.
+int launch_elements(mbddc_ctx* c, bool forces) {
+  ElemArgs g{};
+  g.coords = c->d_coords; g.u = c->d_u; g.elem_nodes = c->d_elem_nodes; g.node_off = c->d_elem_node_off;
+  g.ke_off = c->d_ke_off; g.elem_mat = c->d_elem_mat; g.mats = c->d_mats; g.frames = c->d_frames;
+  g.Ke = c->d_Ke; g.fe = forces ? c->d_fe : nullptr; g.fe_off = c->d_fe_off; g.flag = c->d_flag;
+  for (int o = 0; o < 2; ++o) {
+    if (c->el_list[o].empty()) continue;
+    g.elems = c->d_el_list[o];
+    g.n = (int64_t)c->el_list[o].size();
+    const ElemTables tab = elem_tables(o + 1);
+    ProfScope ps(c, F_ELEMENT, 8.0 * (c->plan.ke_total), 0.0);
+    if (o == 0) hipLaunchKernelGGL((k_element<2>), dim3((unsigned)g.n), dim3(kBlock), 0, c->stream, g, tab);
+    else hipLaunchKernelGGL((k_element<3>), dim3((unsigned)g.n), dim3(kBlock), 0, c->stream, g, tab);
+  }
+  HIPCHK(hipGetLastError());
+  return MBDDC_OK;
+}
+
+// The assembled operator from the element matrices in d_Ke.
+int assemble_operator(mbddc_ctx* c) {
+  {
+    ProfScope ps(c, F_ASSEMBLE_BSR, c->op_bytes[F_ASSEMBLE_BSR], 0.0);
+    hipLaunchKernelGGL(k_assemble_bsr, dim3(nblk(c->nblocks * 9)), dim3(kBlock), 0, c->stream, c->d_Ke, c->d_bsr_rowptr,
+                       c->d_bsr_rownode, c->d_bsr_col, c->d_bsr_cptr, c->d_bsr_contrib, c->d_bsr_kstride, c->d_free,
+                       c->nblocks, c->d_vals);
+  }
+  HIPCHK(hipGetLastError());
+  return MBDDC_OK;
+}
+
 double now_ms() {
   return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
@@ -2405,6 +2487,11 @@ int parse_meshes(int n_inst, const mbddc_mesh* meshes, const mbddc_options* opt,
     mi.elem_part.assign(m.elem_part, m.elem_part + m.n_elems);
     if (m.node_tags) mi.node_tags.assign(m.node_tags, m.node_tags + m.n_nodes);
     if (m.n_dirichlet > 0) mi.dirichlet.assign(m.dirichlet_dofs, m.dirichlet_dofs + m.n_dirichlet);
+    if (m.coords) {
+      for (int64_t k = 0; k < 3LL * m.n_nodes; ++k)
+        if (!std::isfinite(m.coords[k])) return MBDDC_ERR_ARG;
+      mi.coords.assign(m.coords, m.coords + 3LL * m.n_nodes);
+    }
   }
   return MBDDC_OK;
 }
@@ -2476,6 +2563,11 @@ int prepare_host(mbddc_ctx* c, const mbddc_options& o, const std::vector<MeshIn>
   c->sym = (o.symmetric_hint != 0);
   std::string err = build_plan(ms, o.primal, c->plan);
   if (!err.empty()) return MBDDC_ERR_ARG;
+  c->h_coords.clear();
+  bool all_coords = true;
+  for (const MeshIn& m : ms) all_coords &= !m.coords.empty();
+  if (all_coords)
+    for (const MeshIn& m : ms) c->h_coords.insert(c->h_coords.end(), m.coords.begin(), m.coords.end());
   CHK(build_layout(c));
   if (o.levels == 3) CHK(build_level2_host(c, ms));
   return MBDDC_OK;
@@ -2801,7 +2893,11 @@ int mbddc_set_tangent(mbddc_ctx* c, const double* elem_K, int on_device) {
   HIPCHK(hipGetLastError());
   HIPCHK(hipMemcpyAsync(c->h_flag, c->d_flag, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
-  if (*c->h_flag) return MBDDC_ERR_ARG;
+  if (*c->h_flag) {   // operator and factors untouched; the element matrices must be set again
+    c->ke_valid = false;
+    return MBDDC_ERR_ARG;
+  }
+  c->ke_valid = true;
   {
     ProfScope ps(c, F_ASSEMBLE_BSR, c->op_bytes[F_ASSEMBLE_BSR], 0.0);
     hipLaunchKernelGGL(k_assemble_bsr, dim3(nblk(c->nblocks * 9)), dim3(kBlock), 0, c->stream, c->d_Ke, c->d_bsr_rowptr,
@@ -2814,9 +2910,115 @@ int mbddc_set_tangent(mbddc_ctx* c, const double* elem_K, int on_device) {
   return MBDDC_OK;
 }
 
+int mbddc_set_material(mbddc_ctx* c, const mbddc_material* mats, const double* frames) {
+  if (!c || !mats) return MBDDC_ERR_ARG;
+  if (c->state < 1) return MBDDC_ERR_STATE;
+  if (hipSetDevice(c->device) != hipSuccess) return MBDDC_ERR_DEVICE;
+  const Plan& P = c->plan;
+  if ((int64_t)c->h_coords.size() != 3 * P.n_nodes) return MBDDC_ERR_ARG;   // meshes came without coordinates
+  std::vector<MatDev> md(P.n_inst);
+  bool guccione = false;
+  for (int i = 0; i < P.n_inst; ++i) {
+    const mbddc_material& m = mats[i];
+    if (m.kind != MBDDC_MAT_SVK && m.kind != MBDDC_MAT_NEO_HOOKEAN && m.kind != MBDDC_MAT_GUCCIONE) return MBDDC_ERR_ARG;
+    md[i].kind = m.kind;
+    for (int k = 0; k < 5; ++k) {
+      if (!std::isfinite(m.p[k])) return MBDDC_ERR_ARG;
+      md[i].p[k] = m.p[k];
+    }
+    guccione |= m.kind == MBDDC_MAT_GUCCIONE;
+  }
+  if (guccione && !frames) return MBDDC_ERR_ARG;
+  std::vector<int32_t> elem_mat(P.n_elems);
+  for (int i = 0; i < P.n_inst; ++i)
+    for (int32_t e = 0; e < P.inst[i].n_elems; ++e) elem_mat[P.inst[i].elem_off + e] = i;
+  for (int o = 0; o < 2; ++o) c->el_list[o].clear();
+  std::vector<int64_t> fe_off(P.n_elems + 1, 0);
+  for (int64_t e = 0; e < P.n_elems; ++e) {
+    const int npe = P.elem_npe[e];
+    if (npe != 8 && npe != 27) return MBDDC_ERR_UNSUPPORTED;
+    c->el_list[npe == 8 ? 0 : 1].push_back((int32_t)e);
+    fe_off[e + 1] = fe_off[e] + 3 * npe;
+  }
+  // node -> (element force entry) in ascending element order: the fixed order of the force gather
+  std::vector<int32_t> ne_ptr(P.n_nodes + 1, 0);
+  for (int64_t e = 0; e < P.n_elems; ++e)
+    for (int a = 0; a < P.elem_npe[e]; ++a) ne_ptr[P.elem_nodes_flat[P.elem_node_off[e] + a] + 1]++;
+  for (int64_t n = 0; n < P.n_nodes; ++n) ne_ptr[n + 1] += ne_ptr[n];
+  std::vector<int64_t> ne_ent(ne_ptr[P.n_nodes]);
+  std::vector<int32_t> fill(ne_ptr.begin(), ne_ptr.end() - 1);
+  for (int64_t e = 0; e < P.n_elems; ++e)
+    for (int a = 0; a < P.elem_npe[e]; ++a) ne_ent[fill[P.elem_nodes_flat[P.elem_node_off[e] + a]]++] = fe_off[e] + 3 * a;
+  for (auto* p : {&c->d_coords, &c->d_u, &c->d_frames, &c->d_fe, &c->d_fint}) dfree(c, *p);
+  dfree(c, c->d_elem_nodes); dfree(c, c->d_elem_node_off); dfree(c, c->d_elem_mat); dfree(c, c->d_mats);
+  dfree(c, c->d_el_list[0]); dfree(c, c->d_el_list[1]); dfree(c, c->d_fe_off); dfree(c, c->d_ne_ptr);
+  dfree(c, c->d_ne_ent);
+  c->have_material = false;
+  CHK(upload(c, &c->d_coords, c->h_coords));
+  CHK(dalloc(c, &c->d_u, P.n_dofs));
+  CHK(dalloc(c, &c->d_fe, fe_off[P.n_elems]));
+  CHK(dalloc(c, &c->d_fint, P.n_dofs));
+  CHK(upload(c, &c->d_elem_nodes, P.elem_nodes_flat));
+  CHK(upload(c, &c->d_elem_node_off, P.elem_node_off));
+  CHK(upload(c, &c->d_elem_mat, elem_mat));
+  CHK(upload(c, &c->d_mats, md));
+  for (int o = 0; o < 2; ++o) CHK(upload(c, &c->d_el_list[o], c->el_list[o]));
+  CHK(upload(c, &c->d_fe_off, fe_off));
+  CHK(upload(c, &c->d_ne_ptr, ne_ptr));
+  CHK(upload(c, &c->d_ne_ent, ne_ent));
+  if (guccione) {
+    std::vector<double> fr(frames, frames + 9 * P.n_elems);
+    for (double v : fr)
+      if (!std::isfinite(v)) return MBDDC_ERR_ARG;
+    CHK(upload(c, &c->d_frames, fr));
+  }
+  HIPCHK(hipStreamSynchronize(c->stream));
+  c->have_material = true;
+  return MBDDC_OK;
+}
+
+int mbddc_set_displacement(mbddc_ctx* c, const double* u, int on_device, double* f_int, int f_on_device) {
+  if (!c || !u) return MBDDC_ERR_ARG;
+  if (c->state < 1 || !c->have_material) return MBDDC_ERR_STATE;
+  if (hipSetDevice(c->device) != hipSuccess) return MBDDC_ERR_DEVICE;
+  const Plan& P = c->plan;
+  HIPCHK(hipMemcpyAsync(c->d_u, u, P.n_dofs * sizeof(double), on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                        c->stream));
+  HIPCHK(hipMemsetAsync(c->d_flag, 0, sizeof(int32_t), c->stream));
+  CHK(launch_elements(c, f_int != nullptr));
+  HIPCHK(hipMemcpyAsync(c->h_flag, c->d_flag, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  if (*c->h_flag) {   // the element matrices are invalid: the operator and factors stay as they were
+    c->ke_valid = false;
+    return MBDDC_ERR_ARG;
+  }
+  CHK(assemble_operator(c));
+  c->ke_valid = true;
+  if (f_int) {
+    hipLaunchKernelGGL(k_gather_forces, dim3(nblk(3 * P.n_nodes)), dim3(kBlock), 0, c->stream, c->d_ne_ptr, c->d_ne_ent,
+                       c->d_fe, c->d_free, P.n_nodes, c->d_fint);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(f_int, c->d_fint, P.n_dofs * sizeof(double),
+                          f_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream));
+  }
+  HIPCHK(hipStreamSynchronize(c->stream));
+  c->state = std::max(c->state, 2);
+  return MBDDC_OK;
+}
+
+int mbddc_get_element_tangents(const mbddc_ctx* c, double* Ke, int on_device) {
+  if (!c || !Ke) return MBDDC_ERR_ARG;
+  if (c->state < 2) return MBDDC_ERR_STATE;
+  if (hipSetDevice(c->device) != hipSuccess) return MBDDC_ERR_DEVICE;
+  HIPCHK(hipMemcpyAsync(Ke, c->d_Ke, c->plan.ke_total * sizeof(double),
+                        on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return MBDDC_OK;
+}
+
 int mbddc_factor(mbddc_ctx* c) {
   if (!c) return MBDDC_ERR_ARG;
-  if (c->state < 2) return MBDDC_ERR_STATE;
+  if (c->state < 2 || !c->ke_valid) return MBDDC_ERR_STATE;
   if (hipSetDevice(c->device) != hipSuccess) return MBDDC_ERR_DEVICE;
   int st = factor_dispatch(c);
   if (st != MBDDC_OK) {

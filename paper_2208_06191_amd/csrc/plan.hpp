@@ -26,6 +26,7 @@ struct MeshIn {
   std::vector<int32_t> elem_part;
   std::vector<uint32_t> node_tags;
   std::vector<int32_t> dirichlet;
+  std::vector<double> coords;     // optional [n_nodes*3] (element kernels on the device)
 };
 
 // One subdomain's layout. Local DOFs are ordered interior first then interface,

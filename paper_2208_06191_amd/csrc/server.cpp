@@ -10,6 +10,7 @@
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
+#include <cmath>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -37,6 +38,10 @@ struct Job {
   const double* K = nullptr;
   const double* rhs = nullptr;
   double* x = nullptr;
+  mbddc_material material{};         // on-device Newton (K == nullptr)
+  const double* frames = nullptr;
+  const double* u0 = nullptr;
+  const double* f_ext = nullptr;
   size_t footprint = 0;
   bool done = false;
   mbddc_request_result res{};
@@ -137,9 +142,45 @@ struct mbddc_server {
 
 namespace {
 
+// Newton iteration with the tangents and internal forces computed on the device.
+int run_newton(Job* j, mbddc_ctx* h) {
+  mbddc_request_result& r = j->res;
+  int st = mbddc_set_material(h, &j->material, j->frames);
+  const int64_t n = j->n_dofs;
+  std::vector<double> u(j->u0, j->u0 + n), f(n), b(n), du(n);
+  std::vector<uint8_t> clamped(n, 0);
+  for (int32_t d : j->dirichlet) clamped[d] = 1;
+  for (int k = 0; !st && k < j->n_steps; ++k) {
+    st = mbddc_set_displacement(h, u.data(), 0, f.data(), 0);
+    if (!st && (k == 0 || !j->lagged)) st = mbddc_factor(h);
+    if (st) break;
+    double nr = 0.0;
+    for (int64_t d = 0; d < n; ++d) {
+      b[d] = clamped[d] ? 0.0 : j->f_ext[d] - f[d];
+      nr += b[d] * b[d];
+    }
+    r.newton_res[k] = std::sqrt(nr);
+    mbddc_info info{};
+    st = mbddc_solve(h, 1, b.data(), du.data(), 0, &info);
+    r.iterations[k] = info.iterations;
+    r.rel_res_true = std::max(r.rel_res_true, info.rel_res_true);
+    for (int64_t d = 0; d < n; ++d) u[d] += du[d];
+    std::copy(u.begin(), u.end(), j->x + (int64_t)k * n);
+    r.n_steps = k + 1;
+  }
+  return st;
+}
+
 void run_job(mbddc_server* s, Job* j, mbddc_ctx* h) {
   mbddc_request_result& r = j->res;
   int st = mbddc_setup_symbolic(h, &j->mesh, &j->opt);
+  if (!st && !j->K) {
+    st = run_newton(j, h);
+    r.status = st;
+    const int st2 = mbddc_release(h);
+    if (r.status == MBDDC_OK) r.status = st2;
+    return;
+  }
   for (int k = 0; !st && k < j->n_steps; ++k) {
     st = mbddc_set_tangent(h, j->K + (int64_t)k * j->ke_total, 0);
     if (!st && (k == 0 || !j->lagged)) st = mbddc_factor(h);
@@ -220,8 +261,10 @@ int mbddc_server_create(mbddc_server** out, int hip_device, size_t hbm_budget, i
 }
 
 int mbddc_server_submit(mbddc_server* s, const mbddc_request* q, int64_t* ticket) {
-  if (!s || !q || !ticket || q->n_steps < 1 || q->n_steps > 16 || q->nrhs < 1 || q->nrhs > 8 || !q->elem_K ||
-      !q->rhs || !q->x)
+  if (!s || !q || !ticket || q->n_steps < 1 || q->n_steps > 16 || q->nrhs < 1 || q->nrhs > 8 || !q->x)
+    return MBDDC_ERR_ARG;
+  const bool newton = !q->elem_K;
+  if (newton ? (!q->material || !q->u0 || !q->f_ext || q->nrhs != 1 || !q->mesh.coords) : !q->rhs)
     return MBDDC_ERR_ARG;
   const mbddc_mesh& m = q->mesh;
   const int npe = m.elem_type == MBDDC_HEX8 ? 8 : (m.elem_type == MBDDC_HEX27 ? 27 : 0);
@@ -255,6 +298,12 @@ int mbddc_server_submit(mbddc_server* s, const mbddc_request* q, int64_t* ticket
   j->K = q->elem_K;
   j->rhs = q->rhs;
   j->x = q->x;
+  if (newton) {
+    j->material = *q->material;
+    j->frames = q->frames;
+    j->u0 = q->u0;
+    j->f_ext = q->f_ext;
+  }
   j->footprint = fp;
   j->res.footprint = fp;
   {

@@ -24,6 +24,7 @@ MBDDC_ERR_NOCONV, MBDDC_ERR_DEVICE, MBDDC_ERR_STATE, MBDDC_ERR_UNSUPPORTED = -4,
 MBDDC_HEX8, MBDDC_HEX27 = 1, 2
 MBDDC_PRIMAL_V, MBDDC_PRIMAL_E, MBDDC_PRIMAL_F = 1, 2, 4
 MBDDC_FP64, MBDDC_MIXED, MBDDC_MIXED_F32FACT = 0, 1, 2
+MBDDC_MAT_SVK, MBDDC_MAT_NEO_HOOKEAN, MBDDC_MAT_GUCCIONE = 1, 2, 3
 
 _i32p = ctypes.POINTER(ctypes.c_int32)
 _u32p = ctypes.POINTER(ctypes.c_uint32)
@@ -52,6 +53,10 @@ class mbddc_info(ctypes.Structure):
                 ("ms_solve", ctypes.c_double), ("applies", ctypes.c_int32), ("applies_graphed", ctypes.c_int32)]
 
 
+class mbddc_material(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("p", ctypes.c_double * 5)]
+
+
 class mbddc_sizes(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in ("n_dofs", "n_free", "n_interface", "n_coarse", "n_sub",
                                                "n_instances", "n_vertices", "n_edges", "n_faces", "max_local",
@@ -65,12 +70,14 @@ class mbddc_kernel_stat(ctypes.Structure):
 
 class mbddc_request(ctypes.Structure):
     _fields_ = [("mesh", mbddc_mesh), ("opt", mbddc_options), ("n_steps", ctypes.c_int32), ("nrhs", ctypes.c_int32),
-                ("lagged", ctypes.c_int32), ("elem_K", _f64p), ("rhs", _f64p), ("x", _f64p)]
+                ("lagged", ctypes.c_int32), ("elem_K", _f64p), ("rhs", _f64p), ("x", _f64p),
+                ("material", ctypes.c_void_p), ("frames", _f64p), ("u0", _f64p), ("f_ext", _f64p)]
 
 
 class mbddc_request_result(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("n_steps", ctypes.c_int32), ("iterations", ctypes.c_int32 * 16),
-                ("rel_res_true", ctypes.c_double), ("t_submit_ms", ctypes.c_double), ("t_admit_ms", ctypes.c_double),
+                ("rel_res_true", ctypes.c_double), ("newton_res", ctypes.c_double * 16),
+                ("t_submit_ms", ctypes.c_double), ("t_admit_ms", ctypes.c_double),
                 ("t_done_ms", ctypes.c_double), ("footprint", ctypes.c_size_t)]
 
 
@@ -93,6 +100,9 @@ _SIGNATURES = {
     "mbddc_get_sizes": [ctypes.c_void_p, ctypes.POINTER(mbddc_sizes)],
     "mbddc_set_tangent": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int],
     "mbddc_factor": [ctypes.c_void_p],
+    "mbddc_set_material": [ctypes.c_void_p, ctypes.POINTER(mbddc_material), _f64p],
+    "mbddc_set_displacement": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_int],
+    "mbddc_get_element_tangents": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int],
     "mbddc_solve": [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
                     ctypes.POINTER(mbddc_info)],
     "mbddc_apply": [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int],
@@ -290,6 +300,26 @@ class Server:
         self._keep[t.value] = (mesh, K, b, x)
         return t.value
 
+    def submit_newton(self, mesh: _MeshArrays, options: mbddc_options, material, u0: np.ndarray, f_ext: np.ndarray,
+                      n_steps: int = 5, lagged: bool = True, frames=None) -> int:
+        """On-device Newton request: material (kind, params), u0 and f_ext full DOF vectors;
+        the result's x holds the iterates u_1..u_n_steps [n_steps, 1, n_dofs]."""
+        mat = mbddc_material()
+        mat.kind = material[0]
+        for j, v in enumerate(material[1]):
+            mat.p[j] = float(v)
+        u = np.ascontiguousarray(u0, dtype=np.float64).ravel()
+        f = np.ascontiguousarray(f_ext, dtype=np.float64).ravel()
+        fr = None if frames is None else np.ascontiguousarray(frames, dtype=np.float64)
+        x = np.zeros((n_steps, 1, u.size))
+        q = mbddc_request(mesh.mesh, options, n_steps, 1, 1 if lagged else 0, None, None, _ptr(x, ctypes.c_double),
+                          ctypes.cast(ctypes.pointer(mat), ctypes.c_void_p), _ptr(fr, ctypes.c_double),
+                          _ptr(u, ctypes.c_double), _ptr(f, ctypes.c_double))
+        t = ctypes.c_int64()
+        _check(lib().mbddc_server_submit(self._s, ctypes.byref(q), ctypes.byref(t)), "mbddc_server_submit")
+        self._keep[t.value] = (mesh, (mat, u, f, fr), None, x)
+        return t.value
+
     def wait(self, ticket: int):
         """(result, x [n_steps, nrhs, n_dofs]) of a submitted request."""
         r = mbddc_request_result()
@@ -389,6 +419,47 @@ class Solver:
 
     def mbddc_factor(self):
         _check(lib().mbddc_factor(self._h), "mbddc_factor")
+
+    # -- element kernels ---------------------------------------------------------
+    def mbddc_set_material(self, materials, frames=None):
+        """materials: one (kind, params) per instance, params as in mbddc.h; frames [n_elems, 3, 3]
+        (rows f, s, n) for Guccione instances."""
+        arr = (mbddc_material * len(materials))()
+        for k, (kind, params) in enumerate(materials):
+            arr[k].kind = kind
+            for j, v in enumerate(params):
+                arr[k].p[j] = float(v)
+        fr = None if frames is None else np.ascontiguousarray(frames, dtype=np.float64)
+        _check(lib().mbddc_set_material(self._h, arr, _ptr(fr, ctypes.c_double)), "mbddc_set_material")
+        self._frames = fr
+
+    def mbddc_set_displacement(self, u, f_int: bool = False):
+        """Device element tangents at u (full DOF vector, numpy or a device tensor); returns the
+        internal forces (same kind of array as u) when f_int, else None."""
+        if isinstance(u, np.ndarray):
+            u2 = np.ascontiguousarray(u, dtype=np.float64).ravel()
+            f = np.empty_like(u2) if f_int else None
+            _check(lib().mbddc_set_displacement(self._h, u2.ctypes.data_as(ctypes.c_void_p), 0,
+                                                None if f is None else f.ctypes.data_as(ctypes.c_void_p), 0),
+                   "mbddc_set_displacement")
+            return f
+        f = u.new_empty(u.shape) if f_int else None
+        _check(lib().mbddc_set_displacement(self._h, _dev_ptr(u), 1, None if f is None else _dev_ptr(f), 1),
+               "mbddc_set_displacement")
+        return f
+
+    def mbddc_get_element_tangents(self, out=None):
+        """The element matrices of the current operator (numpy [ke_total], or into a device tensor)."""
+        if out is None:
+            sz = self.sizes()
+            n = sum(int(m.mesh.n_elems) * (3 * (8 if m.mesh.elem_type == MBDDC_HEX8 else 27)) ** 2
+                    for m in self._meshes)
+            o = np.empty(n)
+            _check(lib().mbddc_get_element_tangents(self._h, o.ctypes.data_as(ctypes.c_void_p), 0),
+                   "mbddc_get_element_tangents")
+            return o
+        _check(lib().mbddc_get_element_tangents(self._h, _dev_ptr(out), 1), "mbddc_get_element_tangents")
+        return out
 
     def last_bad_subdomain(self) -> int:
         return lib().mbddc_last_bad_subdomain(self._h)

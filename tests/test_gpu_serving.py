@@ -185,3 +185,39 @@ def test_warm_server_makes_no_device_allocations():
     for k, (r, x) in enumerate(again):
         assert r.status == 0
         assert np.array_equal(x, first[k // 2])
+
+
+@pytest.mark.parametrize("lagged", [True, False])
+def test_newton_request_on_device_equals_direct_handle(lagged):
+    """A request that carries the material, u0 and f_ext instead of element tangents: the server
+    runs Newton with the device element kernels, bitwise as a handle driven step by step."""
+    mesh = W.box_mesh(8, 8, 8, 1)
+    part, nsub = W.block_partition(mesh, 4)
+    dirichlet = W.clamp_dofs(mesh, 1)
+    fext = 0.05 * W._loads(mesh, dirichlet, 1, 3)[0]
+    mat = (mbddc.MBDDC_MAT_NEO_HOOKEAN, (1.0, 50.0 - 2.0 / 3.0))
+    m = mbddc._MeshArrays(mesh.coords, mesh.elem_nodes, mesh.elem_type, part, nsub, mesh.node_tags, dirichlet)
+    s = mbddc.Solver(0)
+    s.mbddc_setup_symbolic([m], options(3))
+    s.mbddc_set_material([mat])
+    u = np.zeros(3 * mesh.n_nodes)
+    xs, res = [], []
+    for k in range(4):
+        f = s.mbddc_set_displacement(u, f_int=True)
+        if k == 0 or not lagged:
+            s.mbddc_factor()
+        b = fext - f
+        b[dirichlet] = 0.0
+        res.append(np.linalg.norm(b))
+        du, _ = s.mbddc_solve(b)
+        u = u + du
+        xs.append(u.copy())
+    s.close()
+    srv = mbddc.Server(0, 8 << 30, 2)
+    t = srv.submit_newton(m, options(3), mat, np.zeros(3 * mesh.n_nodes), fext, n_steps=4, lagged=lagged)
+    r, x = srv.wait(t)
+    srv.close()
+    assert r.status == 0 and r.n_steps == 4
+    assert np.array_equal(x[:, 0, :], np.stack(xs))
+    assert np.allclose(list(r.newton_res[:4]), res, rtol=1e-12, atol=0.0)   # summation order differs
+    assert res[3] < 1e-3 * res[0]
