@@ -14,7 +14,13 @@ Follows paper §3.2 ("BDDC preconditioner"):
   minimum-energy extension of the primal constraints (the columns of the
   coarse basis) and S_PiPi = sum_i R_Pi^T Phi_i^T A^(i) Phi_i R_Pi;
 * multilevel BDDC: the coarse problem is itself approximated by one BDDC
-  application (§3.2 last paragraph; §7, coarse problem on a group of 8).
+  application (§3.2 last paragraph; §7, coarse problem on a group of 8);
+* the non-symmetric formulation (§8, realistic simulation: the base pressure
+  breaks the symmetry of the tangent and BDDC is told to use its non-symmetric
+  form): a left coarse basis Psi from the transposed constrained problems
+  N_i^T [Psi_i; Lambda'_i] = [0; I], coarse matrix S_PiPi = sum Psi^T A Phi and
+  coarse right-hand side Psi^T R_D r, so that the preconditioner of A^T is the
+  transpose of the preconditioner of A.
 
 The primal constraints are enforced with Lagrange multipliers in the local
 problems (the constrained Neumann matrices N_i = [A^(i) C_i^T; C_i 0]); for
@@ -192,7 +198,7 @@ class Level:
     coarse solve (multilevel BDDC)."""
 
     def __init__(self, A, spaces: list, Ks: list, n_coarse: int,
-                 coarse_solver: Optional[Callable] = None, build_coarse: bool = True):
+                 coarse_solver: Optional[Callable] = None, build_coarse: bool = True, nonsymmetric: bool = False):
         self.A = A
         self.spaces = spaces
         self.n = A.shape[0]
@@ -211,9 +217,11 @@ class Level:
             rhs[ni:, :] = np.eye(nc)
             sol = sla.lu_solve(N_lu, rhs)                      # N_i [Phi_i; Lambda_i] = [0; I]
             Phi, Lam = sol[:ni], sol[ni:]
-            Kci = Phi.T @ Ki @ Phi                              # Phi_i^T A^(i) Phi_i
+            # left basis: N_i^T [Psi_i; Lambda'_i] = [0; I] (non-symmetric form), else Psi = Phi
+            Psi = sla.lu_solve(N_lu, rhs, trans=1)[:ni] if nonsymmetric else Phi
+            Kci = Psi.T @ Ki @ Phi                              # Psi_i^T A^(i) Phi_i
             Kc[np.ix_(sp_.coarse, sp_.coarse)] += Kci
-            self.loc.append(dict(K=Ki, KII_lu=KII_lu, N_lu=N_lu, Phi=Phi, Lam=Lam, Kc=Kci))
+            self.loc.append(dict(K=Ki, KII_lu=KII_lu, N_lu=N_lu, Phi=Phi, Psi=Psi, Lam=Lam, Kc=Kci))
             interior.append(sp_.dofs[:nI])
         self.Kc = Kc
         self.coarse_solver = coarse_solver
@@ -253,7 +261,7 @@ class Level:
             ri[nI:] = sp_.weights * r[sp_.dofs[nI:]]              # R_D restriction
             sol = sla.lu_solve(L["N_lu"], np.concatenate([ri, np.zeros(nc)]))
             ws.append(sol[:ni])                                   # constrained local solve
-            gc[sp_.coarse] += L["Phi"].T @ ri                     # Phi^T R_D r
+            gc[sp_.coarse] += L["Psi"].T @ ri                     # Psi^T R_D r (Psi = Phi: symmetric form)
         uc = self.coarse_solve(gc) if self.n_coarse else gc
         z = np.zeros(self.n)
         for sp_, L, w in zip(self.spaces, self.loc, ws):
@@ -289,18 +297,18 @@ class BDDC:
     """Two-level (``levels=2``) or three-level (``levels=3``) BDDC on the free-DOF operator."""
 
     def __init__(self, dec: Decomposition, elem_nodes, Ke, levels: int = 2, coarse_group: int = 8,
-                 level2_primal: int = VERTEX | EDGE | FACE):
+                 level2_primal: int = VERTEX | EDGE | FACE, nonsymmetric: bool = False):
         self.dec = dec
         K = fem.assemble(elem_nodes, Ke, dec.n_dofs)
         self.A = fem.reduce_to_free(K, dec.free)
         Ks = local_matrices(dec, elem_nodes, Ke)
         self.levels = levels
         if levels == 2:
-            self.L1 = Level(self.A, dec.subdomains, Ks, dec.n_coarse)
+            self.L1 = Level(self.A, dec.subdomains, Ks, dec.n_coarse, nonsymmetric=nonsymmetric)
             self.L2 = None
         elif levels == 3:
-            self.L1 = Level(self.A, dec.subdomains, Ks, dec.n_coarse, build_coarse=False)
-            self.L2 = coarse_level(dec, self.L1, coarse_group, level2_primal)
+            self.L1 = Level(self.A, dec.subdomains, Ks, dec.n_coarse, build_coarse=False, nonsymmetric=nonsymmetric)
+            self.L2 = coarse_level(dec, self.L1, coarse_group, level2_primal, nonsymmetric)
             self.L1.coarse_solver = self.L2.apply
         else:
             raise ValueError("levels must be 2 or 3")
@@ -310,8 +318,8 @@ class BDDC:
         return self.L1.apply(r_free)
 
 
-def coarse_level(dec: Decomposition, L1: Level, group: int, primal: int) -> Level:
-    """Level-2 BDDC on S_PiPi: fine subdomains are its elements (matrices Phi_i^T A^(i) Phi_i),
+def coarse_level(dec: Decomposition, L1: Level, group: int, primal: int, nonsymmetric: bool = False) -> Level:
+    """Level-2 BDDC on S_PiPi: fine subdomains are its elements (matrices Psi_i^T A^(i) Phi_i),
     fine primal globs its nodes, level-2 subdomain of fine subdomain i is i // group."""
     nsub = dec.n_sub
     part2 = np.arange(nsub) // group
@@ -368,6 +376,6 @@ def coarse_level(dec: Decomposition, L1: Level, group: int, primal: int) -> Leve
         C = np.array(rows) if rows else np.zeros((0, len(local)))
         spaces.append(LocalSpace(local, len(cd_int), w, np.array(cids, dtype=np.int64), C))
         Ks.append(Kj)
-    lvl = Level(L1.Kc, spaces, Ks, len(coarse2))
+    lvl = Level(L1.Kc, spaces, Ks, len(coarse2), nonsymmetric=nonsymmetric)
     lvl.globs = globs2
     return lvl

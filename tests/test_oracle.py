@@ -358,3 +358,57 @@ def test_three_levels_need_more_iterations_than_two():
         assert r.converged
         out.append(r.iterations)
     assert out[1] >= out[0]
+
+
+# --------------------------------------------------------------------------------------------
+# non-symmetric formulation (left coarse basis Psi from the transposed constrained problems)
+# --------------------------------------------------------------------------------------------
+def test_nonsymmetric_form_equals_symmetric_form_on_symmetric_tangents():
+    P = problem("small_ve")
+    dec = decomp(P)
+    r = np.random.default_rng(6).standard_normal(len(dec.free))
+    z0 = bddc.BDDC(dec, P.mesh.elem_nodes, P.Ke).apply(r)
+    z1 = bddc.BDDC(dec, P.mesh.elem_nodes, P.Ke, nonsymmetric=True).apply(r)
+    assert np.linalg.norm(z1 - z0) < 1e-12 * np.linalg.norm(z0)
+
+
+def test_left_coarse_basis_properties():
+    """C Psi = I, A^T Psi = -C^T Lambda' and Psi^T A Phi = -Lambda (the coarse matrix) on a
+    non-symmetric tangent."""
+    P = problem("small_ve")
+    dec = decomp(P)
+    B = bddc.BDDC(dec, P.mesh.elem_nodes, skew_perturbed(P, 0.05), nonsymmetric=True)
+    for sd, L in zip(dec.subdomains, B.L1.loc):
+        K, Phi, Psi, Lam, C = L["K"], L["Phi"], L["Psi"], L["Lam"], sd.C
+        assert np.abs(C @ Psi - np.eye(C.shape[0])).max() < 1e-12
+        Z = np.linalg.lstsq(C.T, -(K.T @ Psi), rcond=None)[0]    # A^T Psi lies in range(C^T)
+        assert np.abs(K.T @ Psi + C.T @ Z).max() < 1e-10 * np.abs(K).max()
+        assert np.abs(L["Kc"] + Lam).max() < 1e-10 * np.abs(Lam).max()
+        assert np.abs(Psi - Phi).max() > 1e-6 * np.abs(Phi).max()   # a genuinely different basis
+
+
+@pytest.mark.parametrize("levels", [2, 3])
+def test_nonsymmetric_preconditioner_of_transpose_is_transpose(levels):
+    """The non-symmetric form is adjoint-consistent: the preconditioner built from A^T is the
+    transpose of the one built from A (local solves with N_i^T, the roles of Phi and Psi swapped);
+    the symmetric form (Psi = Phi) is not, on a non-symmetric tangent."""
+    mesh = W.box_mesh(6, 6, 6, 1)
+    part, nsub = W.block_partition(mesh, 3)
+    dirichlet = W.clamp_dofs(mesh, 1)
+    Ke = W.element_tangents(mesh, W.linear_elastic(1.0, 0.3))
+    rng = np.random.default_rng(3)
+    S = rng.standard_normal(Ke.shape)
+    Ke = Ke + 0.05 * np.abs(Ke).max() * (S - np.transpose(S, (0, 2, 1)))
+    KeT = np.ascontiguousarray(np.transpose(Ke, (0, 2, 1)))
+    dec = bddc.Decomposition(mesh.elem_nodes, mesh.n_nodes, part, nsub, dirichlet, mesh.node_tags, primal=3)
+    n = len(dec.free)
+    out = {}
+    for ns in (True, False):
+        kw = dict(levels=levels, coarse_group=2, nonsymmetric=ns)
+        B = bddc.BDDC(dec, mesh.elem_nodes, Ke, **kw)
+        BT = bddc.BDDC(dec, mesh.elem_nodes, KeT, **kw)
+        M = np.stack([B.apply(e) for e in np.eye(n)], axis=1)
+        MT = np.stack([BT.apply(e) for e in np.eye(n)], axis=1)
+        out[ns] = np.abs(MT - M.T).max() / np.abs(M).max()
+    assert out[True] < 1e-12
+    assert out[False] > 1e-6
