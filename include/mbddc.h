@@ -112,6 +112,19 @@ typedef struct {
                                     handle's stream at the first iteration for each right-hand-side
                                     width; recaptured when the handle's apply buffers move. Applies
                                     whose families are being profiled run eagerly. 0: eager launches */
+  int32_t packed_sym;            /* symmetric path (symmetric_hint = 1): store the symmetric blocks of the
+                                    interior and interface operators (K_II^-1, D S~ D) once, as lower
+                                    column panels of 256 columns, and read every stored tile once per
+                                    application for both its product and its transposed product (about
+                                    half their bytes for blocks of many panels). 1 (default): when that
+                                    cuts the operator bytes by 10 % or more; 2: always; 0: never */
+  int32_t nonsym_coarse;         /* general path (symmetric_hint = 0): 1 (default) the non-symmetric BDDC
+                                    formulation (§8: a tangent whose symmetry is broken, e.g. by a
+                                    follower pressure): the coarse right-hand side uses the left coarse
+                                    basis Psi of the transposed constrained problems (N_i^T [Psi; L'] =
+                                    [0; I]), so that the preconditioner of K^T is the transpose of that of
+                                    K; the coarse matrix Psi^T K Phi equals Phi^T K Phi's formula -Lambda.
+                                    0: Psi = Phi. Identical for symmetric tangents. */
 } mbddc_options;
 
 typedef struct {

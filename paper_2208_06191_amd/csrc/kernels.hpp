@@ -31,6 +31,45 @@ struct SubDev {
   int32_t ld1, ld2, ld3, ld4;
   int64_t oKc;                        // local coarse matrix (nc x nc, FP64)
   int64_t oPiv;                       // pivots: nI for K_II then mP for P
+  // Symmetric path: the operators of phases A ([K_II^-1; G]) and C ([D S~ D; (D Phi)^T]) with their
+  // symmetric top block stored once, as column panels of kSymPanel columns from the panel's
+  // diagonal row down (SymPack below); -1 when stored full (oB1 / oB2). oNP / oTP: the phase's
+  // partial products (units of R-vectors) of the normal and transposed tile products.
+  int64_t oS[2], oNP[2], oTP[2];
+};
+
+// Panel-packed symmetric operator: rows [0, n) = [S; X] with S (nS x nS) symmetric, columns
+// [0, nS). Column panel p holds columns [kSymPanel p, kSymPanel (p + 1)) and rows [kSymPanel p, n)
+// column-major with leading dimension N32 - kSymPanel p (N32 = n rounded up to 32, so every
+// column segment of a row tile starts on a 128-byte boundary in FP32); the diagonal tile of a
+// panel is stored whole. Panels are consecutive.
+constexpr int kSymPanel = 256;
+struct SymPack {
+  __host__ __device__ static int32_t n32(int32_t n) { return (n + 31) / 32 * 32; }
+  __host__ __device__ static int32_t panels(int32_t nS) { return (nS + kSymPanel - 1) / kSymPanel; }
+  // first element of panel p; also the first partial row of panel p divided by kSymPanel
+  __host__ __device__ static int64_t panel_rows_before(int32_t p, int32_t N32) {
+    return (int64_t)p * N32 - (int64_t)(kSymPanel / 2) * p * (p - 1);
+  }
+  __host__ __device__ static int64_t panel_off(int32_t p, int32_t N32) {
+    return (int64_t)kSymPanel * panel_rows_before(p, N32);
+  }
+  __host__ __device__ static int32_t ld(int32_t p, int32_t N32) { return N32 - kSymPanel * p; }
+  __host__ __device__ static int64_t elems(int32_t nS, int32_t n) {
+    const int32_t P = panels(nS), N32 = n32(n);
+    if (P == 0) return 0;
+    return panel_off(P - 1, N32) + (int64_t)(nS - kSymPanel * (P - 1)) * ld(P - 1, N32);
+  }
+  // rows of the normal partial products (all panels)
+  __host__ __device__ static int64_t np_rows(int32_t nS, int32_t n) {
+    const int32_t P = panels(nS), N32 = n32(n);
+    return P == 0 ? 0 : panel_rows_before(P - 1, N32) + ld(P - 1, N32);
+  }
+  // transposed partial of panel b from row tile k (b < k < P), in units of kSymPanel entries
+  __host__ __device__ static int64_t tp_index(int32_t b, int32_t k, int32_t P) {
+    return (int64_t)b * (P - 1) - (int64_t)b * (b - 1) / 2 + (k - b - 1);
+  }
+  __host__ __device__ static int64_t tp_count(int32_t P) { return (int64_t)P * (P - 1) / 2; }
 };
 
 // Batched Gauss-Jordan descriptor: invert the n x n matrix at base+off (row stride ld).

@@ -74,14 +74,14 @@ enum Family {
   F_ASSEMBLE_BSR, F_ASSEMBLE_LOCAL, F_GJ_KII, F_GEMM_GH, F_GEMM_S, F_CONSTRAINTS, F_GJ_P, F_EXTRACT,
   F_COARSE_ASSEMBLE, F_COARSE_GJ_SMALL, F_COARSE_DIAG, F_COARSE_PREP, F_COARSE_GEMM, F_COARSE_ROWS,
   F_APPLY_A, F_APPLY_C, F_APPLY_E, F_APPLY_F, F_APPLY_H, F_SPMV, F_KRYLOV_DOTS, F_KRYLOV_UPDATE,
-  F_KRYLOV_SMALL, F_KRYLOV_VEC, F_LEVEL2_SETUP, F_LEVEL2_APPLY, F_APPLY_WHOLE, F_ELEMENT, F_COUNT
+  F_KRYLOV_SMALL, F_KRYLOV_VEC, F_LEVEL2_SETUP, F_LEVEL2_APPLY, F_APPLY_WHOLE, F_ELEMENT, F_APPLY_SYMRED, F_COUNT
 };
 const char* const kFamilyName[F_COUNT] = {
   "assemble_bsr", "assemble_local", "gj_interior", "gemm_condense", "gemm_schur", "constraints", "gj_interface",
   "extract_operators", "coarse_assemble", "coarse_gj_small", "coarse_gj_diag", "coarse_gj_prep", "coarse_gj_gemm",
   "coarse_gj_rows", "apply_A_interior", "apply_C_interface", "apply_E_coarse", "apply_F_coarse_ext",
   "apply_H_average", "spmv_bsr", "krylov_dots", "krylov_update", "krylov_small", "krylov_vectors",
-  "level2_setup", "apply_E_level2", "apply_whole", "element_tangents"};
+  "level2_setup", "apply_E_level2", "apply_whole", "element_tangents", "apply_sym_reduce"};
 
 struct Profiler {
   uint32_t mask = 0;
@@ -303,6 +303,13 @@ struct mbddc_ctx {
   std::vector<int64_t> csym_item_off;  // [coarse_large.size() + 1]
   double* d_rho = nullptr;
   ApplyItem *d_itA = nullptr, *d_itC = nullptr, *d_itE = nullptr, *d_itF = nullptr, *d_itH = nullptr;
+  // packed symmetric phases A and C: tiles (sub, first row of the tile, first column of the panel,
+  // rows), partial-product sizes (R-vectors) and buffers
+  bool packed = false;
+  std::vector<ApplyItem> itSA, itSC;
+  ApplyItem *d_itSA = nullptr, *d_itSC = nullptr;
+  int64_t np_total = 0, tp_total = 0;
+  double *d_np = nullptr, *d_tp = nullptr;
   int32_t *d_chunk_inst = nullptr, *d_inst_chunk_off = nullptr;
   int64_t* d_chunk_begin = nullptr;
 
@@ -586,6 +593,7 @@ void clear_pointers(mbddc_ctx* c) {
   cl(c->d_coords); cl(c->d_u); cl(c->d_frames); cl(c->d_fe); cl(c->d_fint); cl(c->d_elem_nodes);
   cl(c->d_elem_node_off); cl(c->d_elem_mat); cl(c->d_mats); cl(c->d_el_list[0]); cl(c->d_el_list[1]);
   cl(c->d_fe_off); cl(c->d_ne_ptr); cl(c->d_ne_ent);
+  cl(c->d_itSA); cl(c->d_itSC); cl(c->d_np); cl(c->d_tp);
   c->have_material = false;
 }
 
@@ -737,6 +745,19 @@ int build_layout(mbddc_ctx* c) {
   c->gj_x.clear();
   c->gj_t.clear();
   c->itA.clear(); c->itC.clear(); c->itE.clear(); c->itF.clear(); c->itH.clear();
+  c->itSA.clear(); c->itSC.clear();
+  c->np_total = c->tp_total = 0;
+  // packed symmetric blocks: forced (2), or (1) when they cut the operator bytes by a tenth or more
+  // (blocks spanning several panels; a single panel holds the whole block anyway)
+  c->packed = false;
+  if (c->sym && c->opt.packed_sym != 0) {
+    double full = 0.0, pk = 0.0;
+    for (const SubLayout& L : P.subs) {
+      full += (double)round_up(L.nI + L.nG, 4) * L.nI + (double)round_up(L.nG + L.nc, 4) * L.nG;
+      pk += (double)SymPack::elems(L.nI, L.nI + L.nG) + (double)SymPack::elems(L.nG, L.nG + L.nc);
+    }
+    c->packed = c->opt.packed_sym == 2 || pk <= 0.9 * full;
+  }
   c->max_cols = 1;
   std::vector<GemmDesc> dS, dSs, dPhi, dStil;
   for (int64_t s = 0; s < P.n_sub; ++s) {
@@ -758,8 +779,27 @@ int build_layout(mbddc_ctx* c) {
     d.ld2 = (int32_t)round_up(nG + nc, 4);
     d.ld3 = (int32_t)round_up(nG, 4);
     d.ld4 = (int32_t)round_up(nI, 4);
-    d.oB1 = op; op += round_up((int64_t)d.ld1 * nI, 64);
-    d.oB2 = op; op += round_up((int64_t)d.ld2 * nG, 64);
+    for (int q = 0; q < 2; ++q) d.oS[q] = d.oNP[q] = d.oTP[q] = -1;
+    if (c->packed) {   // symmetric blocks stored once (SymPack), with their partial-product buffers
+      d.oB1 = d.oB2 = -1;
+      const int32_t nS[2] = {(int32_t)nI, (int32_t)nG}, nr[2] = {(int32_t)(nI + nG), (int32_t)(nG + nc)};
+      for (int q = 0; q < 2; ++q) {
+        d.oS[q] = op;
+        op += round_up(SymPack::elems(nS[q], nr[q]), 64);
+        d.oNP[q] = c->np_total;
+        c->np_total += SymPack::np_rows(nS[q], nr[q]);
+        d.oTP[q] = c->tp_total;
+        c->tp_total += SymPack::tp_count(SymPack::panels(nS[q])) * kSymPanel;
+        const int32_t P = SymPack::panels(nS[q]), KT = (nr[q] + kSymPanel - 1) / kSymPanel;
+        for (int32_t pp = 0; pp < P; ++pp)
+          for (int32_t k = pp; k < KT; ++k)
+            (q == 0 ? c->itSA : c->itSC).push_back({(int32_t)s, k * kSymPanel, pp * kSymPanel,
+                                                   std::min<int32_t>(kSymPanel, nr[q] - k * kSymPanel)});
+      }
+    } else {
+      d.oB1 = op; op += round_up((int64_t)d.ld1 * nI, 64);
+      d.oB2 = op; op += round_up((int64_t)d.ld2 * nG, 64);
+    }
     d.oB3 = op; op += round_up((int64_t)d.ld3 * nc, 64);
     d.oB4 = op; op += round_up((int64_t)d.ld4 * nG, 64);
     d.oKc = kcl; kcl += nc * nc;
@@ -920,8 +960,13 @@ int build_layout(mbddc_ctx* c) {
   const double eo = (double)elem_size(c->mixed), ef = (double)elem_size(c->fact32);
   for (const SubDev& d : c->subs) {
     const double nI = d.nI, nG = d.nG, nc = d.nc, m = d.nG + d.nc;
-    c->op_bytes[F_APPLY_A] += eo * d.ld1 * nI;
-    c->op_bytes[F_APPLY_C] += eo * d.ld2 * nG;
+    if (c->packed) {
+      c->op_bytes[F_APPLY_A] += eo * SymPack::elems(d.nI, d.nI + d.nG);
+      c->op_bytes[F_APPLY_C] += eo * SymPack::elems(d.nG, d.nG + d.nc);
+    } else {
+      c->op_bytes[F_APPLY_A] += eo * d.ld1 * nI;
+      c->op_bytes[F_APPLY_C] += eo * d.ld2 * nG;
+    }
     c->op_bytes[F_APPLY_F] += eo * d.ld3 * nc;
     c->op_bytes[F_APPLY_H] += eo * d.ld4 * nG;
     c->fam_flops[F_APPLY_A] += (nI + nG) * nI;
@@ -1017,6 +1062,8 @@ int upload_plan(mbddc_ctx* c) {
   CHK(upload(c, &c->d_itE, c->itE));
   CHK(upload(c, &c->d_itF, c->itF));
   CHK(upload(c, &c->d_itH, c->itH));
+  CHK(upload(c, &c->d_itSA, c->itSA));
+  CHK(upload(c, &c->d_itSC, c->itSC));
   CHK(upload(c, &c->d_chunk_inst, c->chunk_inst));
   CHK(upload(c, &c->d_chunk_begin, c->chunk_begin));
   CHK(upload(c, &c->d_inst_chunk_off, c->inst_chunk_off));
@@ -1180,7 +1227,9 @@ double device_bytes_estimate(const mbddc_ctx* c, bool krylov, int nrhs) {
   b += (double)sizeof(SubDev) * P.n_sub + 64.0 * (c->gj_kii.size() + c->gj_p.size() + c->gj_x.size());
   b += 48.0 * (c->gemm_desc.size()) + 16.0 * (c->gemm_items_gh.size() + c->gemm_items_s.size() +
        c->gemm_items_ssym.size() + c->gemm_items_phi.size() + c->gemm_items_stil.size());
-  b += 16.0 * (c->itA.size() + c->itC.size() + c->itE.size() + c->itF.size() + c->itH.size());
+  b += 16.0 * (c->itA.size() + c->itC.size() + c->itE.size() + c->itF.size() + c->itH.size() + c->itSA.size() +
+               c->itSC.size());
+  b += 8.0 * R * (c->np_total + c->tp_total);
   if (!c->coarse_large.empty()) {
     const double cb = std::max(kCoarseBlock, kSymCB), ld = round_up(c->coarse_max_nc, 4);
     b += 8.0 * (2 * cb * cb + 2 * cb * ld);
@@ -1207,6 +1256,11 @@ int ensure_apply_buffers(mbddc_ctx* c, int R) {
   const Plan& P = c->plan;
   dfree(c, c->d_tb); dfree(c, c->d_wb); dfree(c, c->d_cc); dfree(c, c->d_ep);
   dfree(c, c->d_X); dfree(c, c->d_Y); dfree(c, c->d_io);
+  dfree(c, c->d_np); dfree(c, c->d_tp);
+  if (c->packed) {
+    CHK(dalloc(c, &c->d_np, std::max<int64_t>(c->np_total, 1) * R));
+    CHK(dalloc(c, &c->d_tp, std::max<int64_t>(c->tp_total, 1) * R));
+  }
   CHK(dalloc(c, &c->d_tb, P.n_slots * R));
   CHK(dalloc(c, &c->d_wb, P.n_slots * R));
   CHK(dalloc(c, &c->d_cc, std::max<int64_t>(P.n_cslots, 1) * R));
@@ -1620,7 +1674,7 @@ int factor_impl(mbddc_ctx* c) {
     {
       ProfScope ps(c, F_EXTRACT, 0.0, 0.0);
       hipLaunchKernelGGL((k_extract<T, To>), dim3(nsub), dim3(kBlock), 0, c->stream, c->d_subs, c->d_slot_w, W, Op,
-                         c->d_Kcl);
+                         c->d_Kcl, c->opt.nonsym_coarse != 0 ? 1 : 0);
     }
   }
   // coarse problem (the extraction may still run on the side stream: joined below on every path)
@@ -1696,6 +1750,9 @@ int factor_impl(mbddc_ctx* c) {
 // ----------------------------------------------------------------------------
 template <typename To, int R>
 int apply_attrs();
+// dynamic LDS of the packed tile kernel per right-hand side: cross-wave sums, the panel's and
+// the row tile's inputs
+constexpr size_t kSymLds = (4 * 256 + 2 * kSymPanel) * sizeof(double);
 
 // Phase PH of the local apply (row-block list k of A, C, F, H) with that list's rows per
 // workgroup: 256 (four rows per lane), 128 (two) or 64 (one).
@@ -1737,15 +1794,39 @@ int apply_impl(mbddc_ctx* c, const double* r, double* z, mbddc_ctx* parent = nul
   a.xchunk = std::min(c->max_cols, c->tune.xchunk);
   CHK((apply_attrs<To, R>()));
   if ((4 * 256 * R + (size_t)a.xchunk * R) * sizeof(double) > 160 * 1024) return MBDDC_ERR_UNSUPPORTED;
+  a.np = c->d_np;
+  a.tp = c->d_tp;
   {
     ProfScope ps(c, F_APPLY_A, c->op_bytes[F_APPLY_A] + 8.0 * R * c->vec_words[F_APPLY_A], 2.0 * R * c->fam_flops[F_APPLY_A]);
+    if (c->packed) {
+      a.items = c->d_itSA;
+      if (!c->itSA.empty())
+        hipLaunchKernelGGL((k_apply_sym<To, R, 0>), dim3((unsigned)c->itSA.size()), dim3(kBlock), kSymLds * R, c->stream, a);
+    } else {
+      a.items = c->d_itA;
+      launch_local<To, R, 0>(c, a, 0, c->itA.size());
+    }
+  }
+  if (c->packed) {
+    ProfScope ps(c, F_APPLY_SYMRED, 0.0, 0.0);
     a.items = c->d_itA;
-    launch_local<To, R, 0>(c, a, 0, c->itA.size());
+    hipLaunchKernelGGL((k_apply_sym_reduce<R, 0>), dim3((unsigned)c->itA.size()), dim3(kBlock), 0, c->stream, a);
   }
   {
     ProfScope ps(c, F_APPLY_C, c->op_bytes[F_APPLY_C] + 8.0 * R * c->vec_words[F_APPLY_C], 2.0 * R * c->fam_flops[F_APPLY_C]);
+    if (c->packed) {
+      a.items = c->d_itSC;
+      if (!c->itSC.empty())
+        hipLaunchKernelGGL((k_apply_sym<To, R, 1>), dim3((unsigned)c->itSC.size()), dim3(kBlock), kSymLds * R, c->stream, a);
+    } else {
+      a.items = c->d_itC;
+      launch_local<To, R, 1>(c, a, 1, c->itC.size());
+    }
+  }
+  if (c->packed) {
+    ProfScope ps(c, F_APPLY_SYMRED, 0.0, 0.0);
     a.items = c->d_itC;
-    launch_local<To, R, 1>(c, a, 1, c->itC.size());
+    hipLaunchKernelGGL((k_apply_sym_reduce<R, 1>), dim3((unsigned)c->itC.size()), dim3(kBlock), 0, c->stream, a);
   }
   if (c->child) {
     mbddc_ctx* ch = c->child;
@@ -1829,6 +1910,8 @@ int apply_attrs() {
     if (!e) e = set_lds(k_apply_local<To, R, 1, 1, false>, mx);
     if (!e) e = set_lds(k_apply_local<To, R, 3, 1, false>, mx);
     if (!e) e = set_lds(k_apply_local<To, R, 4, 1, false>, mx);
+    if (!e) e = set_lds(k_apply_sym<To, R, 0>, mx);
+    if (!e) e = set_lds(k_apply_sym<To, R, 1>, mx);
     st = e;
   });
   return st;
@@ -1844,7 +1927,7 @@ int apply_attrs_all(int R) {
 }
 
 constexpr uint32_t kApplyFamilies = (1u << F_APPLY_A) | (1u << F_APPLY_C) | (1u << F_APPLY_E) | (1u << F_APPLY_F) |
-                                    (1u << F_APPLY_H) | (1u << F_LEVEL2_APPLY);
+                                    (1u << F_APPLY_H) | (1u << F_LEVEL2_APPLY) | (1u << F_APPLY_SYMRED);
 
 // z = M^-1 r on the handle's fixed blocks d_X -> d_Y: replayed from a captured graph
 // unless graphs are off or an apply family is being profiled.
@@ -2418,6 +2501,8 @@ int mbddc_default_options(mbddc_options* opt) {
   opt->rtol = 1e-8;
   opt->max_it = 1000;
   opt->graph_apply = 1;
+  opt->packed_sym = 1;
+  opt->nonsym_coarse = 1;
   return MBDDC_OK;
 }
 
@@ -2845,6 +2930,7 @@ int mbddc_footprint(const mbddc_ctx* c, int nrhs, size_t* device_bytes) {
   if (c->R_alloc < R) {
     extra += (size_t)P.n_slots * R * 8 * 2 + (size_t)std::max<int64_t>(P.n_cslots, 1) * R * 8;
     extra += (size_t)c->nchunk_max * std::max<int64_t>(P.n_coarse, 1) * R * 8 + (size_t)P.n_dofs * R * 8 * 3;
+    if (c->packed) extra += (size_t)(c->np_total + c->tp_total) * R * 8;
   }
   if (c->R_kry < R || c->restart_kry < c->opt.restart) extra += (size_t)P.n_dofs * R * 8 * (2 * J + 4);
   if (const mbddc_ctx* ch = c->child) {   // level-2 operators and its apply buffers
@@ -2853,6 +2939,7 @@ int mbddc_footprint(const mbddc_ctx* c, int nrhs, size_t* device_bytes) {
     if (ch->R_alloc < R) {
       extra += (size_t)Q.n_slots * R * 8 * 2 + (size_t)std::max<int64_t>(Q.n_cslots, 1) * R * 8;
       extra += (size_t)ch->nchunk_max * std::max<int64_t>(Q.n_coarse, 1) * R * 8 + (size_t)Q.n_dofs * R * 8 * 3;
+      if (ch->packed) extra += (size_t)(ch->np_total + ch->tp_total) * R * 8;
     }
   }
   *device_bytes = c->bytes + extra;
