@@ -389,6 +389,74 @@ def element_internal_forces(mesh: Mesh, material, u: np.ndarray, frames_fn=None)
     return fe.reshape(mesh.n_elems, 3 * mesh.npe)
 
 
+def boundary_faces(mesh: Mesh, tag_bit: int) -> np.ndarray:
+    """Element faces on a tagged surface: rows (element, d, side) of every face xi_d = side
+    (reference cube [0,1]^3) whose nodes all carry tag_bit, sorted."""
+    p1 = mesh.order + 1
+    out = []
+    for d in range(3):
+        for side in (0, 1):
+            idx = [a + p1 * b + p1 * p1 * c for c in range(p1) for b in range(p1) for a in range(p1)
+                   if (a, b, c)[d] == side * (p1 - 1)]
+            on = np.all((mesh.node_tags[mesh.elem_nodes[:, idx]] & tag_bit) != 0, axis=1)
+            out += [(int(e), d, side) for e in np.nonzero(on)[0]]
+    return np.array(sorted(out), dtype=np.int64).reshape(-1, 3)
+
+
+def boundary_terms(mesh: Mesh, faces: np.ndarray, kind: str, params, u: Optional[np.ndarray] = None):
+    """Element-matrix and element-force contributions [n_el, nd, nd], [n_el, nd] of a boundary
+    condition on `faces` (paper §2, boundary conditions), by the (p+1)^2 Gauss rule of each face:
+    * "robin" (params a_perp, a_par): g = (N (x) N) a_perp u + (I - N (x) N) a_par u, the epicardial
+      condition with the stiffness and damping terms combined into a_perp, a_par;
+      force int N_a g dS, tangent int N_a N_b (a_perp N N^T + a_par (I - N N^T)) dS;
+    * "pressure" (params p): g = p J F^-T N (follower pressure on the endocardium), force
+      int N_a g dS, tangent int N_a p J (F^-T_iJ F^-T_kL - F^-T_iL F^-T_kJ) N_J dN_b/dX_L dS
+      (not symmetric).
+    N is the outward unit normal and dS the area element of the reference configuration."""
+    order = mesh.order
+    p1 = order + 1
+    npe = mesh.npe
+    nd = 3 * npe
+    K = np.zeros((mesh.n_elems, nd, nd))
+    f = np.zeros((mesh.n_elems, nd))
+    g1, w1 = np.polynomial.legendre.leggauss(p1)
+    g1, w1 = 0.5 * (g1 + 1.0), 0.5 * w1
+    for e, d, side in faces:
+        Xe = mesh.coords[mesh.elem_nodes[e]]
+        ue = np.zeros((npe, 3)) if u is None else u[mesh.elem_nodes[e]]
+        d1, d2 = (d + 1) % 3, (d + 2) % 3
+        for q1 in range(p1):
+            for q2 in range(p1):
+                xi = np.zeros(3)
+                xi[d], xi[d1], xi[d2] = float(side), g1[q1], g1[q2]
+                Nq, dNq = shape_functions(order, xi[None, :])
+                Nq, dNq = Nq[0], dNq[0]
+                Jm = Xe.T @ dNq                                   # dX_i / dxi_j
+                nvec = np.cross(Jm[:, d1], Jm[:, d2]) * (1.0 if side == 1 else -1.0) * w1[q1] * w1[q2]
+                dS = np.linalg.norm(nvec)
+                Nn = nvec / dS
+                dNX = dNq @ np.linalg.inv(Jm)                     # dN_a / dX_L
+                if kind == "robin":
+                    ap, al = params
+                    Bm = ap * np.outer(Nn, Nn) + al * (np.eye(3) - np.outer(Nn, Nn))
+                    g = Bm @ (ue.T @ Nq)
+                    f[e] += dS * np.einsum("a,i->ai", Nq, g).ravel()
+                    K[e] += dS * np.einsum("a,b,ik->aibk", Nq, Nq, Bm).reshape(nd, nd)
+                elif kind == "pressure":
+                    (pr,) = params
+                    F = np.eye(3) + ue.T @ dNX
+                    J = np.linalg.det(F)
+                    Fi = np.linalg.inv(F).T                       # F^-T
+                    g = pr * J * Fi @ nvec
+                    f[e] += np.einsum("a,i->ai", Nq, g).ravel()
+                    T = pr * J * (np.einsum("iJ,kL->iJkL", Fi, Fi) - np.einsum("iL,kJ->iJkL", Fi, Fi))
+                    TN = np.einsum("iJkL,J->ikL", T, nvec)
+                    K[e] += np.einsum("a,ikL,bL->aibk", Nq, TN, dNX).reshape(nd, nd)
+                else:
+                    raise ValueError(kind)
+    return K, f
+
+
 def body_force_load(mesh: Mesh, force_at_nodes: np.ndarray) -> np.ndarray:
     """Consistent load b_(a,i) = sum_e sum_q w |J| N_a f_i(X_q), f interpolated from nodal
     values [n_nodes, 3]; returned as a full DOF vector [3*n_nodes]."""

@@ -197,3 +197,41 @@ def test_ventricle_newton_request_shapes_and_first_step():
     assert len(dirichlet) > 0 and np.all(mesh.node_tags[np.asarray(dirichlet) // 3] & W.VENT_BASE)
     assert np.allclose(Ks[0], Ks[0].transpose(0, 2, 1), atol=1e-10 * np.abs(Ks[0]).max())
     assert np.abs(Ks[2] - Ks[0]).max() > 1e-6 * np.abs(Ks[0]).max()
+
+
+# ------------------------------------------------------------------ boundary conditions (§2)
+@pytest.mark.parametrize("kind,params", [("robin", (2.0, 0.5)), ("pressure", (0.7,))])
+def test_boundary_tangent_is_derivative_of_boundary_force(kind, params):
+    mesh, param = W.ventricle_mesh(2, 8, 6, 2)
+    faces = W.boundary_faces(mesh, W.VENT_ENDO if kind == "pressure" else W.VENT_EPI)
+    assert len(faces) == 8 * 6
+    u = W.isochoric_field(mesh.coords, 5, 0.02)
+    du = W.smooth_field(mesh.coords, 6, 1.0)
+    K, f0 = W.boundary_terms(mesh, faces, kind, params, u)
+    h = 1e-6
+    _, fp = W.boundary_terms(mesh, faces, kind, params, u + h * du)
+    _, fm = W.boundary_terms(mesh, faces, kind, params, u - h * du)
+    fd = (fp - fm) / (2 * h)
+    due = du[mesh.elem_nodes].reshape(mesh.n_elems, -1)
+    lin = np.einsum("eij,ej->ei", K, due)
+    assert np.abs(fd - lin).max() <= 1e-7 * np.abs(lin).max()
+    if kind == "robin":   # linear in u, symmetric
+        assert np.abs(K - np.transpose(K, (0, 2, 1))).max() <= 1e-14 * np.abs(K).max()
+    else:                 # a follower load: not symmetric
+        assert np.abs(K - np.transpose(K, (0, 2, 1))).max() > 1e-3 * np.abs(K).max()
+
+
+def test_pressure_on_a_closed_surface_has_no_resultant():
+    """Piola: the integral of J F^-T N over a closed reference surface is the integral of the
+    current normal over the closed deformed surface, zero for any deformation."""
+    mesh = W.box_mesh(3, 2, 2, 2)
+    faces = np.concatenate([W.boundary_faces(mesh, bit) for bit in (1, 2, 4, 8, 16, 32)])
+    u = W.isochoric_field(mesh.coords, 7, 0.05) + 0.03 * W.smooth_field(mesh.coords, 8, 1.0)
+    _, f = W.boundary_terms(mesh, faces, "pressure", (1.3,), u)
+    tot = f.reshape(mesh.n_elems, -1, 3).sum(axis=(0, 1))
+    area = 2 * (1 + 1 + 1)
+    assert np.abs(tot).max() <= 1e-12 * area
+    # and the reference outward normals of a box: the resultant of a uniform unit pressure on one
+    # face is its area along the outward normal
+    _, f1 = W.boundary_terms(mesh, W.boundary_faces(mesh, 2), "pressure", (1.0,))
+    assert np.allclose(f1.reshape(mesh.n_elems, -1, 3).sum(axis=(0, 1)), [1.0, 0.0, 0.0], atol=1e-13)
