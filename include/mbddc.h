@@ -233,6 +233,24 @@ typedef struct {
  * when no instance is Guccione. Copies everything to the device; state >= setup. */
 int mbddc_set_material(mbddc_ctx* ctx, const mbddc_material* mats, const double* frames);
 
+/* Boundary conditions of §2 on the element faces of tagged surfaces, for the element kernels:
+ * a face (xi_d = 0 or 1 of an element's reference cube) carries condition b when all its nodes
+ * carry every bit of bcs[b].tag (mbddc_mesh.node_tags), on instance bcs[b].instance (-1: all).
+ * MBDDC_BC_ROBIN (the epicardial condition, stiffness and damping combined): traction
+ * g = (a_perp N N^T + a_par (I - N N^T)) u with p = {a_perp, a_par}; MBDDC_BC_PRESSURE (the
+ * endocardial follower pressure): g = p J F^-T N with p = {p, unused}; N the reference outward
+ * normal. Each adds int g . v dS to the internal forces and its derivative to the tangent (not
+ * symmetric for the pressure: solve with symmetric_hint = 0, the non-symmetric formulation).
+ * Replaces earlier conditions; mbddc_set_material clears them. Needs mbddc_set_material. */
+enum { MBDDC_BC_ROBIN = 1, MBDDC_BC_PRESSURE = 2 };
+typedef struct {
+  int32_t kind;
+  uint32_t tag;
+  int32_t instance;
+  double p[2];
+} mbddc_boundary;
+int mbddc_set_boundary(mbddc_ctx* ctx, const mbddc_boundary* bcs, int n_bc);
+
 /* The Newton tangent at displacement u (full DOF vector [n_dofs], host or device per
  * on_device), computed on the device (§2 "tangent problem"): for every element and Gauss point
  * of the tensor rule with p+1 points per direction on the reference cube, F = I + grad u,

@@ -394,6 +394,14 @@ struct mbddc_ctx {
   int64_t* d_fe_off = nullptr;
   int32_t* d_ne_ptr = nullptr;
   int64_t* d_ne_ent = nullptr;
+  // boundary conditions on element faces (mbddc_set_boundary)
+  std::vector<uint32_t> h_tags;     // [n_nodes] all instances (zeros where a mesh came without)
+  std::vector<int32_t> bc_items[2]; // per element order: (element, first face) pairs
+  std::vector<int32_t> bc_end[2];
+  int32_t* d_bc_items[2] = {nullptr, nullptr};
+  int32_t* d_bc_end[2] = {nullptr, nullptr};
+  int32_t* d_faces = nullptr;
+  BcDev* d_bcs = nullptr;
 };
 
 namespace {
@@ -594,6 +602,9 @@ void clear_pointers(mbddc_ctx* c) {
   cl(c->d_elem_node_off); cl(c->d_elem_mat); cl(c->d_mats); cl(c->d_el_list[0]); cl(c->d_el_list[1]);
   cl(c->d_fe_off); cl(c->d_ne_ptr); cl(c->d_ne_ent);
   cl(c->d_itSA); cl(c->d_itSC); cl(c->d_np); cl(c->d_tp);
+  cl(c->d_bc_items[0]); cl(c->d_bc_items[1]); cl(c->d_bc_end[0]); cl(c->d_bc_end[1]); cl(c->d_faces);
+  cl(c->d_bcs);
+  c->bc_items[0].clear(); c->bc_items[1].clear(); c->bc_end[0].clear(); c->bc_end[1].clear();
   c->have_material = false;
 }
 
@@ -2425,10 +2436,15 @@ ElemTables elem_tables(int order) {
     if (order == 1) {
       t.N1[q][0] = 1.0 - x; t.N1[q][1] = x;
       t.D1[q][0] = -1.0; t.D1[q][1] = 1.0;
+      t.Dend[q][0] = -1.0; t.Dend[q][1] = 1.0;   // q = end point 0 / 1 (n = 2 of them here)
     } else {
       t.N1[q][0] = 2.0 * (x - 0.5) * (x - 1.0); t.N1[q][1] = -4.0 * x * (x - 1.0); t.N1[q][2] = 2.0 * x * (x - 0.5);
       t.D1[q][0] = 4.0 * x - 3.0; t.D1[q][1] = -8.0 * x + 4.0; t.D1[q][2] = 4.0 * x - 1.0;
     }
+  }
+  if (order == 2) {
+    t.Dend[0][0] = -3.0; t.Dend[0][1] = 4.0; t.Dend[0][2] = -1.0;
+    t.Dend[1][0] = 1.0; t.Dend[1][1] = -4.0; t.Dend[1][2] = 3.0;
   }
   return t;
 }
@@ -2447,6 +2463,18 @@ int launch_elements(mbddc_ctx* c, bool forces) {
     ProfScope ps(c, F_ELEMENT, 8.0 * (c->plan.ke_total), 0.0);
     if (o == 0) hipLaunchKernelGGL((k_element<2>), dim3((unsigned)g.n), dim3(kBlock), 0, c->stream, g, tab);
     else hipLaunchKernelGGL((k_element<3>), dim3((unsigned)g.n), dim3(kBlock), 0, c->stream, g, tab);
+  }
+  for (int o = 0; o < 2; ++o) {   // boundary faces, added to their elements' matrices and forces
+    if (c->bc_end[o].empty()) continue;
+    FaceArgs f{};
+    f.coords = c->d_coords; f.u = c->d_u; f.elem_nodes = c->d_elem_nodes; f.node_off = c->d_elem_node_off;
+    f.ke_off = c->d_ke_off; f.fe_off = c->d_fe_off; f.items = c->d_bc_items[o]; f.item_end = c->d_bc_end[o];
+    f.faces = c->d_faces; f.bcs = c->d_bcs; f.n = (int64_t)c->bc_end[o].size(); f.Ke = c->d_Ke;
+    f.fe = forces ? c->d_fe : nullptr; f.flag = c->d_flag;
+    const ElemTables tab = elem_tables(o + 1);
+    ProfScope ps(c, F_ELEMENT, 0.0, 0.0);
+    if (o == 0) hipLaunchKernelGGL((k_element_faces<2>), dim3((unsigned)f.n), dim3(kBlock), 0, c->stream, f, tab);
+    else hipLaunchKernelGGL((k_element_faces<3>), dim3((unsigned)f.n), dim3(kBlock), 0, c->stream, f, tab);
   }
   HIPCHK(hipGetLastError());
   return MBDDC_OK;
@@ -2648,6 +2676,11 @@ int prepare_host(mbddc_ctx* c, const mbddc_options& o, const std::vector<MeshIn>
   c->sym = (o.symmetric_hint != 0);
   std::string err = build_plan(ms, o.primal, c->plan);
   if (!err.empty()) return MBDDC_ERR_ARG;
+  c->h_tags.clear();
+  for (const MeshIn& m : ms) {
+    if (m.node_tags.empty()) c->h_tags.insert(c->h_tags.end(), m.n_nodes, 0u);
+    else c->h_tags.insert(c->h_tags.end(), m.node_tags.begin(), m.node_tags.end());
+  }
   c->h_coords.clear();
   bool all_coords = true;
   for (const MeshIn& m : ms) all_coords &= !m.coords.empty();
@@ -3016,6 +3049,7 @@ int mbddc_set_material(mbddc_ctx* c, const mbddc_material* mats, const double* f
     guccione |= m.kind == MBDDC_MAT_GUCCIONE;
   }
   if (guccione && !frames) return MBDDC_ERR_ARG;
+  for (int o = 0; o < 2; ++o) { c->bc_items[o].clear(); c->bc_end[o].clear(); }   // conditions set again after
   std::vector<int32_t> elem_mat(P.n_elems);
   for (int i = 0; i < P.n_inst; ++i)
     for (int32_t e = 0; e < P.inst[i].n_elems; ++e) elem_mat[P.inst[i].elem_off + e] = i;
@@ -3061,6 +3095,64 @@ int mbddc_set_material(mbddc_ctx* c, const mbddc_material* mats, const double* f
   }
   HIPCHK(hipStreamSynchronize(c->stream));
   c->have_material = true;
+  return MBDDC_OK;
+}
+
+int mbddc_set_boundary(mbddc_ctx* c, const mbddc_boundary* bcs, int n_bc) {
+  if (!c || n_bc < 0 || (n_bc > 0 && !bcs)) return MBDDC_ERR_ARG;
+  if (c->state < 1 || !c->have_material) return MBDDC_ERR_STATE;
+  if (hipSetDevice(c->device) != hipSuccess) return MBDDC_ERR_DEVICE;
+  const Plan& P = c->plan;
+  std::vector<BcDev> bd(n_bc);
+  for (int b = 0; b < n_bc; ++b) {
+    const mbddc_boundary& x = bcs[b];
+    if ((x.kind != MBDDC_BC_ROBIN && x.kind != MBDDC_BC_PRESSURE) || x.tag == 0 || x.instance < -1 ||
+        x.instance >= P.n_inst || !std::isfinite(x.p[0]) || !std::isfinite(x.p[1]))
+      return MBDDC_ERR_ARG;
+    bd[b].kind = x.kind;
+    bd[b].p[0] = x.p[0];
+    bd[b].p[1] = x.p[1];
+  }
+  // faces xi_d = side of every element whose nodes all carry a condition's tag bits
+  std::vector<int32_t> faces;
+  for (int o = 0; o < 2; ++o) { c->bc_items[o].clear(); c->bc_end[o].clear(); }
+  for (int32_t ii = 0; ii < P.n_inst; ++ii) {
+    const Instance& in = P.inst[ii];
+    for (int32_t el = 0; el < in.n_elems; ++el) {
+      const int64_t e = in.elem_off + el;
+      const int npe = P.elem_npe[e], p1 = npe == 8 ? 2 : 3;
+      const int32_t first = (int32_t)(faces.size() / 3);
+      for (int b = 0; b < n_bc; ++b) {
+        if (bcs[b].instance >= 0 && bcs[b].instance != ii) continue;
+        for (int d = 0; d < 3; ++d)
+          for (int side = 0; side < 2; ++side) {
+            bool on = true;
+            for (int a = 0; a < npe && on; ++a) {
+              const int ia[3] = {a % p1, (a / p1) % p1, a / (p1 * p1)};
+              if (ia[d] != side * (p1 - 1)) continue;
+              on = (c->h_tags[P.elem_nodes_flat[P.elem_node_off[e] + a]] & bcs[b].tag) == bcs[b].tag;
+            }
+            if (on) faces.insert(faces.end(), {d, side, b});
+          }
+      }
+      const int32_t last = (int32_t)(faces.size() / 3);
+      if (last > first) {
+        const int o = npe == 8 ? 0 : 1;
+        c->bc_items[o].insert(c->bc_items[o].end(), {(int32_t)e, first});
+        c->bc_end[o].push_back(last);
+      }
+    }
+  }
+  for (int o = 0; o < 2; ++o) { dfree(c, c->d_bc_items[o]); dfree(c, c->d_bc_end[o]); }
+  dfree(c, c->d_faces);
+  dfree(c, c->d_bcs);
+  for (int o = 0; o < 2; ++o) {
+    CHK(upload(c, &c->d_bc_items[o], c->bc_items[o]));
+    CHK(upload(c, &c->d_bc_end[o], c->bc_end[o]));
+  }
+  CHK(upload(c, &c->d_faces, faces));
+  CHK(upload(c, &c->d_bcs, bd));
+  HIPCHK(hipStreamSynchronize(c->stream));
   return MBDDC_OK;
 }
 

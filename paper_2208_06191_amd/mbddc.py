@@ -25,6 +25,7 @@ MBDDC_HEX8, MBDDC_HEX27 = 1, 2
 MBDDC_PRIMAL_V, MBDDC_PRIMAL_E, MBDDC_PRIMAL_F = 1, 2, 4
 MBDDC_FP64, MBDDC_MIXED, MBDDC_MIXED_F32FACT = 0, 1, 2
 MBDDC_MAT_SVK, MBDDC_MAT_NEO_HOOKEAN, MBDDC_MAT_GUCCIONE = 1, 2, 3
+MBDDC_BC_ROBIN, MBDDC_BC_PRESSURE = 1, 2
 
 _i32p = ctypes.POINTER(ctypes.c_int32)
 _u32p = ctypes.POINTER(ctypes.c_uint32)
@@ -56,6 +57,11 @@ class mbddc_info(ctypes.Structure):
 
 class mbddc_material(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("p", ctypes.c_double * 5)]
+
+
+class mbddc_boundary(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("tag", ctypes.c_uint32), ("instance", ctypes.c_int32),
+                ("p", ctypes.c_double * 2)]
 
 
 class mbddc_sizes(ctypes.Structure):
@@ -103,6 +109,7 @@ _SIGNATURES = {
     "mbddc_factor": [ctypes.c_void_p],
     "mbddc_set_material": [ctypes.c_void_p, ctypes.POINTER(mbddc_material), _f64p],
     "mbddc_set_displacement": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_int],
+    "mbddc_set_boundary": [ctypes.c_void_p, ctypes.POINTER(mbddc_boundary), ctypes.c_int],
     "mbddc_get_element_tangents": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int],
     "mbddc_solve": [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
                     ctypes.POINTER(mbddc_info)],
@@ -433,6 +440,15 @@ class Solver:
         fr = None if frames is None else np.ascontiguousarray(frames, dtype=np.float64)
         _check(lib().mbddc_set_material(self._h, arr, _ptr(fr, ctypes.c_double)), "mbddc_set_material")
         self._frames = fr
+
+    def mbddc_set_boundary(self, conditions):
+        """conditions: (kind, tag bits, instance (-1: all), params) per boundary condition."""
+        arr = (mbddc_boundary * max(1, len(conditions)))()
+        for k, (kind, tag, inst, params) in enumerate(conditions):
+            arr[k].kind, arr[k].tag, arr[k].instance = kind, tag, inst
+            for j, v in enumerate(params):
+                arr[k].p[j] = float(v)
+        _check(lib().mbddc_set_boundary(self._h, arr, len(conditions)), "mbddc_set_boundary")
 
     def mbddc_set_displacement(self, u, f_int: bool = False):
         """Device element tangents at u (full DOF vector, numpy or a device tensor); returns the

@@ -166,3 +166,92 @@ def test_newton_on_device_matches_host_newton(name):
     assert res[4] <= 1e-7 * res[0]
     assert res[3] <= 10.0 * res[2] ** 2 / res[0] and res[4] < res[3] < res[2]
     s.close()
+
+
+# ------------------------------------------------------------------ boundary conditions (§2)
+def shell_with_bcs():
+    mesh, param = W.ventricle_mesh(2, 12, 8, 2)
+    part, nsub = W.rcb_partition(mesh, param, 480, 3)
+    frames = W.ventricle_frames(mesh, param)
+    return mesh, part, nsub, W.clamp_dofs(mesh, W.VENT_BASE), frames
+
+
+BCS = [(mbddc.MBDDC_BC_ROBIN, W.VENT_EPI, -1, (2.0, 0.5)), (mbddc.MBDDC_BC_PRESSURE, W.VENT_ENDO, -1, (0.05, 0.0))]
+
+
+def host_boundary(mesh, u):
+    K = np.zeros((mesh.n_elems, 81, 81))
+    f = np.zeros((mesh.n_elems, 81))
+    for kind, tag, _, params in BCS:
+        name = "robin" if kind == mbddc.MBDDC_BC_ROBIN else "pressure"
+        Kb, fb = W.boundary_terms(mesh, W.boundary_faces(mesh, tag), name, params[:2] if name == "robin" else params[:1],
+                                  u)
+        K += Kb
+        f += fb
+    return K, f
+
+
+def test_boundary_terms_match_host():
+    mesh, part, nsub, dirichlet, frames = shell_with_bcs()
+    mat = W.guccione()
+    u = W.isochoric_field(mesh.coords, 2, 0.015)
+    Kv = W.element_tangents(mesh, mat, u, frames_fn=lambda el, q: frames[el])
+    Kb, fb = host_boundary(mesh, u)
+    fe = W.element_internal_forces(mesh, mat, u, frames_fn=lambda el, q: frames[el]) + fb
+    fh = np.zeros(3 * mesh.n_nodes)
+    dofs = (3 * mesh.elem_nodes[:, :, None] + np.arange(3)[None, None, :]).reshape(mesh.n_elems, -1)
+    np.add.at(fh, dofs.ravel(), fe.ravel())
+    fh[dirichlet] = 0.0
+    s = handle(mesh, part, nsub, dirichlet)
+    s.mbddc_set_material([mat_params(mat)], frames)
+    s.mbddc_set_boundary(BCS)
+    f = s.mbddc_set_displacement(u.ravel(), f_int=True)
+    Kd = s.mbddc_get_element_tangents().reshape(Kv.shape)
+    Kh = Kv + Kb
+    ek = np.abs(Kd - Kh).max() / np.abs(Kh).max()
+    ef = np.abs(f - fh).max() / np.abs(fh).max()
+    eb = np.abs((Kd - Kv) - Kb).max() / np.abs(Kb).max()
+    print(f"shell with Robin and pressure: element tangents {ek:.2e} (boundary part {eb:.2e}), forces {ef:.2e}")
+    # the boundary part is isolated by subtracting the much larger volume part: its floor is the
+    # total's 1e-13 scaled by their ratio
+    assert ek <= 1e-13 and ef <= 1e-13 and eb <= 1e-13 * np.abs(Kh).max() / np.abs(Kb).max()
+    s.close()
+
+
+def test_realistic_shell_newton_nonsymmetric():
+    """The realistic setting of §8 in miniature: Guccione shell, base clamped, Robin epicardium,
+    follower pressure on the endocardium (a non-symmetric tangent), Newton on the device with the
+    non-symmetric BDDC formulation on the pivoted path, against a host Newton with direct solves."""
+    mesh, part, nsub, dirichlet, frames = shell_with_bcs()
+    mat = W.guccione()
+    free = np.setdiff1d(np.arange(3 * mesh.n_nodes), dirichlet)
+    m = mbddc._MeshArrays(mesh.coords, mesh.elem_nodes, mesh.elem_type, part, nsub, mesh.node_tags, dirichlet)
+    s = mbddc.Solver(0)
+    s.mbddc_setup_symbolic([m], mbddc.default_options(primal=7, symmetric_hint=0, rtol=1e-12,
+                                                      precision=mbddc.MBDDC_FP64))
+    s.mbddc_set_material([mat_params(mat)], frames)
+    s.mbddc_set_boundary(BCS)
+    ud = np.zeros(3 * mesh.n_nodes)
+    uh = np.zeros(3 * mesh.n_nodes)
+    dofs = (3 * mesh.elem_nodes[:, :, None] + np.arange(3)[None, None, :]).reshape(mesh.n_elems, -1)
+    res = []
+    for k in range(5):
+        fint = s.mbddc_set_displacement(ud, f_int=True)
+        s.mbddc_factor()
+        r = -fint
+        res.append(np.linalg.norm(r[free]))
+        du, info = s.mbddc_solve(r)
+        ud = ud + du
+        U = uh.reshape(-1, 3)
+        Kb, fb = host_boundary(mesh, U)
+        Kh = W.element_tangents(mesh, mat, U, frames_fn=lambda el, q: frames[el]) + Kb
+        A = fem.reduce_to_free(fem.assemble(mesh.elem_nodes, Kh, 3 * mesh.n_nodes), free)
+        fe = W.element_internal_forces(mesh, mat, U, frames_fn=lambda el, q: frames[el]) + fb
+        fh = np.zeros(3 * mesh.n_nodes)
+        np.add.at(fh, dofs.ravel(), fe.ravel())
+        uh[free] += spla.spsolve(A.tocsc(), -fh[free])
+        e = np.linalg.norm(ud - uh) / np.linalg.norm(uh)
+        print(f"realistic Newton step {k}: residual {res[-1]:.3e}, its {info.iterations}, |u_dev - u_host| / |u| = {e:.2e}")
+        assert e <= 1e-9
+    assert res[4] <= 1e-7 * res[0]
+    s.close()
