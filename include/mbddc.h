@@ -219,11 +219,12 @@ int mbddc_set_tangent(mbddc_ctx* ctx, const double* elem_K, int on_device);
  * Psi = mu/2 (I1 - 3) - mu ln J + lambda/2 (ln J)^2): mu, lambda. MBDDC_MAT_GUCCIONE (§2,
  * transversely isotropic exponential law Psi = C/2 (e^Q - 1) + B/2 (J - 1) ln J with
  * Q = b_f E_ff^2 + b_t (E_ss^2 + E_nn^2 + 2 E_sn^2) + b_fs (2 E_fs^2 + 2 E_fn^2) in the fibre
- * frame (f, s, n)): C, b_f, b_t, b_fs, B. */
+ * frame (f, s, n)), with the active stress of §2, P_act = gamma (F f) (x) f / |F f|, added to
+ * P: C, b_f, b_t, b_fs, B, gamma (gamma = 0: passive). Unused entries are ignored (finite). */
 enum { MBDDC_MAT_SVK = 1, MBDDC_MAT_NEO_HOOKEAN = 2, MBDDC_MAT_GUCCIONE = 3 };
 typedef struct {
   int32_t kind;
-  double p[5];
+  double p[6];
 } mbddc_material;
 
 /* Sets the material of every instance (mats[n_instances]) for the element kernels. Needs the

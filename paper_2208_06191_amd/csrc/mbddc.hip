@@ -3042,7 +3042,7 @@ int mbddc_set_material(mbddc_ctx* c, const mbddc_material* mats, const double* f
     const mbddc_material& m = mats[i];
     if (m.kind != MBDDC_MAT_SVK && m.kind != MBDDC_MAT_NEO_HOOKEAN && m.kind != MBDDC_MAT_GUCCIONE) return MBDDC_ERR_ARG;
     md[i].kind = m.kind;
-    for (int k = 0; k < 5; ++k) {
+    for (int k = 0; k < 6; ++k) {
       if (!std::isfinite(m.p[k])) return MBDDC_ERR_ARG;
       md[i].p[k] = m.p[k];
     }

@@ -56,7 +56,7 @@ class mbddc_info(ctypes.Structure):
 
 
 class mbddc_material(ctypes.Structure):
-    _fields_ = [("kind", ctypes.c_int32), ("p", ctypes.c_double * 5)]
+    _fields_ = [("kind", ctypes.c_int32), ("p", ctypes.c_double * 6)]
 
 
 class mbddc_boundary(ctypes.Structure):

@@ -261,8 +261,10 @@ def _stress_tangent(mat, F):
     raise ValueError(mat["kind"])
 
 
-def guccione(C: float = 0.88, bf: float = 8.0, bt: float = 2.0, bfs: float = 2.0, B: float = 50.0):
-    return {"kind": "guccione", "C": C, "bf": bf, "bt": bt, "bfs": bfs, "B": B}
+def guccione(C: float = 0.88, bf: float = 8.0, bt: float = 2.0, bfs: float = 2.0, B: float = 50.0,
+             gamma: float = 0.0):
+    """Guccione law; gamma > 0 adds the active stress of §2, P_act = gamma (F f) (x) f / |F f|."""
+    return {"kind": "guccione", "C": C, "bf": bf, "bt": bt, "bfs": bfs, "B": B, "gamma": gamma}
 
 
 def _guccione(mat, F):
@@ -299,6 +301,15 @@ def _guccione(mat, F):
     CC = CC + (a2[:, None, None, None, None] * np.einsum("mij,mkl->mijkl", Ci, Ci)
                - a1[:, None, None, None, None]
                * (np.einsum("mik,mjl->mijkl", Ci, Ci) + np.einsum("mil,mjk->mijkl", Ci, Ci)))
+    gamma = mat.get("gamma", 0.0)
+    if gamma != 0.0:
+        # active stress P_act = gamma (F f) (x) f / |F f|: S_act = gamma f (x) f / sqrt(f.C f),
+        # CC_act = 2 dS_act/dC = -gamma f (x) f (x) f (x) f / (f.C f)^(3/2)
+        f = Q[:, 0, :]
+        lam2 = np.einsum("mi,mij,mj->m", f, Cg, f)
+        ff = np.einsum("mi,mj->mij", f, f)
+        S = S + (gamma / np.sqrt(lam2))[:, None, None] * ff
+        CC = CC - (gamma / lam2 ** 1.5)[:, None, None, None, None] * np.einsum("mij,mkl->mijkl", ff, ff)
     return S, CC
 
 

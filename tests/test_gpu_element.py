@@ -26,7 +26,8 @@ def mat_params(material):
         return (mbddc.MBDDC_MAT_SVK, (material["lam"], material["mu"]))
     if k == "neo_hookean":
         return (mbddc.MBDDC_MAT_NEO_HOOKEAN, (material["mu"], material["lam"]))
-    return (mbddc.MBDDC_MAT_GUCCIONE, (material["C"], material["bf"], material["bt"], material["bfs"], material["B"]))
+    return (mbddc.MBDDC_MAT_GUCCIONE, (material["C"], material["bf"], material["bt"], material["bfs"], material["B"],
+                                       material.get("gamma", 0.0)))
 
 
 def case(name):
@@ -42,7 +43,8 @@ def case(name):
     part, nsub = W.rcb_partition(mesh, param, 900, 3)
     frames = W.ventricle_frames(mesh, param)
     u = W.isochoric_field(mesh.coords, 2, 0.015)
-    return mesh, part, nsub, W.clamp_dofs(mesh, W.VENT_BASE), W.guccione(), u, frames
+    mat = W.guccione(gamma=0.3) if name == "shell_guccione_active" else W.guccione()
+    return mesh, part, nsub, W.clamp_dofs(mesh, W.VENT_BASE), mat, u, frames
 
 
 def host_forces(mesh, mat, u, frames, dirichlet):
@@ -61,7 +63,7 @@ def handle(mesh, part, nsub, dirichlet):
     return s
 
 
-@pytest.mark.parametrize("name", ["q1_linear", "q1_nh", "q2_nh", "shell_guccione"])
+@pytest.mark.parametrize("name", ["q1_linear", "q1_nh", "q2_nh", "shell_guccione", "shell_guccione_active"])
 def test_element_tangents_and_forces_match_host(name):
     torch = pytest.importorskip("torch")
     mesh, part, nsub, dirichlet, mat, u, frames = case(name)

@@ -235,3 +235,17 @@ def test_pressure_on_a_closed_surface_has_no_resultant():
     # face is its area along the outward normal
     _, f1 = W.boundary_terms(mesh, W.boundary_faces(mesh, 2), "pressure", (1.0,))
     assert np.allclose(f1.reshape(mesh.n_elems, -1, 3).sum(axis=(0, 1)), [1.0, 0.0, 0.0], atol=1e-13)
+
+
+def test_active_stress_tangent_is_derivative_and_stress_is_along_the_fibre():
+    """§2 active part P_act = gamma (F f) (x) f / |F f|: the tangent with it is still the derivative
+    of the internal force, and at u = 0 it adds exactly gamma f (x) f to the stress (|f| = 1)."""
+    mesh, param = W.ventricle_mesh(2, 8, 6, 2)
+    Q = W.ventricle_frames(mesh, param)
+    u = W.isochoric_field(mesh.coords, 3, 0.02)
+    assert _fd_check(mesh, W.guccione(gamma=0.4), u, frames_fn=lambda e, q: Q[e]) < 1e-7
+    F = np.broadcast_to(np.eye(3), (5, 3, 3)).copy()
+    mat = dict(W.guccione(gamma=0.4), frames=Q[:5])
+    S1, _ = W._stress_tangent(mat, F)
+    S0, _ = W._stress_tangent(dict(W.guccione(), frames=Q[:5]), F)
+    assert np.abs(S1 - S0 - 0.4 * np.einsum("mi,mj->mij", Q[:5, 0], Q[:5, 0])).max() < 1e-14
