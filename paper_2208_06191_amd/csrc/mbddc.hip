@@ -26,6 +26,7 @@
 #include <memory>
 #include <new>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "mbddc.h"
@@ -257,6 +258,11 @@ struct mbddc_ctx {
   std::vector<SubDev> subs;
   std::vector<GjDesc> gj_kii, gj_p, gj_coarse_small;
   std::vector<int32_t> coarse_large;                 // instances inverted by the blocked path
+  std::vector<GjDesc> gj_kii_large, gj_p_large;      // general path: blocks above kGjMax rows (multi-workgroup
+                                                     // Gauss-Jordan, one matrix at a time)
+  int32_t gen_large_max = 0;                        // largest row stride among them
+  struct PivGemm { int32_t n, ld; GemmDesc* d_gd; GemmItem* d_items; int32_t n_items; };
+  std::vector<PivGemm> piv_gemm;                     // rank-64 update descriptors per matrix shape
   std::vector<GemmDesc> gemm_desc;
   std::vector<GemmItem> gemm_items_gh, gemm_items_s, gemm_items_g, gemm_items_ssym, gemm_items_phi, gemm_items_stil;
   std::vector<GjDesc> gj_x;                          // (S + rho C^T C) blocks of the symmetric path
@@ -604,6 +610,7 @@ void clear_pointers(mbddc_ctx* c) {
   cl(c->d_itSA); cl(c->d_itSC); cl(c->d_np); cl(c->d_tp);
   cl(c->d_bc_items[0]); cl(c->d_bc_items[1]); cl(c->d_bc_end[0]); cl(c->d_bc_end[1]); cl(c->d_faces);
   cl(c->d_bcs);
+  c->piv_gemm.clear();
   c->bc_items[0].clear(); c->bc_items[1].clear(); c->bc_end[0].clear(); c->bc_end[1].clear();
   c->have_material = false;
 }
@@ -746,6 +753,10 @@ int build_layout(mbddc_ctx* c) {
   int64_t w = 0, op = 0, kcl = 0, piv = 0;
   c->gj_kii.clear();
   c->gj_p.clear();
+  c->gj_kii_large.clear();
+  c->gj_p_large.clear();
+  c->gen_large_max = 0;
+  c->piv_gemm.clear();
   c->gemm_desc.clear();
   c->gemm_items_gh.clear();
   c->gemm_items_s.clear();
@@ -780,7 +791,9 @@ int build_layout(mbddc_ctx* c) {
     const int64_t ni = L.ni(), nI = L.nI, nG = L.nG, nc = L.nc, m = L.mP();
     // the pivoting path inverts in one workgroup; the symmetric path sweeps larger FP64
     // matrices with the batched blocked kernels, larger FP32 ones not at all
-    if (!c->sym && std::max<int64_t>(nI, m) > kGjMax) return MBDDC_ERR_UNSUPPORTED;
+    // the general path inverts blocks up to kGjMax rows in one workgroup, larger ones (FP64
+    // factorisations only) by the multi-workgroup pivoted Gauss-Jordan
+    if (!c->sym && c->fact32 && std::max<int64_t>(nI, m) > kGjMax) return MBDDC_ERR_UNSUPPORTED;
     d.oK = w; w += round_up(ni * ni, 64);
     d.oG = w; w += round_up(nG * nI, 64);
     d.oH = w;
@@ -816,8 +829,13 @@ int build_layout(mbddc_ctx* c) {
     d.oKc = kcl; kcl += nc * nc;
     d.oPiv = piv; piv += nI + m;
     c->max_cols = std::max<int>(c->max_cols, (int)std::max(std::max(nI, nG), nc));
-    c->gj_kii.push_back({d.oK, (int32_t)nI, (int32_t)ni, d.oPiv, (int32_t)s, 0});
-    c->gj_p.push_back({d.oP, (int32_t)m, (int32_t)m, d.oPiv + nI, (int32_t)s, 0});
+    if (!c->sym && nI > kGjMax) c->gj_kii_large.push_back({d.oK, (int32_t)nI, (int32_t)ni, d.oPiv, (int32_t)s, 0});
+    else c->gj_kii.push_back({d.oK, (int32_t)nI, (int32_t)ni, d.oPiv, (int32_t)s, 0});
+    if (!c->sym && m > kGjMax) c->gj_p_large.push_back({d.oP, (int32_t)m, (int32_t)m, d.oPiv + nI, (int32_t)s, 0});
+    else c->gj_p.push_back({d.oP, (int32_t)m, (int32_t)m, d.oPiv + nI, (int32_t)s, 0});
+    // the blocked inverse stages kCoarseBlock rows at the matrix's row stride (ni for K_II)
+    if (!c->sym) c->gen_large_max = std::max<int32_t>(c->gen_large_max, (int32_t)std::max<int64_t>(
+                                       nI > kGjMax ? ni : 0, m > kGjMax ? m : 0));
     c->gj_x.push_back({d.oP, (int32_t)nG, (int32_t)nG, 0, (int32_t)s, 0});
     if (c->sym)   // T = C X C^T, inverted by the batched sweep
       c->gj_t.push_back({d.oP + nG * nG + 2 * nG * nc, (int32_t)nc, (int32_t)nc, 0, (int32_t)s, 0});
@@ -1090,9 +1108,16 @@ int upload_plan(mbddc_ctx* c) {
   CHK(dalloc(c, &c->d_piv, c->piv_elems));
   c->status_len = std::max<int64_t>(P.n_sub, (int64_t)c->gj_coarse_small.size()) + 1;
   CHK(dalloc(c, &c->d_status, c->status_len));
-  CHK(dalloc(c, &c->d_piv_c, std::max<int64_t>(std::max<int64_t>(P.n_coarse, c->coarse_max_nc), 1)));
+  CHK(dalloc(c, &c->d_piv_c, std::max<int64_t>(std::max<int64_t>(P.n_coarse, std::max(c->coarse_max_nc,
+                                                                                          c->gen_large_max)), 1)));
+  if (c->gen_large_max > 0 && c->coarse_large.empty()) {   // pivoted Gauss-Jordan of large local blocks
+    const int64_t ldmax = round_up(c->gen_large_max, 4), cb = std::max(kCoarseBlock, kSymCB);
+    CHK(dalloc(c, &c->d_cDinv, 2 * cb * cb));
+    CHK(dalloc(c, &c->d_cY, cb * ldmax));
+    CHK(dalloc(c, &c->d_cCcol, ldmax * cb));
+  }
   if (!c->coarse_large.empty()) {
-    int64_t ldmax = round_up(c->coarse_max_nc, 4);
+    int64_t ldmax = round_up(std::max(c->coarse_max_nc, c->gen_large_max), 4);
     const int64_t cb = std::max(kCoarseBlock, kSymCB);
     CHK(dalloc(c, &c->d_cDinv, 2 * cb * cb));
     CHK(dalloc(c, &c->d_cY, cb * ldmax));
@@ -1114,7 +1139,7 @@ int upload_plan(mbddc_ctx* c) {
     CHK(upload(c, &c->d_csym_gd, gds));
     CHK(upload(c, &c->d_csym_items, items));
   }
-  CHK(dalloc(c, &c->d_amax, 1));
+  CHK(dalloc(c, &c->d_amax, 2));   // [0]: max |A| of a blocked inversion, [1]: rho of an augmentation
   if (c->big_count > 0) {
     CHK(dalloc(c, &c->d_bpanel, c->big_pbuf));
     CHK(dalloc(c, &c->d_bdinv, c->big_count * kSymCB * kSymCB));
@@ -1494,9 +1519,24 @@ int coarse_sweep_large(mbddc_ctx* c, int32_t ii) {
   return MBDDC_OK;
 }
 
+// In-place inverse of one n x n FP64 matrix (row stride ld) by multi-workgroup Gauss-Jordan in
+// blocks of kCoarseBlock pivots, each pivot the largest entry of its column within the diagonal
+// block; *singular = 1 on a pivot below n eps max|A|. The rank-kCoarseBlock update descriptors
+// are made once per matrix shape.
+int invert_pivoted(mbddc_ctx* c, double* A, int n, int ld, int* singular);
+
 int coarse_invert_large(mbddc_ctx* c, int32_t ii) {
-  const int n = c->inst_nc[ii], ld = c->inst_kc_ld[ii];
-  double* A = c->d_Kc + c->inst_kc_off[ii];
+  int sing = 0;
+  CHK(invert_pivoted(c, c->d_Kc + c->inst_kc_off[ii], c->inst_nc[ii], c->inst_kc_ld[ii], &sing));
+  if (sing) {
+    c->last_bad = -1;
+    return MBDDC_ERR_SINGULAR;
+  }
+  return MBDDC_OK;
+}
+
+int invert_pivoted(mbddc_ctx* c, double* A, int n, int ld, int* singular) {
+  *singular = 0;
   HIPCHK(hipMemsetAsync(c->d_amax, 0, sizeof(double), c->stream));
   hipLaunchKernelGGL(k_absmax, dim3(512), dim3(kBlock), 0, c->stream, A, n, ld, c->d_amax);
   double amax = 0.0;
@@ -1504,17 +1544,26 @@ int coarse_invert_large(mbddc_ctx* c, int32_t ii) {
   HIPCHK(hipMemsetAsync(c->d_status, 0, sizeof(int32_t), c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
   const double thresh = (double)n * 2.220446049250313e-16 * amax;
-  // single-problem GEMM descriptor re-used for every diagonal block
-  GemmDesc gd{};
-  gd.M = n; gd.N = n; gd.K = kCoarseBlock; gd.lda = kCoarseBlock; gd.ldb = ld; gd.ldc = ld; gd.ldci = ld;
-  gd.tiles_n = (n + 63) / 64; gd.oA = 0; gd.oB = 0; gd.oC = 0; gd.oCi = 0; gd.alpha = -1.0; gd.beta = 1.0;
-  std::vector<GemmItem> items;
-  for (int a = 0; a < (n + 63) / 64; ++a)
-    for (int b = 0; b < gd.tiles_n; ++b) items.push_back({0, a, b, 0});
-  GemmDesc* d_gd = nullptr;
-  GemmItem* d_items = nullptr;
-  CHK(upload(c, &d_gd, std::vector<GemmDesc>{gd}));
-  CHK(upload(c, &d_items, items));
+  // single-problem GEMM descriptor re-used for every diagonal block (kept per shape)
+  mbddc_ctx::PivGemm* pg = nullptr;
+  for (auto& q : c->piv_gemm)
+    if (q.n == n && q.ld == ld) pg = &q;
+  if (!pg) {
+    GemmDesc gd{};
+    gd.M = n; gd.N = n; gd.K = kCoarseBlock; gd.lda = kCoarseBlock; gd.ldb = ld; gd.ldc = ld; gd.ldci = ld;
+    gd.tiles_n = (n + 63) / 64; gd.oA = 0; gd.oB = 0; gd.oC = 0; gd.oCi = 0; gd.alpha = -1.0; gd.beta = 1.0;
+    std::vector<GemmItem> its;
+    for (int a = 0; a < (n + 63) / 64; ++a)
+      for (int b = 0; b < gd.tiles_n; ++b) its.push_back({0, a, b, 0});
+    mbddc_ctx::PivGemm q{n, ld, nullptr, nullptr, (int32_t)its.size()};
+    CHK(upload(c, &q.d_gd, std::vector<GemmDesc>{gd}));
+    CHK(upload(c, &q.d_items, its));
+    c->piv_gemm.push_back(q);
+    pg = &c->piv_gemm.back();
+  }
+  GemmDesc* d_gd = pg->d_gd;
+  GemmItem* d_items = pg->d_items;
+  const int32_t n_items = pg->n_items;
   const unsigned ncb = nblk(n, 64);
   const double gemm_flops = 2.0 * n * (double)n * kCoarseBlock;
   for (int k0 = 0; k0 < n; k0 += kCoarseBlock) {
@@ -1532,8 +1581,7 @@ int coarse_invert_large(mbddc_ctx* c, int32_t ii) {
     }
     {
       ProfScope ps(c, F_COARSE_GEMM, 16.0 * n * (double)n, gemm_flops);
-      launch_gemm<double>(c, (unsigned)items.size(), c->stream, d_gd,
-                         d_items, c->d_cCcol, c->d_cY, A, A);
+      launch_gemm<double>(c, (unsigned)n_items, c->stream, d_gd, d_items, c->d_cCcol, c->d_cY, A, A);
     }
     {
       ProfScope ps(c, F_COARSE_ROWS, 0.0, 0.0);
@@ -1547,11 +1595,39 @@ int coarse_invert_large(mbddc_ctx* c, int32_t ii) {
   int32_t st = 0;
   HIPCHK(hipMemcpyAsync(&st, c->d_status, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
-  dfree(c, d_gd);
-  dfree(c, d_items);
-  if (st != 0) {
-    c->last_bad = -1;
-    return MBDDC_ERR_SINGULAR;
+  *singular = st != 0;
+  return MBDDC_OK;
+}
+
+// General path: the local blocks above kGjMax rows, one matrix at a time. Constrained interface
+// matrices (constrained = true) are augmented around the inversion (k_gen_augment).
+template <typename T>
+int run_gj_large(mbddc_ctx* c, T* W, const std::vector<GjDesc>& descs, int fam, bool constrained) {
+  if (descs.empty()) return MBDDC_OK;
+  if (!std::is_same<T, double>::value) return MBDDC_ERR_UNSUPPORTED;
+  for (const GjDesc& d : descs) {
+    int sing = 0;
+    double* A = reinterpret_cast<double*>(W) + d.off;
+    const int nc = constrained ? c->subs[d.id].nc : 0, nG = d.n - nc;
+    {
+      ProfScope ps(c, fam, 0.0, 2.0 * (double)d.n * d.n * d.n);
+      if (nc > 0) {
+        hipLaunchKernelGGL(k_gen_rho, dim3(1), dim3(kBlock), 0, c->stream, A, nG, d.ld, c->d_amax + 1);
+        hipLaunchKernelGGL(k_gen_augment, dim3(std::min<unsigned>(2048, nblk((int64_t)nG * nG))), dim3(kBlock), 0,
+                           c->stream, A, nG, nc, d.ld, c->d_amax + 1);
+        HIPCHK(hipGetLastError());
+      }
+      CHK(invert_pivoted(c, A, d.n, d.ld, &sing));
+      if (nc > 0 && !sing) {
+        hipLaunchKernelGGL(k_gen_unaugment, dim3(nblk(nc)), dim3(kBlock), 0, c->stream, A, nG, nc, d.ld,
+                           c->d_amax + 1);
+        HIPCHK(hipGetLastError());
+      }
+    }
+    if (sing) {
+      c->last_bad = d.id;
+      return MBDDC_ERR_SINGULAR;
+    }
   }
   return MBDDC_OK;
 }
@@ -1568,11 +1644,9 @@ int factor_impl(mbddc_ctx* c) {
                        c->d_sub_elems, c->d_ke_off, c->d_elem_npe, c->d_elem_ldof, c->d_elem_ldof_off, W);
   }
   HIPCHK(hipGetLastError());
-  int maxI = 1, maxP = 1;
-  for (const SubDev& d : c->subs) {
-    maxI = std::max(maxI, d.nI);
-    maxP = std::max(maxP, d.nG + d.nc);
-  }
+  int maxI = 1, maxP = 1;   // the one-workgroup kernel's blocks (the general path's large ones go apart)
+  for (const GjDesc& d : c->gj_kii) maxI = std::max(maxI, d.n);
+  for (const GjDesc& d : c->gj_p) maxP = std::max(maxP, d.n);
   int bad = 0, st = 0;
   // K_II^-1 (interior / Dirichlet problems, §3.2 block factorisation)
   {
@@ -1586,6 +1660,7 @@ int factor_impl(mbddc_ctx* c) {
     c->last_bad = bad;
     return st;
   }
+  if (!c->sym) CHK(run_gj_large<T>(c, W, c->gj_kii_large, F_GJ_KII, false));
   // G = K_GI K_II^-1 (and H = K_II^-1 K_IG on the general path), S = K_GG - G K_IG
   const std::vector<GemmItem>& igh = c->sym ? c->gemm_items_g : c->gemm_items_gh;
   const std::vector<GemmItem>& is = c->sym ? c->gemm_items_ssym : c->gemm_items_s;
@@ -1682,6 +1757,7 @@ int factor_impl(mbddc_ctx* c) {
       c->last_bad = bad;
       return st;
     }
+    CHK(run_gj_large<T>(c, W, c->gj_p_large, F_GJ_P, true));
     {
       ProfScope ps(c, F_EXTRACT, 0.0, 0.0);
       hipLaunchKernelGGL((k_extract<T, To>), dim3(nsub), dim3(kBlock), 0, c->stream, c->d_subs, c->d_slot_w, W, Op,

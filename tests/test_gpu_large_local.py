@@ -121,11 +121,77 @@ def test_three_levels_with_large_locals(precision):
     assert info.rel_res_true <= 1e-8
 
 
-def test_pivoting_path_rejects_large_locals():
+# general path (symmetric_hint = 0): blocks above 512 rows go to the multi-workgroup pivoted
+# inverse, the interface matrices augmented by rho C^T C around it
+GENERAL = [("large_q1", 3), ("vent_parts6k", 7)]
+
+
+@pytest.mark.parametrize("precision", PRECS)
+@pytest.mark.parametrize("name,primal", GENERAL)
+def test_general_path_large_locals(name, primal, precision):
+    P = problem(name)
+    dec, B = oracle_of(name, primal)
+    nI = np.array([s.n_interior for s in dec.subdomains])
+    m = np.array([len(s.dofs) - s.n_interior + s.C.shape[0] for s in dec.subdomains])
+    assert nI.max() > 512 and m.max() > 512
+    s = solver_for(P, precision, primal, sym=0)
+    err_c = rel(s.mbddc_get_coarse_matrix(0, dec.n_coarse), B.Kc)
+    r = np.random.default_rng(7).standard_normal((2, P.n_dofs))
+    r[:, P.dirichlet] = 0.0
+    z = s.mbddc_apply(r)
+    err = max(rel(z[k][dec.free], B.apply(r[k][dec.free])) for k in range(2))
+    bound = max(TOL_APPLY[precision], 100.0 * apply_noise_floor(name, primal))
+    b = P.rhs[0][dec.free]
+    ref = gmres.gmres(lambda v: B.A @ v, B.apply, b, 1e-8, 30, 1000)
+    x, info = s.mbddc_solve(P.rhs[0])
+    print(f"general {name} prec={precision}: coarse {err_c:.2e} apply {err:.2e} (bound {bound:.1e}) "
+          f"its {info.iterations} (oracle {ref.iterations})")
+    assert err_c <= 1e-11
+    assert err <= bound
+    assert np.linalg.norm(b - B.A @ x[dec.free]) <= 1e-8 * np.linalg.norm(b)
+    if precision == mbddc.MBDDC_FP64:
+        assert abs(info.iterations - ref.iterations) <= 1
+    else:
+        assert info.iterations <= ref.iterations + 2
+    s.close()
+
+
+def test_general_path_large_nonsymmetric():
+    """Skew-perturbed tangents (5 % of the largest entry) on the large Q1 box against the
+    oracle's non-symmetric formulation (left coarse basis)."""
+    P = problem("large_q1")
+    S = np.random.default_rng(3).standard_normal(P.Ke.shape)
+    Ke = P.Ke + 0.05 * np.abs(P.Ke).max() * (S - np.transpose(S, (0, 2, 1)))
+    dec = bddc.Decomposition(P.mesh.elem_nodes, P.mesh.n_nodes, P.elem_part, P.n_sub, P.dirichlet,
+                             P.mesh.node_tags, primal=3)
+    B = bddc.BDDC(dec, P.mesh.elem_nodes, Ke, nonsymmetric=True)
+    s = mbddc.Solver(0)
+    s.mbddc_setup_symbolic([mbddc.mesh_from_problem(P)],
+                           mbddc.default_options(precision=mbddc.MBDDC_FP64, primal=3, symmetric_hint=0))
+    s.mbddc_set_tangent(Ke)
+    s.mbddc_factor()
+    r = np.random.default_rng(7).standard_normal((2, P.n_dofs))
+    r[:, P.dirichlet] = 0.0
+    z = s.mbddc_apply(r)
+    err = max(rel(z[k][dec.free], B.apply(r[k][dec.free])) for k in range(2))
+    b = P.rhs[0][dec.free]
+    ref = gmres.gmres(lambda v: B.A @ v, B.apply, b, 1e-8, 30, 1000)
+    x, info = s.mbddc_solve(P.rhs[0])
+    bound = max(1e-12, 100.0 * apply_noise_floor("large_q1", 3))
+    print(f"general nonsymmetric large_q1: apply {err:.2e} (bound {bound:.1e}) its {info.iterations} "
+          f"(oracle {ref.iterations})")
+    assert err <= bound
+    assert abs(info.iterations - ref.iterations) <= 1
+    assert np.linalg.norm(b - B.A @ x[dec.free]) <= 1e-8 * np.linalg.norm(b)
+    s.close()
+
+
+def test_general_path_rejects_large_locals_in_fp32_factor():
     P = problem("large_q1")
     s = mbddc.Solver(0)
     with pytest.raises(mbddc.MbddcError) as e:
-        s.mbddc_setup_symbolic([mbddc.mesh_from_problem(P)], mbddc.default_options(primal=3, symmetric_hint=0))
+        s.mbddc_setup_symbolic([mbddc.mesh_from_problem(P)],
+                               mbddc.default_options(primal=3, symmetric_hint=0, precision=mbddc.MBDDC_MIXED_F32FACT))
     assert e.value.status == mbddc.MBDDC_ERR_UNSUPPORTED
 
 
