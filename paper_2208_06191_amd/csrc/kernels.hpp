@@ -27,15 +27,21 @@ struct SubDev {
   int64_t oG;                         // K_GI K_II^-1   (nG x nI)
   int64_t oH;                         // K_II^-1 K_IG   (nI x nG)
   int64_t oP;                         // [S C^T; C 0] (mP x mP), inverted in place
-  int64_t oB1, oB2, oB3, oB4;         // operators: [K_II^-1; G], [D S~ D; (D Phi)^T], D Phi, H
+  int64_t oB1, oB2, oB3, oB4;         // operators: [K_II^-1; G] (G alone when packed), [D S~ D; (D Phi)^T],
+                                      // D Phi, H (-1 when packed)
   int32_t ld1, ld2, ld3, ld4;
   int64_t oKc;                        // local coarse matrix (nc x nc, FP64)
   int64_t oPiv;                       // pivots: nI for K_II then mP for P
-  // Symmetric path: the operators of phases A ([K_II^-1; G]) and C ([D S~ D; (D Phi)^T]) with their
-  // symmetric top block stored once, as column panels of kSymPanel columns from the panel's
-  // diagonal row down (SymPack below); -1 when stored full (oB1 / oB2). oNP / oTP: the phase's
-  // partial products (units of R-vectors) of the normal and transposed tile products.
+  // Symmetric path, packed: K_II^-1 (slot 0) and [D S~ D; (D Phi)^T] (slot 1) with their symmetric
+  // block stored once, as column panels of kSymPanel columns from the panel's diagonal row down
+  // (SymPack below); -1 when stored full (oB1 / oB2). oNP / oTP: the partial products (units of
+  // R-vectors) of the normal and transposed tile products.
   int64_t oS[2], oNP[2], oTP[2];
+  // Packed path: phase A forms G r_I alone and phase H solves z_I = K_II^-1 (r_I - K_IG z_G), with
+  // K_IG as CSR rows over the interior: row pointers (nI + 1, relative) at kig_ptr of the pointer
+  // array, interface-local columns at kig_col of the column array, values at oKig of the operator
+  // buffer (-1 otherwise).
+  int64_t oKig, kig_ptr, kig_col;
 };
 
 // Panel-packed symmetric operator: rows [0, n) = [S; X] with S (nS x nS) symmetric, columns

@@ -75,14 +75,15 @@ enum Family {
   F_ASSEMBLE_BSR, F_ASSEMBLE_LOCAL, F_GJ_KII, F_GEMM_GH, F_GEMM_S, F_CONSTRAINTS, F_GJ_P, F_EXTRACT,
   F_COARSE_ASSEMBLE, F_COARSE_GJ_SMALL, F_COARSE_DIAG, F_COARSE_PREP, F_COARSE_GEMM, F_COARSE_ROWS,
   F_APPLY_A, F_APPLY_C, F_APPLY_E, F_APPLY_F, F_APPLY_H, F_SPMV, F_KRYLOV_DOTS, F_KRYLOV_UPDATE,
-  F_KRYLOV_SMALL, F_KRYLOV_VEC, F_LEVEL2_SETUP, F_LEVEL2_APPLY, F_APPLY_WHOLE, F_ELEMENT, F_APPLY_SYMRED, F_COUNT
+  F_KRYLOV_SMALL, F_KRYLOV_VEC, F_LEVEL2_SETUP, F_LEVEL2_APPLY, F_APPLY_WHOLE, F_ELEMENT, F_APPLY_SYMRED,
+  F_APPLY_HPREP, F_COUNT
 };
 const char* const kFamilyName[F_COUNT] = {
   "assemble_bsr", "assemble_local", "gj_interior", "gemm_condense", "gemm_schur", "constraints", "gj_interface",
   "extract_operators", "coarse_assemble", "coarse_gj_small", "coarse_gj_diag", "coarse_gj_prep", "coarse_gj_gemm",
   "coarse_gj_rows", "apply_A_interior", "apply_C_interface", "apply_E_coarse", "apply_F_coarse_ext",
   "apply_H_average", "spmv_bsr", "krylov_dots", "krylov_update", "krylov_small", "krylov_vectors",
-  "level2_setup", "apply_E_level2", "apply_whole", "element_tangents", "apply_sym_reduce"};
+  "level2_setup", "apply_E_level2", "apply_whole", "element_tangents", "apply_sym_reduce", "apply_H_prep"};
 
 struct Profiler {
   uint32_t mask = 0;
@@ -314,6 +315,8 @@ struct mbddc_ctx {
   bool packed = false;
   std::vector<ApplyItem> itSA, itSC;
   ApplyItem *d_itSA = nullptr, *d_itSC = nullptr;
+  std::vector<int32_t> kig_ptr, kig_col;   // K_IG rows of the packed path's phase H (SubDev::kig_*)
+  int32_t *d_kig_ptr = nullptr, *d_kig_col = nullptr;
   int64_t np_total = 0, tp_total = 0;
   double *d_np = nullptr, *d_tp = nullptr;
   int32_t *d_chunk_inst = nullptr, *d_inst_chunk_off = nullptr;
@@ -607,7 +610,7 @@ void clear_pointers(mbddc_ctx* c) {
   cl(c->d_coords); cl(c->d_u); cl(c->d_frames); cl(c->d_fe); cl(c->d_fint); cl(c->d_elem_nodes);
   cl(c->d_elem_node_off); cl(c->d_elem_mat); cl(c->d_mats); cl(c->d_el_list[0]); cl(c->d_el_list[1]);
   cl(c->d_fe_off); cl(c->d_ne_ptr); cl(c->d_ne_ent);
-  cl(c->d_itSA); cl(c->d_itSC); cl(c->d_np); cl(c->d_tp);
+  cl(c->d_itSA); cl(c->d_itSC); cl(c->d_np); cl(c->d_tp); cl(c->d_kig_ptr); cl(c->d_kig_col);
   cl(c->d_bc_items[0]); cl(c->d_bc_items[1]); cl(c->d_bc_end[0]); cl(c->d_bc_end[1]); cl(c->d_faces);
   cl(c->d_bcs);
   c->piv_gemm.clear();
@@ -715,13 +718,49 @@ Tuning child_tuning(const Tuning& t) {
   return u;
 }
 
+// Structural pattern of K_IG^(i) (interior row, interface column: the pairs that share an
+// element), as CSR rows over the interior appended to ptr / col; sets d.kig_ptr / d.kig_col and
+// returns the entry count.
+int64_t kig_pattern(const Plan& P, const SubLayout& L, std::vector<int32_t>& ptr, std::vector<int32_t>& col,
+                    SubDev& d) {
+  std::vector<std::vector<int32_t>> rows(L.nI);
+  std::vector<int32_t> in, ifc;
+  for (int32_t k = 0; k < L.n_elems; ++k) {
+    const int64_t e = L.elem_off + k;
+    const int32_t npe = P.elem_npe[P.sub_elems[e]];
+    const int32_t* ld = P.elem_ldof.data() + P.elem_ldof_off[e];
+    in.clear();
+    ifc.clear();
+    for (int32_t a = 0; a < 3 * npe; ++a) {
+      if (ld[a] < 0) continue;
+      (ld[a] < L.nI ? in : ifc).push_back(ld[a]);
+    }
+    if (ifc.empty()) continue;
+    for (int32_t i : in)
+      for (int32_t g : ifc) rows[i].push_back(g - L.nI);
+  }
+  d.kig_ptr = (int64_t)ptr.size();
+  d.kig_col = (int64_t)col.size();
+  int32_t n = 0;
+  ptr.push_back(0);
+  for (auto& r : rows) {
+    std::sort(r.begin(), r.end());
+    r.erase(std::unique(r.begin(), r.end()), r.end());
+    col.insert(col.end(), r.begin(), r.end());
+    n += (int32_t)r.size();
+    ptr.push_back(n);
+  }
+  return n;
+}
+
 // Row blocks of the local apply phases: at most 64, 128 or 256 rows per workgroup per phase, from
 // the tuning table, or (0) the one of 128 and 256 that pads the phase's row counts least (256 on ties).
 void build_apply_items(mbddc_ctx* c) {
   c->itA.clear(); c->itC.clear(); c->itF.clear(); c->itH.clear();
   std::vector<ApplyItem>* lists[4] = {&c->itA, &c->itC, &c->itF, &c->itH};
-  auto rows_of = [](const SubDev& d, int k) -> int64_t {
-    return k == 0 ? d.nI + d.nG : (k == 1 ? d.nG + d.nc : (k == 2 ? d.nG : d.nI));
+  const bool gonly = c->packed;   // phase A multiplies by G alone on the packed path
+  auto rows_of = [gonly](const SubDev& d, int k) -> int64_t {
+    return k == 0 ? (gonly ? d.nG : d.nI + d.nG) : (k == 1 ? d.nG + d.nc : (k == 2 ? d.nG : d.nI));
   };
   for (int k = 0; k < 4; ++k) {
     int rw = c->tune.apply_rows[k];
@@ -768,15 +807,18 @@ int build_layout(mbddc_ctx* c) {
   c->gj_t.clear();
   c->itA.clear(); c->itC.clear(); c->itE.clear(); c->itF.clear(); c->itH.clear();
   c->itSA.clear(); c->itSC.clear();
+  c->kig_ptr.clear(); c->kig_col.clear();
   c->np_total = c->tp_total = 0;
   // packed symmetric blocks: forced (2), or (1) when they cut the operator bytes by a tenth or more
   // (blocks spanning several panels; a single panel holds the whole block anyway)
   c->packed = false;
   if (c->sym && c->opt.packed_sym != 0) {
     double full = 0.0, pk = 0.0;
-    for (const SubLayout& L : P.subs) {
-      full += (double)round_up(L.nI + L.nG, 4) * L.nI + (double)round_up(L.nG + L.nc, 4) * L.nG;
-      pk += (double)SymPack::elems(L.nI, L.nI + L.nG) + (double)SymPack::elems(L.nG, L.nG + L.nc);
+    for (const SubLayout& L : P.subs) {   // full: [K_II^-1; G], [D S~ D; (D Phi)^T], H; packed: G, K_II^-1, S~
+      full += (double)round_up(L.nI + L.nG, 4) * L.nI + (double)round_up(L.nG + L.nc, 4) * L.nG +
+              (double)round_up(L.nI, 4) * L.nG;
+      pk += (double)round_up(L.nG, 4) * L.nI + (double)SymPack::elems(L.nI, L.nI) +
+            (double)SymPack::elems(L.nG, L.nG + L.nc);
     }
     c->packed = c->opt.packed_sym == 2 || pk <= 0.9 * full;
   }
@@ -804,9 +846,12 @@ int build_layout(mbddc_ctx* c) {
     d.ld3 = (int32_t)round_up(nG, 4);
     d.ld4 = (int32_t)round_up(nI, 4);
     for (int q = 0; q < 2; ++q) d.oS[q] = d.oNP[q] = d.oTP[q] = -1;
+    d.oKig = d.kig_ptr = d.kig_col = -1;
     if (c->packed) {   // symmetric blocks stored once (SymPack), with their partial-product buffers
-      d.oB1 = d.oB2 = -1;
-      const int32_t nS[2] = {(int32_t)nI, (int32_t)nG}, nr[2] = {(int32_t)(nI + nG), (int32_t)(nG + nc)};
+      d.ld1 = (int32_t)round_up(nG, 4);   // G alone (column-major) for phase A
+      d.oB1 = op; op += round_up((int64_t)d.ld1 * nI, 64);
+      d.oB2 = -1;
+      const int32_t nS[2] = {(int32_t)nI, (int32_t)nG}, nr[2] = {(int32_t)nI, (int32_t)(nG + nc)};
       for (int q = 0; q < 2; ++q) {
         d.oS[q] = op;
         op += round_up(SymPack::elems(nS[q], nr[q]), 64);
@@ -825,7 +870,13 @@ int build_layout(mbddc_ctx* c) {
       d.oB2 = op; op += round_up((int64_t)d.ld2 * nG, 64);
     }
     d.oB3 = op; op += round_up((int64_t)d.ld3 * nc, 64);
-    d.oB4 = op; op += round_up((int64_t)d.ld4 * nG, 64);
+    if (c->packed) {
+      d.oB4 = -1;
+      const int64_t nnz = kig_pattern(P, L, c->kig_ptr, c->kig_col, d);
+      d.oKig = op; op += round_up(nnz, 64);
+    } else {
+      d.oB4 = op; op += round_up((int64_t)d.ld4 * nG, 64);
+    }
     d.oKc = kcl; kcl += nc * nc;
     d.oPiv = piv; piv += nI + m;
     c->max_cols = std::max<int>(c->max_cols, (int)std::max(std::max(nI, nG), nc));
@@ -990,22 +1041,32 @@ int build_layout(mbddc_ctx* c) {
   for (const SubDev& d : c->subs) {
     const double nI = d.nI, nG = d.nG, nc = d.nc, m = d.nG + d.nc;
     if (c->packed) {
-      c->op_bytes[F_APPLY_A] += eo * SymPack::elems(d.nI, d.nI + d.nG);
+      // A: G r_I; H: the slots' averages and r_I - K_IG z_G (prep), then K_II^-1 of it
+      const double nnz = (double)(c->kig_ptr[d.kig_ptr + d.nI]);
+      c->op_bytes[F_APPLY_A] += eo * d.ld1 * nI;
       c->op_bytes[F_APPLY_C] += eo * SymPack::elems(d.nG, d.nG + d.nc);
+      c->op_bytes[F_APPLY_H] += eo * SymPack::elems(d.nI, d.nI);
+      c->op_bytes[F_APPLY_HPREP] += (eo + 4.0) * nnz + 4.0 * (nI + 1);
+      c->fam_flops[F_APPLY_A] += nG * nI;
+      c->fam_flops[F_APPLY_H] += nI * nI;
+      c->fam_flops[F_APPLY_HPREP] += nnz;
+      c->vec_words[F_APPLY_A] += nI + nG;
+      c->vec_words[F_APPLY_H] += 2 * nI;
+      c->vec_words[F_APPLY_HPREP] += 3 * nG + 2 * nI;
     } else {
       c->op_bytes[F_APPLY_A] += eo * d.ld1 * nI;
       c->op_bytes[F_APPLY_C] += eo * d.ld2 * nG;
+      c->op_bytes[F_APPLY_H] += eo * d.ld4 * nG;
+      c->fam_flops[F_APPLY_A] += (nI + nG) * nI;
+      c->fam_flops[F_APPLY_H] += nI * nG;
+      c->vec_words[F_APPLY_A] += 2 * nI + nG;
+      c->vec_words[F_APPLY_H] += nG + 2 * nI;
     }
     c->op_bytes[F_APPLY_F] += eo * d.ld3 * nc;
-    c->op_bytes[F_APPLY_H] += eo * d.ld4 * nG;
-    c->fam_flops[F_APPLY_A] += (nI + nG) * nI;
     c->fam_flops[F_APPLY_C] += (nG + nc) * nG;
     c->fam_flops[F_APPLY_F] += nG * nc;
-    c->fam_flops[F_APPLY_H] += nI * nG;
-    c->vec_words[F_APPLY_A] += 2 * nI + nG;
     c->vec_words[F_APPLY_C] += 2 * nG + nG + nc;
     c->vec_words[F_APPLY_F] += nc + 2 * nG;
-    c->vec_words[F_APPLY_H] += nG + 2 * nI;
     c->fam_flops[F_GJ_KII] += 2.0 * nI * nI * nI;
     c->fam_flops[F_GJ_P] += 2.0 * m * m * m;
     c->fam_flops[F_GEMM_GH] += 4.0 * nG * nI * nI;
@@ -1093,6 +1154,10 @@ int upload_plan(mbddc_ctx* c) {
   CHK(upload(c, &c->d_itH, c->itH));
   CHK(upload(c, &c->d_itSA, c->itSA));
   CHK(upload(c, &c->d_itSC, c->itSC));
+  if (c->packed) {
+    CHK(upload(c, &c->d_kig_ptr, c->kig_ptr));
+    CHK(upload(c, &c->d_kig_col, c->kig_col));
+  }
   CHK(upload(c, &c->d_chunk_inst, c->chunk_inst));
   CHK(upload(c, &c->d_chunk_begin, c->chunk_begin));
   CHK(upload(c, &c->d_inst_chunk_off, c->inst_chunk_off));
@@ -1224,6 +1289,7 @@ int build_level2_host(mbddc_ctx* c, const std::vector<MeshIn>& fine) {
   ch->opt.levels = 2;
   ch->opt.primal = c->opt.coarse_primal;
   ch->opt.precision = MBDDC_FP64;
+  ch->opt.packed_sym = 0;   // level-2 blocks: few panels, dense couplings; the full layout's fewer launches
   ch->mixed = false;
   ch->fact32 = false;
   ch->sym = c->sym;
@@ -1265,9 +1331,13 @@ double device_bytes_estimate(const mbddc_ctx* c, bool krylov, int nrhs) {
        c->gemm_items_ssym.size() + c->gemm_items_phi.size() + c->gemm_items_stil.size());
   b += 16.0 * (c->itA.size() + c->itC.size() + c->itE.size() + c->itF.size() + c->itH.size() + c->itSA.size() +
                c->itSC.size());
-  b += 8.0 * R * (c->np_total + c->tp_total);
+  b += 8.0 * R * (c->np_total + c->tp_total) + 4.0 * (c->kig_ptr.size() + c->kig_col.size());
+  if (c->gen_large_max > 0 && c->coarse_large.empty()) {
+    const double cb = std::max(kCoarseBlock, kSymCB), ld = round_up(c->gen_large_max, 4);
+    b += 8.0 * (2 * cb * cb + 2 * cb * ld);
+  }
   if (!c->coarse_large.empty()) {
-    const double cb = std::max(kCoarseBlock, kSymCB), ld = round_up(c->coarse_max_nc, 4);
+    const double cb = std::max(kCoarseBlock, kSymCB), ld = round_up(std::max(c->coarse_max_nc, c->gen_large_max), 4);
     b += 8.0 * (2 * cb * cb + 2 * cb * ld);
   }
   if (c->big_count > 0) b += 8.0 * (c->big_pbuf + c->big_count * ((double)kSymCB * kSymCB + 1));
@@ -1734,7 +1804,8 @@ int factor_impl(mbddc_ctx* c) {
         HIPCHK(hipStreamWaitEvent(c->side, c->ev_side, 0));
         es = c->side;
       }
-      hipLaunchKernelGGL((k_extract_sym<T, To>), dim3(parts, nsub), dim3(kBlock), 0, es, c->d_subs, c->d_slot_w, W, Op);
+      hipLaunchKernelGGL((k_extract_sym<T, To>), dim3(parts, nsub), dim3(kBlock), 0, es, c->d_subs, c->d_slot_w,
+                         c->d_kig_ptr, c->d_kig_col, W, Op);
       if (es != c->stream) {
         HIPCHK(hipEventRecord(c->ev_side, c->side));
         c->side_pending = true;
@@ -1883,21 +1954,14 @@ int apply_impl(mbddc_ctx* c, const double* r, double* z, mbddc_ctx* parent = nul
   if ((4 * 256 * R + (size_t)a.xchunk * R) * sizeof(double) > 160 * 1024) return MBDDC_ERR_UNSUPPORTED;
   a.np = c->d_np;
   a.tp = c->d_tp;
+  a.kig_ptr = c->d_kig_ptr;
+  a.kig_col = c->d_kig_col;
+  a.n_slots = P.n_slots;
   {
     ProfScope ps(c, F_APPLY_A, c->op_bytes[F_APPLY_A] + 8.0 * R * c->vec_words[F_APPLY_A], 2.0 * R * c->fam_flops[F_APPLY_A]);
-    if (c->packed) {
-      a.items = c->d_itSA;
-      if (!c->itSA.empty())
-        hipLaunchKernelGGL((k_apply_sym<To, R, 0>), dim3((unsigned)c->itSA.size()), dim3(kBlock), kSymLds * R, c->stream, a);
-    } else {
-      a.items = c->d_itA;
-      launch_local<To, R, 0>(c, a, 0, c->itA.size());
-    }
-  }
-  if (c->packed) {
-    ProfScope ps(c, F_APPLY_SYMRED, 0.0, 0.0);
     a.items = c->d_itA;
-    hipLaunchKernelGGL((k_apply_sym_reduce<R, 0>), dim3((unsigned)c->itA.size()), dim3(kBlock), 0, c->stream, a);
+    if (c->packed) launch_local<To, R, 5>(c, a, 0, c->itA.size());   // G r_I alone
+    else launch_local<To, R, 0>(c, a, 0, c->itA.size());
   }
   {
     ProfScope ps(c, F_APPLY_C, c->op_bytes[F_APPLY_C] + 8.0 * R * c->vec_words[F_APPLY_C], 2.0 * R * c->fam_flops[F_APPLY_C]);
@@ -1918,7 +1982,7 @@ int apply_impl(mbddc_ctx* c, const double* r, double* z, mbddc_ctx* parent = nul
   if (c->child) {
     mbddc_ctx* ch = c->child;
     double b2 = 16.0 * R * P.n_coarse, f2 = 0.0;   // coarse gather + scatter, then the level-2 phases
-    for (int f : {F_APPLY_A, F_APPLY_C, F_APPLY_E, F_APPLY_F, F_APPLY_H}) {
+    for (int f : {F_APPLY_A, F_APPLY_C, F_APPLY_E, F_APPLY_F, F_APPLY_H, F_APPLY_HPREP}) {
       b2 += ch->op_bytes[f] + 8.0 * R * ch->vec_words[f];
       f2 += 2.0 * R * ch->fam_flops[f];
     }
@@ -1940,7 +2004,26 @@ int apply_impl(mbddc_ctx* c, const double* r, double* z, mbddc_ctx* parent = nul
     a.items = c->d_itF;
     launch_local<To, R, 3>(c, a, 2, c->itF.size());
   }
-  {
+  if (c->packed) {   // z_G, then z_I = K_II^-1 (r_I - K_IG z_G)
+    {
+      ProfScope ps(c, F_APPLY_HPREP, c->op_bytes[F_APPLY_HPREP] + 8.0 * R * c->vec_words[F_APPLY_HPREP],
+                   2.0 * R * c->fam_flops[F_APPLY_HPREP]);
+      if (P.n_slots > 0)
+        hipLaunchKernelGGL((k_h_gather<R>), dim3(nblk(P.n_slots)), dim3(kBlock), 0, c->stream, a);
+      a.items = c->d_itH;
+      hipLaunchKernelGGL((k_h_prep<To, R>), dim3((unsigned)c->itH.size()), dim3(kBlock), 0, c->stream, a);
+    }
+    {
+      ProfScope ps(c, F_APPLY_H, c->op_bytes[F_APPLY_H] + 8.0 * R * c->vec_words[F_APPLY_H],
+                   2.0 * R * c->fam_flops[F_APPLY_H]);
+      a.items = c->d_itSA;
+      if (!c->itSA.empty())
+        hipLaunchKernelGGL((k_apply_sym<To, R, 2>), dim3((unsigned)c->itSA.size()), dim3(kBlock), kSymLds * R, c->stream, a);
+    }
+    ProfScope ps(c, F_APPLY_SYMRED, 0.0, 0.0);
+    a.items = c->d_itH;
+    hipLaunchKernelGGL((k_apply_sym_reduce<R, 2>), dim3((unsigned)c->itH.size()), dim3(kBlock), 0, c->stream, a);
+  } else {
     ProfScope ps(c, F_APPLY_H, c->op_bytes[F_APPLY_H] + 8.0 * R * c->vec_words[F_APPLY_H], 2.0 * R * c->fam_flops[F_APPLY_H]);
     a.items = c->d_itH;
     launch_local<To, R, 4>(c, a, 3, c->itH.size());
@@ -1997,8 +2080,13 @@ int apply_attrs() {
     if (!e) e = set_lds(k_apply_local<To, R, 1, 1, false>, mx);
     if (!e) e = set_lds(k_apply_local<To, R, 3, 1, false>, mx);
     if (!e) e = set_lds(k_apply_local<To, R, 4, 1, false>, mx);
-    if (!e) e = set_lds(k_apply_sym<To, R, 0>, mx);
+    if (!e) e = set_lds(k_apply_local<To, R, 5, 4, false>, mx);
+    if (!e) e = set_lds(k_apply_local<To, R, 5, 2, false>, mx);
+    if (!e) e = set_lds(k_apply_local<To, R, 5, 4, true>, mx);
+    if (!e) e = set_lds(k_apply_local<To, R, 5, 2, true>, mx);
+    if (!e) e = set_lds(k_apply_local<To, R, 5, 1, false>, mx);
     if (!e) e = set_lds(k_apply_sym<To, R, 1>, mx);
+    if (!e) e = set_lds(k_apply_sym<To, R, 2>, mx);
     st = e;
   });
   return st;
@@ -2014,7 +2102,8 @@ int apply_attrs_all(int R) {
 }
 
 constexpr uint32_t kApplyFamilies = (1u << F_APPLY_A) | (1u << F_APPLY_C) | (1u << F_APPLY_E) | (1u << F_APPLY_F) |
-                                    (1u << F_APPLY_H) | (1u << F_LEVEL2_APPLY) | (1u << F_APPLY_SYMRED);
+                                    (1u << F_APPLY_H) | (1u << F_LEVEL2_APPLY) | (1u << F_APPLY_SYMRED) |
+                                    (1u << F_APPLY_HPREP);
 
 // z = M^-1 r on the handle's fixed blocks d_X -> d_Y: replayed from a captured graph
 // unless graphs are off or an apply family is being profiled.
@@ -2022,13 +2111,13 @@ constexpr uint32_t kApplyFamilies = (1u << F_APPLY_A) | (1u << F_APPLY_C) | (1u 
 // (every phase, and the level-2 application when there is one).
 void apply_totals(const mbddc_ctx* c, int R, double* bytes, double* flops) {
   double b = 0.0, f = 0.0;
-  for (int k : {F_APPLY_A, F_APPLY_C, F_APPLY_F, F_APPLY_H}) {
+  for (int k : {F_APPLY_A, F_APPLY_C, F_APPLY_F, F_APPLY_H, F_APPLY_HPREP}) {
     b += c->op_bytes[k] + 8.0 * R * c->vec_words[k];
     f += 2.0 * R * c->fam_flops[k];
   }
   if (const mbddc_ctx* ch = c->child) {
     b += 16.0 * R * c->plan.n_coarse;
-    for (int k : {F_APPLY_A, F_APPLY_C, F_APPLY_E, F_APPLY_F, F_APPLY_H}) {
+    for (int k : {F_APPLY_A, F_APPLY_C, F_APPLY_E, F_APPLY_F, F_APPLY_H, F_APPLY_HPREP}) {
       b += ch->op_bytes[k] + 8.0 * R * ch->vec_words[k];
       f += 2.0 * R * ch->fam_flops[k];
     }

@@ -47,10 +47,13 @@ struct Job {
   mbddc_request_result res{};
 };
 
-// Caching device-memory pool shared by the workers' handles. Blocks are kept by size after
-// they are returned; an allocation takes the smallest cached block of at least the requested
-// size and at most twice it, else a new hipMalloc (rounded to 2 MiB above 1 MiB). When a
-// hipMalloc fails, or the cache would hold more than `cap` bytes, cached blocks are freed.
+// Caching device-memory pool shared by the workers' handles. Sizes are rounded (4 KiB up to
+// 1 MiB, 2 MiB above) and blocks kept by rounded size after they are returned; an allocation
+// takes a cached block of exactly its rounded size, else a new hipMalloc. Exact classes make
+// reuse predictable: once a request has run, a request with the same allocation sizes finds all
+// of its blocks cached (a larger block taken for a smaller size could starve a later
+// allocation). When a hipMalloc fails, or the cache would hold more than `cap` bytes, cached
+// blocks are freed.
 struct Pool {
   int device = 0;
   size_t cap = 0;
@@ -77,8 +80,8 @@ struct Pool {
   void* alloc(size_t b) {
     b = round(b);
     std::lock_guard<std::mutex> lk(mu);
-    auto it = cache.lower_bound(b);
-    if (it != cache.end() && it->first <= 2 * b) {
+    auto it = cache.find(b);
+    if (it != cache.end()) {
       void* p = it->second;
       const size_t sz = it->first;
       cache.erase(it);
