@@ -15,6 +15,9 @@ Follows paper §3.2 ("BDDC preconditioner"):
   coarse basis) and S_PiPi = sum_i R_Pi^T Phi_i^T A^(i) Phi_i R_Pi;
 * multilevel BDDC: the coarse problem is itself approximated by one BDDC
   application (§3.2 last paragraph; §7, coarse problem on a group of 8);
+* near-null-space primals (§4, rigid motions given to BDDC as extra primal
+  degrees of freedom): on every primal edge and face the constraint rows span
+  the six rigid motions restricted to the glob (``nnsp=True``);
 * the non-symmetric formulation (§8, realistic simulation: the base pressure
   breaks the symmetry of the tangent and BDDC is told to use its non-symmetric
   form): a left coarse basis Psi from the transposed constrained problems
@@ -34,6 +37,13 @@ Readings of the paper used here (the paper is silent on them):
   |N'| >= 3 makes an edge and |N'| = 2 a face;
 * an edge/face constraint is the plain mean of one displacement component
   over the glob's nodes; a vertex constraint selects one component;
+* near-null-space rows (the paper names the option, not the construction): the
+  candidates are the translations along x, y, z, then the rotations about the
+  x, y, z axes through the centroid of the glob's nodes, restricted to the
+  glob's free DOFs; they are orthonormalised in that order by modified
+  Gram-Schmidt with one re-orthogonalisation pass, and a candidate whose norm
+  after projection is at most 1e-8 of its norm before is dropped (a straight
+  edge keeps 5 rows, a planar face 6); vertices keep their component rows;
 * vertices are weighted by delta^dagger like every interface DOF (primal
   values are single-valued, so this equals the paper's unweighted R_GammaPi);
 * clamped DOFs are eliminated from every matrix;
@@ -58,6 +68,33 @@ import scipy.sparse.csgraph as csgraph
 from . import fem
 
 VERTEX, EDGE, FACE = 1, 2, 4
+NNSP_DROP = 1e-8     # relative norm below which a rigid-motion candidate is dependent
+
+
+def rigid_motion_rows(X: np.ndarray, free: np.ndarray) -> np.ndarray:
+    """Orthonormal rows spanning the rigid motions of the nodes X (nn x 3) restricted to the free
+    entries (``free``: nn x 3 mask, entries ordered node-major), candidates in the order
+    translations x, y, z, rotations about x, y, z through the nodes' centroid (§4)."""
+    d = X - X.mean(axis=0)
+    cand = np.zeros((6, X.shape[0], 3))
+    for a in range(3):
+        cand[a, :, a] = 1.0                              # translation along axis a
+        w = np.zeros(3)
+        w[a] = 1.0
+        cand[3 + a] = np.cross(w, d)                     # rotation about axis a: w x (x - centroid)
+    Q = []
+    for v in cand.reshape(6, -1)[:, free.ravel()]:
+        n0 = np.linalg.norm(v)
+        if n0 == 0.0:
+            continue
+        for _ in range(2):
+            for q in Q:
+                v = v - (q @ v) * q
+        n1 = np.linalg.norm(v)
+        if n1 <= NNSP_DROP * n0:
+            continue
+        Q.append(v / n1)
+    return np.array(Q) if Q else np.zeros((0, int(free.sum())))
 
 
 def classify_globs(n_items: int, item_subs: list, item_tags: np.ndarray, is_interface: np.ndarray,
@@ -111,13 +148,16 @@ class Decomposition:
     weights. The level index space is the free-DOF vector (positions in ``free``)."""
 
     def __init__(self, elem_nodes, n_nodes, elem_part, n_sub, dirichlet, node_tags=None,
-                 primal: int = VERTEX, all_interface_vertices: bool = False):
+                 primal: int = VERTEX, all_interface_vertices: bool = False, coords=None, nnsp: bool = False):
         elem_nodes = np.asarray(elem_nodes, dtype=np.int64)
         elem_part = np.asarray(elem_part, dtype=np.int64)
         self.n_nodes = int(n_nodes)
         self.n_dofs = 3 * self.n_nodes
         self.n_sub = int(n_sub)
         self.primal = primal
+        self.nnsp = nnsp
+        if nnsp and coords is None:
+            raise ValueError("near-null-space primals need the node coordinates")
         free_mask = np.ones(self.n_dofs, dtype=bool)
         free_mask[np.asarray(dirichlet, dtype=np.int64)] = False
         self.free_mask = free_mask
@@ -145,12 +185,21 @@ class Decomposition:
             self.node_glob[nodes] = gi
 
         sel = (VERTEX | EDGE | FACE) if all_interface_vertices else primal
-        self.coarse = []                       # (glob, component) per coarse DOF
+        self.coarse = []                       # (glob, component) per coarse DOF; (glob, row) for nnsp globs
+        self.glob_rows = {}                    # nnsp glob -> (its free DOFs, orthonormal rows over them)
         for gi, (kind, nodes, _) in enumerate(self.globs):
-            if kind & sel:
-                for c in range(3):
-                    if free_mask[3 * nodes + c].any():
-                        self.coarse.append((gi, c))
+            if not kind & sel:
+                continue
+            if nnsp and kind != VERTEX:
+                fm = free_mask[(3 * nodes[:, None] + np.arange(3)[None, :])]
+                B = rigid_motion_rows(np.asarray(coords, dtype=np.float64)[nodes], fm)
+                dd = (3 * nodes[:, None] + np.arange(3)[None, :])[fm]
+                self.glob_rows[gi] = (dd, B)
+                self.coarse.extend((gi, k) for k in range(B.shape[0]))
+                continue
+            for c in range(3):
+                if free_mask[3 * nodes + c].any():
+                    self.coarse.append((gi, c))
         self.n_coarse = len(self.coarse)
 
         sub_coarse = [[] for _ in range(self.n_sub)]
@@ -171,12 +220,17 @@ class Decomposition:
             rows, cids = [], []
             for cid in sub_coarse[i]:
                 gi, c = self.coarse[cid]
-                gnodes = self.globs[gi][1]
-                dd = 3 * gnodes + c
-                dd = dd[free_mask[dd]]
                 row = np.zeros(len(local))
-                for d in dd:
-                    row[pos[int(d)]] = 1.0 / len(dd)
+                if gi in self.glob_rows:               # row c of the glob's rigid-motion basis
+                    dd, B = self.glob_rows[gi]
+                    for d, b in zip(dd, B[c]):
+                        row[pos[int(d)]] = b
+                else:                                  # mean of component c over the glob
+                    gnodes = self.globs[gi][1]
+                    dd = 3 * gnodes + c
+                    dd = dd[free_mask[dd]]
+                    for d in dd:
+                        row[pos[int(d)]] = 1.0 / len(dd)
                 rows.append(row)
                 cids.append(cid)
             C = np.array(rows) if rows else np.zeros((0, len(local)))
@@ -307,6 +361,8 @@ class BDDC:
             self.L1 = Level(self.A, dec.subdomains, Ks, dec.n_coarse, nonsymmetric=nonsymmetric)
             self.L2 = None
         elif levels == 3:
+            if dec.nnsp:
+                raise NotImplementedError("three levels with near-null-space primals")
             self.L1 = Level(self.A, dec.subdomains, Ks, dec.n_coarse, build_coarse=False, nonsymmetric=nonsymmetric)
             self.L2 = coarse_level(dec, self.L1, coarse_group, level2_primal, nonsymmetric)
             self.L1.coarse_solver = self.L2.apply
