@@ -125,6 +125,16 @@ typedef struct {
                                     [0; I]), so that the preconditioner of K^T is the transpose of that of
                                     K; the coarse matrix Psi^T K Phi equals Phi^T K Phi's formula -Lambda.
                                     0: Psi = Phi. Identical for symmetric tangents. */
+  int32_t nnsp;                  /* 1: near-null-space primals (§4: the rigid motions given to BDDC as
+                                    primal degrees of freedom): on every primal edge and face the
+                                    constraint rows are an orthonormal basis of the six rigid motions
+                                    restricted to the glob's free DOFs (candidates: translations x, y, z,
+                                    then rotations about x, y, z through the glob's node centroid;
+                                    modified Gram-Schmidt with one re-orthogonalisation; a candidate
+                                    left with at most 1e-8 of its norm is dropped: a straight edge keeps
+                                    5 rows, a planar face 6); vertices keep their component rows. Needs
+                                    node coordinates (MBDDC_ERR_ARG without); levels = 3 returns
+                                    MBDDC_ERR_UNSUPPORTED. 0 (default): component averages */
 } mbddc_options;
 
 typedef struct {

@@ -1289,6 +1289,7 @@ int build_level2_host(mbddc_ctx* c, const std::vector<MeshIn>& fine) {
   ch->opt.levels = 2;
   ch->opt.primal = c->opt.coarse_primal;
   ch->opt.precision = MBDDC_FP64;
+  ch->opt.nnsp = 0;
   ch->opt.packed_sym = 0;   // level-2 blocks: few panels, dense couplings; the full layout's fewer launches
   ch->mixed = false;
   ch->fact32 = false;
@@ -2749,8 +2750,9 @@ int parse_meshes(int n_inst, const mbddc_mesh* meshes, const mbddc_options* opt,
   else mbddc_default_options(&o);
   if ((o.levels != 2 && o.levels != 3) || o.coarse_group < 1 || (o.coarse_primal & ~7u) || o.restart < 1 || o.restart > 63 || !(o.rtol > 0.0) || o.max_it < 1 ||
       (o.precision != MBDDC_FP64 && o.precision != MBDDC_MIXED && o.precision != MBDDC_MIXED_F32FACT) ||
-      (o.primal & ~7u))
+      (o.primal & ~7u) || (o.nnsp != 0 && o.nnsp != 1))
     return MBDDC_ERR_ARG;
+  if (o.nnsp && o.levels == 3) return MBDDC_ERR_UNSUPPORTED;   // level-2 nodes carry three components
   ms.assign(n_inst, MeshIn());
   for (int i = 0; i < n_inst; ++i) {
     const mbddc_mesh& m = meshes[i];
@@ -2839,7 +2841,7 @@ int prepare_host(mbddc_ctx* c, const mbddc_options& o, const std::vector<MeshIn>
   c->mixed = (o.precision != MBDDC_FP64);
   c->fact32 = (o.precision == MBDDC_MIXED_F32FACT);
   c->sym = (o.symmetric_hint != 0);
-  std::string err = build_plan(ms, o.primal, c->plan);
+  std::string err = build_plan(ms, o.primal, c->plan, o.nnsp != 0);
   if (!err.empty()) return MBDDC_ERR_ARG;
   c->h_tags.clear();
   for (const MeshIn& m : ms) {

@@ -2,6 +2,7 @@
 #include "plan.hpp"
 
 #include <algorithm>
+#include <cmath>
 #include <map>
 #include <numeric>
 
@@ -27,9 +28,69 @@ struct UnionFind {
 
 int popcount32(uint32_t v) { return __builtin_popcount(v); }
 
+// Near-null-space rows of one glob (paper §4, rigid motions as primal degrees of freedom): an
+// orthonormal basis of the six rigid motions restricted to the glob's free DOFs. Candidates in
+// the order translations x, y, z, rotations about x, y, z through the centroid of the glob's
+// nodes; modified Gram-Schmidt with one re-orthogonalisation pass; a candidate left with at most
+// 1e-8 of its norm is dependent and dropped. `dofs` receives the free DOFs (node-major, global
+// ids), `rows` the r rows over them (row-major); returns r.
+int rigid_rows(const MeshIn& m, const std::vector<int32_t>& nodes, const std::vector<uint8_t>& free_dof,
+               int64_t node_off, std::vector<int32_t>& dofs, std::vector<double>& rows) {
+  double cen[3] = {0.0, 0.0, 0.0};
+  for (int32_t n : nodes)
+    for (int a = 0; a < 3; ++a) cen[a] += m.coords[3 * (int64_t)n + a];
+  for (int a = 0; a < 3; ++a) cen[a] /= (double)nodes.size();
+  std::vector<double> dx;   // d = x - centroid per free DOF's node, and the DOF's component
+  std::vector<int> comp;
+  dofs.clear();
+  for (int32_t n : nodes)
+    for (int c = 0; c < 3; ++c) {
+      const int64_t d = 3 * (node_off + n) + c;
+      if (!free_dof[d]) continue;
+      dofs.push_back((int32_t)d);
+      comp.push_back(c);
+      for (int a = 0; a < 3; ++a) dx.push_back(m.coords[3 * (int64_t)n + a] - cen[a]);
+    }
+  const size_t nd = dofs.size();
+  std::vector<std::vector<double>> Q;
+  std::vector<double> v(nd);
+  for (int k = 0; k < 6; ++k) {
+    for (size_t j = 0; j < nd; ++j) {
+      const int c = comp[j];
+      const double* d = &dx[3 * j];
+      if (k < 3) {
+        v[j] = (c == k) ? 1.0 : 0.0;
+      } else {   // (e_a x d)_c for a = k - 3
+        const int a = k - 3;
+        const int c1 = (a + 1) % 3, c2 = (a + 2) % 3;   // e_a x d = (.., -d_c2 at c1, d_c1 at c2)
+        v[j] = (c == c1) ? -d[c2] : (c == c2 ? d[c1] : 0.0);
+      }
+    }
+    double n0 = 0.0;
+    for (double x : v) n0 += x * x;
+    n0 = std::sqrt(n0);
+    if (n0 == 0.0) continue;
+    for (int pass = 0; pass < 2; ++pass)
+      for (const std::vector<double>& q : Q) {
+        double dot = 0.0;
+        for (size_t j = 0; j < nd; ++j) dot += q[j] * v[j];
+        for (size_t j = 0; j < nd; ++j) v[j] -= dot * q[j];
+      }
+    double n1 = 0.0;
+    for (double x : v) n1 += x * x;
+    n1 = std::sqrt(n1);
+    if (n1 <= 1e-8 * n0) continue;
+    for (double& x : v) x /= n1;
+    Q.push_back(v);
+  }
+  rows.clear();
+  for (const std::vector<double>& q : Q) rows.insert(rows.end(), q.begin(), q.end());
+  return (int)Q.size();
+}
+
 }  // namespace
 
-std::string build_plan(const std::vector<MeshIn>& meshes, uint32_t primal, Plan& P) {
+std::string build_plan(const std::vector<MeshIn>& meshes, uint32_t primal, Plan& P, bool nnsp) {
   P = Plan();
   P.n_inst = static_cast<int32_t>(meshes.size());
   if (P.n_inst <= 0) return "no instance";
@@ -81,6 +142,8 @@ std::string build_plan(const std::vector<MeshIn>& meshes, uint32_t primal, Plan&
   std::vector<std::vector<int32_t>> sub_coarse_ids(P.n_sub);  // global coarse ids per subdomain
   std::vector<std::vector<int32_t>> glob_nodes_all;           // global node ids per global glob
   std::vector<std::vector<int32_t>> glob_subs_all;            // global sub ids per glob
+  std::vector<std::vector<int32_t>> glob_rdofs_all;           // near-null-space globs: free DOFs
+  std::vector<std::vector<double>> glob_rows_all;             // and their rows (empty otherwise)
   std::vector<int32_t> node_deg(P.n_nodes, 0);                // |N(x)|
 
   for (int32_t ii = 0; ii < P.n_inst; ++ii) {
@@ -184,7 +247,18 @@ std::string build_plan(const std::vector<MeshIn>& meshes, uint32_t primal, Plan&
       }
       std::vector<int32_t> gsubs(nsl.begin() + nsp[n0], nsl.begin() + nsp[n0 + 1]);
       for (int32_t& s : gsubs) s += (int32_t)in.sub_off;
-      if (kind & primal) {
+      std::vector<int32_t> rdofs;
+      std::vector<double> rrows;
+      if ((kind & primal) && nnsp && kind != kVertex) {   // rows of the glob's rigid motions
+        if (m.coords.size() != 3 * (size_t)m.n_nodes) return "near-null-space primals need node coordinates";
+        const int r = rigid_rows(m, gn, P.free_dof, in.node_off, rdofs, rrows);
+        for (int k = 0; k < r; ++k) {
+          int32_t cid = (int32_t)(in.coarse_off + ncoarse++);
+          P.coarse_glob.push_back((int32_t)(in.glob_off + g));
+          P.coarse_comp.push_back(k);
+          for (int32_t s : gsubs) sub_coarse_ids[s].push_back(cid);
+        }
+      } else if (kind & primal) {
         for (int c = 0; c < 3; ++c) {
           bool any = false;
           for (int32_t nd : gglob_nodes) any |= P.free_dof[3 * (int64_t)nd + c] != 0;
@@ -195,6 +269,8 @@ std::string build_plan(const std::vector<MeshIn>& meshes, uint32_t primal, Plan&
           for (int32_t s : gsubs) sub_coarse_ids[s].push_back(cid);
         }
       }
+      glob_rdofs_all.push_back(std::move(rdofs));
+      glob_rows_all.push_back(std::move(rrows));
       glob_nodes_all.push_back(std::move(gglob_nodes));
       glob_subs_all.push_back(std::move(gsubs));
     }
@@ -270,7 +346,22 @@ std::string build_plan(const std::vector<MeshIn>& meshes, uint32_t primal, Plan&
     L.cons_off = (int64_t)P.cons_ptr.size();
     P.cons_ptr.push_back((int32_t)P.cons_idx.size());
     for (int32_t cid : cids) {
-      const std::vector<int32_t>& gn = glob_nodes_all[P.coarse_glob[cid]];
+      const int32_t gg = P.coarse_glob[cid];
+      if (!glob_rows_all[gg].empty()) {   // row coarse_comp of the glob's rigid-motion basis
+        const std::vector<int32_t>& dd = glob_rdofs_all[gg];
+        const double* row = glob_rows_all[gg].data() + (size_t)P.coarse_comp[cid] * dd.size();
+        for (size_t j = 0; j < dd.size(); ++j) {
+          if (row[j] == 0.0) continue;
+          int32_t l = local_of[dd[j]] - L.nI;
+          if (l < 0) return "internal error: constraint on an interior DOF";
+          P.cons_idx.push_back(l);
+          P.cons_w.push_back(row[j]);
+        }
+        P.cons_ptr.push_back((int32_t)P.cons_idx.size());
+        P.cslot_coarse.push_back(cid);
+        continue;
+      }
+      const std::vector<int32_t>& gn = glob_nodes_all[gg];
       int c = P.coarse_comp[cid];
       int32_t cnt = 0;
       for (int32_t nd : gn) cnt += P.free_dof[3 * (int64_t)nd + c];

@@ -68,7 +68,7 @@ struct Plan {
   std::vector<int32_t> glob_kind;
   std::vector<int32_t> glob_node0;    // first (lowest) global node of each glob
   std::vector<int32_t> node_glob;     // [n_nodes] or -1
-  std::vector<int32_t> coarse_glob, coarse_comp;   // [n_coarse]
+  std::vector<int32_t> coarse_glob, coarse_comp;   // [n_coarse] glob; component (row index for nnsp globs)
   int64_t n_vertices = 0, n_edges = 0, n_faces = 0;
 
   // assembled operator: 3x3 blocks over nodes
@@ -104,6 +104,8 @@ struct Plan {
 
 // Builds the plan for a batch of instances. Returns an empty string on success,
 // an error message otherwise.
-std::string build_plan(const std::vector<MeshIn>& meshes, uint32_t primal, Plan& out);
+// With nnsp, primal edges and faces carry near-null-space rows (their rigid motions) instead of
+// component averages; coarse_comp is then the row's index in the glob's basis.
+std::string build_plan(const std::vector<MeshIn>& meshes, uint32_t primal, Plan& out, bool nnsp = false);
 
 }  // namespace mbddc

@@ -45,7 +45,7 @@ class mbddc_options(ctypes.Structure):
                 ("max_it", ctypes.c_int32), ("symmetric_hint", ctypes.c_int32), ("tune_table", ctypes.c_char_p),
                 ("keep_coarse_matrix", ctypes.c_int32), ("coarse_primal", ctypes.c_uint32),
                 ("graph_apply", ctypes.c_int32), ("packed_sym", ctypes.c_int32),
-                ("nonsym_coarse", ctypes.c_int32)]
+                ("nonsym_coarse", ctypes.c_int32), ("nnsp", ctypes.c_int32)]
 
 
 class mbddc_info(ctypes.Structure):

@@ -138,3 +138,20 @@ def test_tuning_table_is_read_and_checked(tmp_path):
     with pytest.raises(mbddc.MbddcError) as e:
         mbddc.mbddc_estimate_footprint([m], mbddc.default_options(tune_table=str(tmp_path / "missing.json")))
     assert e.value.status == mbddc.MBDDC_ERR_ARG
+
+
+def test_nnsp_option_is_checked_on_the_host():
+    """Near-null-space primals need node coordinates and two levels; the flag is 0 or 1."""
+    P = problem("small_ve")
+    m = mbddc.mesh_from_problem(P)
+    bare = mbddc._MeshArrays(None, P.mesh.elem_nodes, P.mesh.elem_type, P.elem_part, P.n_sub, P.mesh.node_tags,
+                             P.dirichlet)
+    avg = mbddc.mbddc_estimate_footprint([m], mbddc.default_options(primal=7))
+    rows = mbddc.mbddc_estimate_footprint([m], mbddc.default_options(primal=7, nnsp=1))
+    assert rows > avg          # more coarse DOFs per edge and face
+    for mesh, kw, status in ((bare, dict(nnsp=1), mbddc.MBDDC_ERR_ARG),
+                             (m, dict(nnsp=2), mbddc.MBDDC_ERR_ARG),
+                             (m, dict(nnsp=1, levels=3), mbddc.MBDDC_ERR_UNSUPPORTED)):
+        with pytest.raises(mbddc.MbddcError) as e:
+            mbddc.mbddc_estimate_footprint([mesh], mbddc.default_options(primal=7, **kw))
+        assert e.value.status == status
