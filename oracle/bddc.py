@@ -6,7 +6,13 @@ Follows paper §3.2 ("BDDC preconditioner"):
   Gamma = U dOmega_i minus dOmega, local spaces V^(i) = V_I^(i) (+) V_Gamma^(i);
 * primal degrees of freedom associated with subdomain vertices, edges and/or
   faces (edge and face primals are averages, §3.2 and §6.2);
-* counting-function scaling delta_i^dagger = 1 / #{subdomains sharing x};
+* counting-function scaling delta_i^dagger = 1 / #{subdomains sharing x}, or the
+  deluxe scaling the paper names as the more robust option (§3.2, remark after
+  the counting function; ``scaling="deluxe"``): per glob g and subdomain i,
+  D_g^(i) = (sum_j S_g^(j))^-1 S_g^(i) with S_g^(j) the glob block of subdomain
+  j's interface Schur complement; the extension averages the local interface
+  values with these weights (the S-weighted mean), the restriction applies
+  their transposes;
 * the exact block factorisation of A^-1 through the interface Schur complement
   S_Gamma, in which BDDC replaces S_Gamma^-1 by
   M^-1_BDDC = R_{D,Gamma}^T S~_Gamma^-1 R_{D,Gamma};
@@ -141,6 +147,7 @@ class LocalSpace:
     weights: np.ndarray       # counting-function weights on the interface entries
     coarse: np.ndarray        # global coarse ids of the local primal constraints
     C: np.ndarray             # [n_c, n_i] constraint rows
+    iglob: Optional[np.ndarray] = None   # glob id of each interface entry (deluxe scaling)
 
 
 class Decomposition:
@@ -235,7 +242,8 @@ class Decomposition:
                 cids.append(cid)
             C = np.array(rows) if rows else np.zeros((0, len(local)))
             self.subdomains.append(LocalSpace(self.free_pos[local], int((~is_if).sum()), w,
-                                              np.array(cids, dtype=np.int64), C))
+                                              np.array(cids, dtype=np.int64), C,
+                                              self.node_glob[dofs[is_if] // 3]))
             self.sub_elems.append(elems)
         self.local_dofs = [self.free[s.dofs] for s in self.subdomains]   # global DOF ids
 
@@ -252,7 +260,12 @@ class Level:
     coarse solve (multilevel BDDC)."""
 
     def __init__(self, A, spaces: list, Ks: list, n_coarse: int,
-                 coarse_solver: Optional[Callable] = None, build_coarse: bool = True, nonsymmetric: bool = False):
+                 coarse_solver: Optional[Callable] = None, build_coarse: bool = True, nonsymmetric: bool = False,
+                 scaling: str = "counting"):
+        if scaling not in ("counting", "deluxe"):
+            raise ValueError("scaling is 'counting' or 'deluxe'")
+        if scaling == "deluxe" and nonsymmetric:
+            raise NotImplementedError("deluxe scaling of the non-symmetric formulation")
         self.A = A
         self.spaces = spaces
         self.n = A.shape[0]
@@ -278,6 +291,8 @@ class Level:
             self.loc.append(dict(K=Ki, KII_lu=KII_lu, N_lu=N_lu, Phi=Phi, Psi=Psi, Lam=Lam, Kc=Kci))
             interior.append(sp_.dofs[:nI])
         self.Kc = Kc
+        # interface weights: R_D restricts with D_i^T and R_D^T extends with D_i
+        self.D = [np.diag(sp_.weights) for sp_ in spaces] if scaling == "counting" else deluxe_weights(spaces, Ks)
         self.coarse_solver = coarse_solver
         self.Kc_lu = sla.lu_factor(Kc) if (n_coarse and coarse_solver is None and build_coarse) else None
         I = np.sort(np.concatenate(interior)) if interior else np.zeros(0, np.int64)
@@ -309,19 +324,19 @@ class Level:
         """M^-1_BDDC r on the interface entries of ``r`` (full level vector in and out)."""
         gc = np.zeros(self.n_coarse)
         ws = []
-        for sp_, L in zip(self.spaces, self.loc):
+        for sp_, L, D in zip(self.spaces, self.loc, self.D):
             nI, ni, nc = sp_.n_interior, len(sp_.dofs), sp_.C.shape[0]
             ri = np.zeros(ni)
-            ri[nI:] = sp_.weights * r[sp_.dofs[nI:]]              # R_D restriction
+            ri[nI:] = D.T @ r[sp_.dofs[nI:]]                      # R_D restriction
             sol = sla.lu_solve(L["N_lu"], np.concatenate([ri, np.zeros(nc)]))
             ws.append(sol[:ni])                                   # constrained local solve
             gc[sp_.coarse] += L["Psi"].T @ ri                     # Psi^T R_D r (Psi = Phi: symmetric form)
         uc = self.coarse_solve(gc) if self.n_coarse else gc
         z = np.zeros(self.n)
-        for sp_, L, w in zip(self.spaces, self.loc, ws):
+        for sp_, L, w, D in zip(self.spaces, self.loc, ws, self.D):
             nI = sp_.n_interior
             w = w + L["Phi"] @ uc[sp_.coarse]
-            np.add.at(z, sp_.dofs[nI:], sp_.weights * w[nI:])    # R_D^T
+            np.add.at(z, sp_.dofs[nI:], D @ w[nI:])               # R_D^T
         return z
 
     def apply(self, r: np.ndarray) -> np.ndarray:
@@ -338,6 +353,27 @@ class Level:
         return z
 
 
+def deluxe_weights(spaces: list, Ks: list) -> list:
+    """Deluxe scaling (§3.2 remark): per subdomain the block-diagonal matrix D_i on its interface
+    entries with blocks D_g^(i) = (sum_j S_g^(j))^-1 S_g^(i), S_g^(j) the rows and columns of glob g
+    in subdomain j's interface Schur complement S^(j) = A_GG - A_GI A_II^-1 A_IG. The entries of a
+    glob appear in the same (ascending DOF) order in every subdomain that shares it."""
+    S = []
+    for sp_, K in zip(spaces, Ks):
+        nI = sp_.n_interior
+        S.append(K[nI:, nI:] - K[nI:, :nI] @ np.linalg.solve(K[:nI, :nI], K[:nI, nI:]) if nI else K.copy())
+    members = {}
+    for i, sp_ in enumerate(spaces):
+        for g in np.unique(sp_.iglob):
+            members.setdefault(int(g), []).append((i, np.nonzero(sp_.iglob == g)[0]))
+    D = [np.zeros_like(Si) for Si in S]
+    for g, lst in members.items():
+        T = sum(S[i][np.ix_(p, p)] for i, p in lst)
+        for i, p in lst:
+            D[i][np.ix_(p, p)] = np.linalg.solve(T, S[i][np.ix_(p, p)])
+    return D
+
+
 def local_matrices(dec: Decomposition, elem_nodes, Ke) -> list:
     """A^(i) = sum of the subdomain's element matrices on its local free DOFs."""
     out = []
@@ -351,19 +387,20 @@ class BDDC:
     """Two-level (``levels=2``) or three-level (``levels=3``) BDDC on the free-DOF operator."""
 
     def __init__(self, dec: Decomposition, elem_nodes, Ke, levels: int = 2, coarse_group: int = 8,
-                 level2_primal: int = VERTEX | EDGE | FACE, nonsymmetric: bool = False):
+                 level2_primal: int = VERTEX | EDGE | FACE, nonsymmetric: bool = False, scaling: str = "counting"):
         self.dec = dec
         K = fem.assemble(elem_nodes, Ke, dec.n_dofs)
         self.A = fem.reduce_to_free(K, dec.free)
         Ks = local_matrices(dec, elem_nodes, Ke)
         self.levels = levels
         if levels == 2:
-            self.L1 = Level(self.A, dec.subdomains, Ks, dec.n_coarse, nonsymmetric=nonsymmetric)
+            self.L1 = Level(self.A, dec.subdomains, Ks, dec.n_coarse, nonsymmetric=nonsymmetric, scaling=scaling)
             self.L2 = None
         elif levels == 3:
             if dec.nnsp:
                 raise NotImplementedError("three levels with near-null-space primals")
-            self.L1 = Level(self.A, dec.subdomains, Ks, dec.n_coarse, build_coarse=False, nonsymmetric=nonsymmetric)
+            self.L1 = Level(self.A, dec.subdomains, Ks, dec.n_coarse, build_coarse=False, nonsymmetric=nonsymmetric,
+                            scaling=scaling)
             self.L2 = coarse_level(dec, self.L1, coarse_group, level2_primal, nonsymmetric)
             self.L1.coarse_solver = self.L2.apply
         else:
