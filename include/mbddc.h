@@ -60,6 +60,8 @@ enum { MBDDC_PRIMAL_V = 1, MBDDC_PRIMAL_E = 2, MBDDC_PRIMAL_F = 4 }; /* §6.2 pr
  * GMRES iterations (the FP32 local inverses are less accurate) and is outside
  * the oracle + 2 iteration contract of MBDDC_MIXED. */
 enum { MBDDC_FP64 = 0, MBDDC_MIXED = 1, MBDDC_MIXED_F32FACT = 2 };
+/* interface scaling of the averaging operator (mbddc_options.scaling) */
+enum { MBDDC_SCALING_COUNTING = 0, MBDDC_SCALING_DELUXE = 1 };
 
 typedef struct mbddc_ctx mbddc_ctx;
 
@@ -135,6 +137,17 @@ typedef struct {
                                     5 rows, a planar face 6); vertices keep their component rows. Needs
                                     node coordinates (MBDDC_ERR_ARG without); levels = 3 returns
                                     MBDDC_ERR_UNSUPPORTED. 0 (default): component averages */
+  int32_t scaling;               /* interface weights of the averaging operator R_D (§3.2):
+                                    MBDDC_SCALING_COUNTING (default) the pseudo-inverse of the counting
+                                    function; MBDDC_SCALING_DELUXE the deluxe scaling named there as the
+                                    more robust option: per glob g and subdomain i the block
+                                    D_g^(i) = (sum_j S_g^(j))^-1 S_g^(i) of the glob's rows and columns of
+                                    the interface Schur complements, the extension averaging with D and
+                                    the restriction applying D^T (computed in the factorisation, folded
+                                    into the stored operators: the application costs the same).
+                                    Symmetric path with FP64 local factors only (symmetric_hint = 1,
+                                    precision FP64 or MIXED), else MBDDC_ERR_UNSUPPORTED; level 2 of a
+                                    three-level handle keeps the counting function */
 } mbddc_options;
 
 typedef struct {

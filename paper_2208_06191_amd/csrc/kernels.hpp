@@ -108,6 +108,20 @@ struct GemmItem {
   int32_t prob, tm, tn, pad;
 };
 
+// Deluxe scaling: one block per (subdomain, glob of its interface): the glob's n entries at
+// idx[idx_off ..] (interface-local, ascending DOF), its n x n blocks S_g^(i) and D_g^(i) at off of
+// their buffers, and the glob's summed block at toff.
+struct DlxBlock {
+  int64_t off, idx_off, toff;
+  int32_t n, sub;
+};
+// A glob shared for deluxe scaling: its summed block (n x n) at toff, its blocks at
+// gblk[first .. first + count) (ascending subdomain).
+struct DlxGlob {
+  int64_t toff;
+  int32_t n, first, count, pad;
+};
+
 // Apply work item: (subdomain or instance, first row, first column, column count).
 struct ApplyItem {
   int32_t sub, row0, col0, ncol;

@@ -26,6 +26,7 @@
 #include <memory>
 #include <new>
 #include <string>
+#include <map>
 #include <type_traits>
 #include <vector>
 
@@ -76,14 +77,14 @@ enum Family {
   F_COARSE_ASSEMBLE, F_COARSE_GJ_SMALL, F_COARSE_DIAG, F_COARSE_PREP, F_COARSE_GEMM, F_COARSE_ROWS,
   F_APPLY_A, F_APPLY_C, F_APPLY_E, F_APPLY_F, F_APPLY_H, F_SPMV, F_KRYLOV_DOTS, F_KRYLOV_UPDATE,
   F_KRYLOV_SMALL, F_KRYLOV_VEC, F_LEVEL2_SETUP, F_LEVEL2_APPLY, F_APPLY_WHOLE, F_ELEMENT, F_APPLY_SYMRED,
-  F_APPLY_HPREP, F_COUNT
+  F_APPLY_HPREP, F_DELUXE, F_COUNT
 };
 const char* const kFamilyName[F_COUNT] = {
   "assemble_bsr", "assemble_local", "gj_interior", "gemm_condense", "gemm_schur", "constraints", "gj_interface",
   "extract_operators", "coarse_assemble", "coarse_gj_small", "coarse_gj_diag", "coarse_gj_prep", "coarse_gj_gemm",
   "coarse_gj_rows", "apply_A_interior", "apply_C_interface", "apply_E_coarse", "apply_F_coarse_ext",
   "apply_H_average", "spmv_bsr", "krylov_dots", "krylov_update", "krylov_small", "krylov_vectors",
-  "level2_setup", "apply_E_level2", "apply_whole", "element_tangents", "apply_sym_reduce", "apply_H_prep"};
+  "level2_setup", "apply_E_level2", "apply_whole", "element_tangents", "apply_sym_reduce", "apply_H_prep", "deluxe_scaling"};
 
 struct Profiler {
   uint32_t mask = 0;
@@ -268,7 +269,7 @@ struct mbddc_ctx {
   std::vector<GemmItem> gemm_items_gh, gemm_items_s, gemm_items_g, gemm_items_ssym, gemm_items_phi, gemm_items_stil;
   std::vector<GjDesc> gj_x;                          // (S + rho C^T C) blocks of the symmetric path
   std::vector<GjDesc> gj_t;                          // T = C X C^T blocks too large for LDS (symmetric path)
-  SymSet set_kii, set_x, set_t;                      // symmetric path: the three inversion families
+  SymSet set_kii, set_x, set_t, set_dlx;                      // symmetric path: the three inversion families
   Tuning tune;                                       // kernel variants (tuning table or defaults)
   int32_t apply_rows_eff[4] = {256, 256, 256, 256};  // rows per workgroup of apply phases A, C, F, H
   int64_t big_pbuf = 0, big_count = 0;               // batched blocked sweep: panel elements, matrices
@@ -317,6 +318,23 @@ struct mbddc_ctx {
   ApplyItem *d_itSA = nullptr, *d_itSC = nullptr;
   std::vector<int32_t> kig_ptr, kig_col;   // K_IG rows of the packed path's phase H (SubDev::kig_*)
   int32_t *d_kig_ptr = nullptr, *d_kig_col = nullptr;
+  // deluxe scaling: blocks per (subdomain, glob) and shared globs (DlxBlock / DlxGlob), each
+  // interface slot's block and position in it, per-subdomain scratch offsets, the sweep set of
+  // the summed blocks and the GEMM items of D = (sum S)^-1 S
+  bool deluxe = false;
+  std::vector<DlxBlock> dlx_blk;
+  std::vector<DlxGlob> dlx_glob;
+  std::vector<int32_t> dlx_idx, dlx_gblk, dlx_ent_blk, dlx_ent_pos;
+  std::vector<int64_t> dlx_tmp_off;
+  int64_t dlx_s_elems = 0, dlx_t_elems = 0, dlx_tmp_elems = 0;
+  std::vector<GjDesc> gj_dlx;
+  std::vector<GemmItem> gemm_items_dlx;
+  DlxBlock* d_dlx_blk = nullptr;
+  DlxGlob* d_dlx_glob = nullptr;
+  int32_t *d_dlx_idx = nullptr, *d_dlx_gblk = nullptr, *d_dlx_ent_blk = nullptr, *d_dlx_ent_pos = nullptr;
+  int64_t* d_dlx_tmp_off = nullptr;
+  double *d_dlx_S = nullptr, *d_dlx_D = nullptr, *d_dlx_T = nullptr, *d_dlx_tmp = nullptr, *d_ones = nullptr;
+  GemmItem* d_gemm_dlx = nullptr;
   int64_t np_total = 0, tp_total = 0;
   double *d_np = nullptr, *d_tp = nullptr;
   int32_t *d_chunk_inst = nullptr, *d_inst_chunk_off = nullptr;
@@ -604,13 +622,16 @@ void clear_pointers(mbddc_ctx* c) {
   cl(c->d_its);
   cl(c->d_active);
   cl(c->d_mode);
-  for (SymSet* S : {&c->set_kii, &c->set_x, &c->set_t}) {
+  for (SymSet* S : {&c->set_kii, &c->set_x, &c->set_t, &c->set_dlx}) {
     cl(S->d_all); cl(S->d_big); cl(S->d_items); cl(S->d_gd); cl(S->d_gitems);
   }
   cl(c->d_coords); cl(c->d_u); cl(c->d_frames); cl(c->d_fe); cl(c->d_fint); cl(c->d_elem_nodes);
   cl(c->d_elem_node_off); cl(c->d_elem_mat); cl(c->d_mats); cl(c->d_el_list[0]); cl(c->d_el_list[1]);
   cl(c->d_fe_off); cl(c->d_ne_ptr); cl(c->d_ne_ent);
   cl(c->d_itSA); cl(c->d_itSC); cl(c->d_np); cl(c->d_tp); cl(c->d_kig_ptr); cl(c->d_kig_col);
+  cl(c->d_dlx_blk); cl(c->d_dlx_glob); cl(c->d_dlx_idx); cl(c->d_dlx_gblk); cl(c->d_dlx_ent_blk);
+  cl(c->d_dlx_ent_pos); cl(c->d_dlx_tmp_off); cl(c->d_dlx_S); cl(c->d_dlx_D); cl(c->d_dlx_T); cl(c->d_dlx_tmp);
+  cl(c->d_ones); cl(c->d_gemm_dlx);
   cl(c->d_bc_items[0]); cl(c->d_bc_items[1]); cl(c->d_bc_end[0]); cl(c->d_bc_end[1]); cl(c->d_faces);
   cl(c->d_bcs);
   c->piv_gemm.clear();
@@ -786,6 +807,71 @@ void build_apply_items(mbddc_ctx* c) {
   }
 }
 
+// Deluxe scaling layout: the glob blocks of every subdomain's interface (entries in interface
+// order, i.e. ascending DOF, so that the subdomains sharing a glob list it alike), the shared
+// globs with their summed blocks, and the GEMMs D_g^(i) = (sum_j S_g^(j))^-1 S_g^(i).
+int build_deluxe(mbddc_ctx* c) {
+  const Plan& P = c->plan;
+  c->dlx_blk.clear(); c->dlx_glob.clear(); c->dlx_idx.clear(); c->dlx_gblk.clear();
+  c->dlx_ent_blk.clear(); c->dlx_ent_pos.clear(); c->dlx_tmp_off.clear(); c->gj_dlx.clear();
+  c->gemm_items_dlx.clear();
+  c->dlx_s_elems = c->dlx_t_elems = c->dlx_tmp_elems = 0;
+  if (!c->deluxe) return MBDDC_OK;
+  if (!c->sym || c->fact32) return MBDDC_ERR_UNSUPPORTED;
+  c->dlx_ent_blk.assign(P.n_slots, -1);
+  c->dlx_ent_pos.assign(P.n_slots, -1);
+  std::map<int32_t, std::vector<int32_t>> members;   // glob -> its blocks
+  for (int64_t s = 0; s < P.n_sub; ++s) {
+    const SubDev& d = c->subs[s];
+    std::map<int32_t, std::vector<int32_t>> pos;
+    for (int32_t j = 0; j < d.nG; ++j) {
+      const int32_t g = P.node_glob[P.slot_dof[d.if_off + j] / 3];
+      if (g < 0) return MBDDC_ERR_ARG;
+      pos[g].push_back(j);
+    }
+    for (auto& kv : pos) {
+      const int32_t id = (int32_t)c->dlx_blk.size(), n = (int32_t)kv.second.size();
+      DlxBlock b{};
+      b.off = c->dlx_s_elems; b.idx_off = (int64_t)c->dlx_idx.size(); b.toff = -1; b.n = n; b.sub = (int32_t)s;
+      c->dlx_s_elems += (int64_t)n * n;
+      for (int32_t k = 0; k < n; ++k) {
+        c->dlx_idx.push_back(kv.second[k]);
+        c->dlx_ent_blk[d.if_off + kv.second[k]] = id;
+        c->dlx_ent_pos[d.if_off + kv.second[k]] = k;
+      }
+      c->dlx_blk.push_back(b);
+      members[kv.first].push_back(id);
+    }
+    c->dlx_tmp_off.push_back(c->dlx_tmp_elems);
+    c->dlx_tmp_elems += std::max<int64_t>((int64_t)d.nG * d.nG, (int64_t)d.nG * d.nc);
+  }
+  for (auto& kv : members) {
+    DlxGlob g{};
+    g.toff = c->dlx_t_elems; g.n = c->dlx_blk[kv.second[0]].n;
+    g.first = (int32_t)c->dlx_gblk.size(); g.count = (int32_t)kv.second.size();
+    const int32_t gid = (int32_t)c->dlx_glob.size();
+    c->dlx_t_elems += (int64_t)g.n * g.n;
+    for (int32_t b : kv.second) {
+      if (c->dlx_blk[b].n != g.n) return MBDDC_ERR_ARG;   // a glob seen with different sizes
+      c->dlx_blk[b].toff = g.toff;
+      c->dlx_gblk.push_back(b);
+    }
+    c->dlx_glob.push_back(g);
+    c->gj_dlx.push_back({g.toff, g.n, g.n, 0, gid, 0});
+  }
+  for (const DlxBlock& b : c->dlx_blk) {   // D = T^-1 S: A from the summed blocks, B and C the blocks
+    GemmDesc gd{};
+    gd.M = b.n; gd.N = b.n; gd.K = b.n; gd.lda = b.n; gd.ldb = b.n; gd.ldc = b.n; gd.ldci = b.n;
+    gd.oA = b.toff; gd.oB = b.off; gd.oC = b.off; gd.oCi = b.off; gd.alpha = 1.0; gd.beta = 0.0;
+    gd.tiles_n = (b.n + 63) / 64;
+    const int32_t id = (int32_t)c->gemm_desc.size();
+    c->gemm_desc.push_back(gd);
+    for (int32_t a = 0; a < (b.n + 63) / 64; ++a)
+      for (int32_t t = 0; t < gd.tiles_n; ++t) c->gemm_items_dlx.push_back({id, a, t, 0});
+  }
+  return MBDDC_OK;
+}
+
 int build_layout(mbddc_ctx* c) {
   const Plan& P = c->plan;
   c->subs.assign(P.n_sub, SubDev{});
@@ -951,11 +1037,16 @@ int build_layout(mbddc_ctx* c) {
   add_items(dSs, c->gemm_items_ssym);
   add_items(dPhi, c->gemm_items_phi);
   add_items(dStil, c->gemm_items_stil);
+  CHK(build_deluxe(c));
   if (c->sym && !(c->set_kii.build(c->gj_kii, c->fact32, c->tune) && c->set_x.build(c->gj_x, c->fact32, c->tune) &&
-                  c->set_t.build(c->gj_t, c->fact32, c->tune)))
+                  c->set_t.build(c->gj_t, c->fact32, c->tune) && c->set_dlx.build(c->gj_dlx, false, c->tune)))
     return MBDDC_ERR_UNSUPPORTED;
-  c->big_pbuf = std::max(std::max(c->set_kii.pbuf_elems, c->set_x.pbuf_elems), c->set_t.pbuf_elems);
-  c->big_count = (int64_t)std::max(std::max(c->set_kii.big.size(), c->set_x.big.size()), c->set_t.big.size());
+  c->big_pbuf = 0;
+  c->big_count = 0;
+  for (const SymSet* S : {&c->set_kii, &c->set_x, &c->set_t, &c->set_dlx}) {
+    c->big_pbuf = std::max(c->big_pbuf, S->pbuf_elems);
+    c->big_count = std::max(c->big_count, (int64_t)S->big.size());
+  }
   c->w_elems = w;
   c->op_elems = op;
   c->kcl_elems = kcl;
@@ -1139,7 +1230,7 @@ int upload_plan(mbddc_ctx* c) {
   CHK(upload(c, &c->d_gemm_stil, c->gemm_items_stil));
   CHK(upload(c, &c->d_gj_x, c->gj_x));
   CHK(upload(c, &c->d_gj_t, c->gj_t));
-  for (SymSet* S : {&c->set_kii, &c->set_x, &c->set_t}) {
+  for (SymSet* S : {&c->set_kii, &c->set_x, &c->set_t, &c->set_dlx}) {
     CHK(upload(c, &S->d_all, S->all));
     CHK(upload(c, &S->d_big, S->big));
     CHK(upload(c, &S->d_items, S->items));
@@ -1158,6 +1249,21 @@ int upload_plan(mbddc_ctx* c) {
     CHK(upload(c, &c->d_kig_ptr, c->kig_ptr));
     CHK(upload(c, &c->d_kig_col, c->kig_col));
   }
+  if (c->deluxe) {
+    CHK(upload(c, &c->d_dlx_blk, c->dlx_blk));
+    CHK(upload(c, &c->d_dlx_glob, c->dlx_glob));
+    CHK(upload(c, &c->d_dlx_idx, c->dlx_idx));
+    CHK(upload(c, &c->d_dlx_gblk, c->dlx_gblk));
+    CHK(upload(c, &c->d_dlx_ent_blk, c->dlx_ent_blk));
+    CHK(upload(c, &c->d_dlx_ent_pos, c->dlx_ent_pos));
+    CHK(upload(c, &c->d_dlx_tmp_off, c->dlx_tmp_off));
+    CHK(upload(c, &c->d_gemm_dlx, c->gemm_items_dlx));
+    CHK(upload(c, &c->d_ones, std::vector<double>(std::max<int64_t>(P.n_slots, 1), 1.0)));
+    CHK(dalloc(c, &c->d_dlx_S, std::max<int64_t>(c->dlx_s_elems, 1)));
+    CHK(dalloc(c, &c->d_dlx_D, std::max<int64_t>(c->dlx_s_elems, 1)));
+    CHK(dalloc(c, &c->d_dlx_T, std::max<int64_t>(c->dlx_t_elems, 1)));
+    CHK(dalloc(c, &c->d_dlx_tmp, std::max<int64_t>(c->dlx_tmp_elems, 1)));
+  }
   CHK(upload(c, &c->d_chunk_inst, c->chunk_inst));
   CHK(upload(c, &c->d_chunk_begin, c->chunk_begin));
   CHK(upload(c, &c->d_inst_chunk_off, c->inst_chunk_off));
@@ -1171,7 +1277,8 @@ int upload_plan(mbddc_ctx* c) {
   CHK(dalloc(c, &c->d_Kc, c->opt.levels == 3 ? 1 : c->kc_elems));
   if (c->opt.keep_coarse_matrix) CHK(dalloc(c, &c->d_Kc_keep, c->kc_elems));
   CHK(dalloc(c, &c->d_piv, c->piv_elems));
-  c->status_len = std::max<int64_t>(P.n_sub, (int64_t)c->gj_coarse_small.size()) + 1;
+  c->status_len = std::max<int64_t>(std::max<int64_t>(P.n_sub, (int64_t)c->gj_coarse_small.size()),
+                                    (int64_t)c->gj_dlx.size()) + 1;
   CHK(dalloc(c, &c->d_status, c->status_len));
   CHK(dalloc(c, &c->d_piv_c, std::max<int64_t>(std::max<int64_t>(P.n_coarse, std::max(c->coarse_max_nc,
                                                                                           c->gen_large_max)), 1)));
@@ -1290,6 +1397,7 @@ int build_level2_host(mbddc_ctx* c, const std::vector<MeshIn>& fine) {
   ch->opt.primal = c->opt.coarse_primal;
   ch->opt.precision = MBDDC_FP64;
   ch->opt.nnsp = 0;
+  ch->opt.scaling = MBDDC_SCALING_COUNTING;
   ch->opt.packed_sym = 0;   // level-2 blocks: few panels, dense couplings; the full layout's fewer launches
   ch->mixed = false;
   ch->fact32 = false;
@@ -1333,6 +1441,10 @@ double device_bytes_estimate(const mbddc_ctx* c, bool krylov, int nrhs) {
   b += 16.0 * (c->itA.size() + c->itC.size() + c->itE.size() + c->itF.size() + c->itH.size() + c->itSA.size() +
                c->itSC.size());
   b += 8.0 * R * (c->np_total + c->tp_total) + 4.0 * (c->kig_ptr.size() + c->kig_col.size());
+  if (c->deluxe)
+    b += 8.0 * (2.0 * c->dlx_s_elems + c->dlx_t_elems + c->dlx_tmp_elems + c->dlx_tmp_off.size() + P.n_slots) +
+         4.0 * (c->dlx_idx.size() + c->dlx_gblk.size() + 2.0 * P.n_slots) + 32.0 * c->dlx_blk.size() +
+         24.0 * c->dlx_glob.size() + 48.0 * c->dlx_blk.size() + 16.0 * c->gemm_items_dlx.size();
   if (c->gen_large_max > 0 && c->coarse_large.empty()) {
     const double cb = std::max(kCoarseBlock, kSymCB), ld = round_up(c->gen_large_max, 4);
     b += 8.0 * (2 * cb * cb + 2 * cb * ld);
@@ -1342,7 +1454,7 @@ double device_bytes_estimate(const mbddc_ctx* c, bool krylov, int nrhs) {
     b += 8.0 * (2 * cb * cb + 2 * cb * ld);
   }
   if (c->big_count > 0) b += 8.0 * (c->big_pbuf + c->big_count * ((double)kSymCB * kSymCB + 1));
-  for (const SymSet* S : {&c->set_kii, &c->set_x, &c->set_t})
+  for (const SymSet* S : {&c->set_kii, &c->set_x, &c->set_t, &c->set_dlx})
     b += 32.0 * S->all.size() + 24.0 * S->big.size() + 8.0 * S->items.size() + 64.0 * S->gd.size() +
          16.0 * S->gitems.size();
   b += 8.0 * R * (2.0 * P.n_slots + std::max<int64_t>(P.n_cslots, 1) + c->nchunk_max * std::max<int64_t>(P.n_coarse, 1));
@@ -1703,6 +1815,51 @@ int run_gj_large(mbddc_ctx* c, T* W, const std::vector<GjDesc>& descs, int fam, 
   return MBDDC_OK;
 }
 
+// Deluxe weights from the Schur complements in the X blocks (before their augmentation): the glob
+// blocks, their sums per glob, the sums' inverses and D = (sum S)^-1 S per block.
+template <typename T>
+int deluxe_weights(mbddc_ctx* c, T* W) {
+  const unsigned nb = (unsigned)c->dlx_blk.size(), ng = (unsigned)c->dlx_glob.size();
+  if (nb == 0) return MBDDC_OK;
+  ProfScope ps(c, F_DELUXE, 0.0, 0.0);
+  hipLaunchKernelGGL((k_dlx_gather<T>), dim3(nb), dim3(kBlock), 0, c->stream, c->d_subs, c->d_dlx_blk, c->d_dlx_idx,
+                     W, c->d_dlx_S);
+  hipLaunchKernelGGL(k_dlx_sum, dim3(ng), dim3(kBlock), 0, c->stream, c->d_dlx_glob, c->d_dlx_gblk, c->d_dlx_blk,
+                     c->d_dlx_S, c->d_dlx_T);
+  HIPCHK(hipGetLastError());
+  CHK(run_symset<double>(c, c->d_dlx_T, c->set_dlx));
+  int bad = 0;
+  const int st = check_status(c, (int64_t)c->set_dlx.all.size(), c->set_dlx.all, &bad);
+  if (st) {
+    c->last_bad = -1;
+    return st;
+  }
+  launch_gemm<double>(c, (unsigned)c->gemm_items_dlx.size(), c->stream, c->d_gemm_desc, c->d_gemm_dlx, c->d_dlx_T,
+                      c->d_dlx_S, c->d_dlx_D, c->d_dlx_D);
+  HIPCHK(hipGetLastError());
+  return MBDDC_OK;
+}
+
+// S~ <- D S~ D^T and Phi <- D Phi per subdomain (through its scratch block).
+template <typename T>
+int deluxe_apply(mbddc_ctx* c, T* W) {
+  if (c->dlx_blk.empty()) return MBDDC_OK;
+  ProfScope ps(c, F_DELUXE, 0.0, 0.0);
+  int64_t mx = 1;
+  for (const SubDev& d : c->subs) mx = std::max<int64_t>(mx, (int64_t)d.nG * d.nG);
+  const dim3 g((unsigned)std::min<int64_t>(64, (mx + 4 * kBlock - 1) / (4 * kBlock)), (unsigned)c->plan.n_sub);
+  hipLaunchKernelGGL((k_dlx_right<T>), g, dim3(kBlock), 0, c->stream, c->d_subs, c->d_dlx_blk, c->d_dlx_idx,
+                     c->d_dlx_ent_blk, c->d_dlx_ent_pos, c->d_dlx_D, W, c->d_dlx_tmp, c->d_dlx_tmp_off);
+  hipLaunchKernelGGL((k_dlx_left<T>), g, dim3(kBlock), 0, c->stream, c->d_subs, c->d_dlx_blk, c->d_dlx_idx,
+                     c->d_dlx_ent_blk, c->d_dlx_ent_pos, c->d_dlx_D, W, c->d_dlx_tmp, c->d_dlx_tmp_off);
+  hipLaunchKernelGGL((k_dlx_phi<T, 0>), g, dim3(kBlock), 0, c->stream, c->d_subs, c->d_dlx_blk, c->d_dlx_idx,
+                     c->d_dlx_ent_blk, c->d_dlx_ent_pos, c->d_dlx_D, W, c->d_dlx_tmp, c->d_dlx_tmp_off);
+  hipLaunchKernelGGL((k_dlx_phi<T, 1>), g, dim3(kBlock), 0, c->stream, c->d_subs, c->d_dlx_blk, c->d_dlx_idx,
+                     c->d_dlx_ent_blk, c->d_dlx_ent_pos, c->d_dlx_D, W, c->d_dlx_tmp, c->d_dlx_tmp_off);
+  HIPCHK(hipGetLastError());
+  return MBDDC_OK;
+}
+
 template <typename T, typename To>
 int factor_impl(mbddc_ctx* c) {
   const Plan& P = c->plan;
@@ -1747,6 +1904,7 @@ int factor_impl(mbddc_ctx* c) {
   }
   HIPCHK(hipGetLastError());
   if (c->sym) {
+    if (c->deluxe) CHK(deluxe_weights<T>(c, W));
     // [S C^T; C 0]^-1 through X = (S + rho C^T C)^-1 and the constraint Schur complement
     {
       ProfScope ps(c, F_CONSTRAINTS, 0.0, 0.0);
@@ -1788,6 +1946,7 @@ int factor_impl(mbddc_ctx* c) {
       if (!c->gemm_items_stil.empty())
         launch_gemm<T>(c, (unsigned)c->gemm_items_stil.size(),
                            c->stream, c->d_gemm_desc, c->d_gemm_stil, W, W, W, W);
+      if (c->deluxe) CHK(deluxe_apply<T>(c, W));   // weights folded into S~ and Phi (extracted unweighted)
       const unsigned parts = (unsigned)std::min(64, std::max(1, (c->max_cols + 127) / 128));
       // the apply operators are not needed by the coarse problem: unless its families or the
       // extraction are being timed, they are written on a side stream while the coarse problem
@@ -1805,8 +1964,8 @@ int factor_impl(mbddc_ctx* c) {
         HIPCHK(hipStreamWaitEvent(c->side, c->ev_side, 0));
         es = c->side;
       }
-      hipLaunchKernelGGL((k_extract_sym<T, To>), dim3(parts, nsub), dim3(kBlock), 0, es, c->d_subs, c->d_slot_w,
-                         c->d_kig_ptr, c->d_kig_col, W, Op);
+      hipLaunchKernelGGL((k_extract_sym<T, To>), dim3(parts, nsub), dim3(kBlock), 0, es, c->d_subs,
+                         c->deluxe ? c->d_ones : c->d_slot_w, c->d_kig_ptr, c->d_kig_col, W, Op);
       if (es != c->stream) {
         HIPCHK(hipEventRecord(c->ev_side, c->side));
         c->side_pending = true;
@@ -2750,8 +2909,12 @@ int parse_meshes(int n_inst, const mbddc_mesh* meshes, const mbddc_options* opt,
   else mbddc_default_options(&o);
   if ((o.levels != 2 && o.levels != 3) || o.coarse_group < 1 || (o.coarse_primal & ~7u) || o.restart < 1 || o.restart > 63 || !(o.rtol > 0.0) || o.max_it < 1 ||
       (o.precision != MBDDC_FP64 && o.precision != MBDDC_MIXED && o.precision != MBDDC_MIXED_F32FACT) ||
-      (o.primal & ~7u) || (o.nnsp != 0 && o.nnsp != 1))
+      (o.primal & ~7u) || (o.nnsp != 0 && o.nnsp != 1) ||
+      (o.scaling != MBDDC_SCALING_COUNTING && o.scaling != MBDDC_SCALING_DELUXE))
     return MBDDC_ERR_ARG;
+  // deluxe scaling: symmetric path with FP64 local factors
+  if (o.scaling == MBDDC_SCALING_DELUXE && (o.symmetric_hint == 0 || o.precision == MBDDC_MIXED_F32FACT))
+    return MBDDC_ERR_UNSUPPORTED;
   if (o.nnsp && o.levels == 3) return MBDDC_ERR_UNSUPPORTED;   // level-2 nodes carry three components
   ms.assign(n_inst, MeshIn());
   for (int i = 0; i < n_inst; ++i) {
@@ -2841,6 +3004,7 @@ int prepare_host(mbddc_ctx* c, const mbddc_options& o, const std::vector<MeshIn>
   c->mixed = (o.precision != MBDDC_FP64);
   c->fact32 = (o.precision == MBDDC_MIXED_F32FACT);
   c->sym = (o.symmetric_hint != 0);
+  c->deluxe = (o.scaling == MBDDC_SCALING_DELUXE);
   std::string err = build_plan(ms, o.primal, c->plan, o.nnsp != 0);
   if (!err.empty()) return MBDDC_ERR_ARG;
   c->h_tags.clear();
@@ -2868,22 +3032,24 @@ int factor_dispatch(mbddc_ctx* c) {
 // (and the level-2 child's).
 int rebuild_symsets(mbddc_ctx* c) {
   if (c->sym) {
-    for (SymSet* S : {&c->set_kii, &c->set_x, &c->set_t}) {
+    for (SymSet* S : {&c->set_kii, &c->set_x, &c->set_t, &c->set_dlx}) {
       dfree(c, S->d_all); dfree(c, S->d_big); dfree(c, S->d_items); dfree(c, S->d_gd); dfree(c, S->d_gitems);
     }
     if (!(c->set_kii.build(c->gj_kii, c->fact32, c->tune) && c->set_x.build(c->gj_x, c->fact32, c->tune) &&
-          c->set_t.build(c->gj_t, c->fact32, c->tune)))
+          c->set_t.build(c->gj_t, c->fact32, c->tune) && c->set_dlx.build(c->gj_dlx, false, c->tune)))
       return MBDDC_ERR_UNSUPPORTED;
-    for (SymSet* S : {&c->set_kii, &c->set_x, &c->set_t}) {
+    for (SymSet* S : {&c->set_kii, &c->set_x, &c->set_t, &c->set_dlx}) {
       CHK(upload(c, &S->d_all, S->all));
       CHK(upload(c, &S->d_big, S->big));
       CHK(upload(c, &S->d_items, S->items));
       CHK(upload(c, &S->d_gd, S->gd));
       CHK(upload(c, &S->d_gitems, S->gitems));
     }
-    const int64_t pb = std::max(std::max(c->set_kii.pbuf_elems, c->set_x.pbuf_elems), c->set_t.pbuf_elems);
-    const int64_t bc =
-        (int64_t)std::max(std::max(c->set_kii.big.size(), c->set_x.big.size()), c->set_t.big.size());
+    int64_t pb = 0, bc = 0;
+    for (const SymSet* S : {&c->set_kii, &c->set_x, &c->set_t, &c->set_dlx}) {
+      pb = std::max(pb, S->pbuf_elems);
+      bc = std::max(bc, (int64_t)S->big.size());
+    }
     if (pb > c->big_pbuf || bc > c->big_count || (bc > 0 && !c->d_bpanel)) {
       dfree(c, c->d_bpanel); dfree(c, c->d_bdinv); dfree(c, c->d_bthr);
       c->big_pbuf = std::max(pb, c->big_pbuf);

@@ -24,6 +24,7 @@ MBDDC_ERR_NOCONV, MBDDC_ERR_DEVICE, MBDDC_ERR_STATE, MBDDC_ERR_UNSUPPORTED = -4,
 MBDDC_HEX8, MBDDC_HEX27 = 1, 2
 MBDDC_PRIMAL_V, MBDDC_PRIMAL_E, MBDDC_PRIMAL_F = 1, 2, 4
 MBDDC_FP64, MBDDC_MIXED, MBDDC_MIXED_F32FACT = 0, 1, 2
+MBDDC_SCALING_COUNTING, MBDDC_SCALING_DELUXE = 0, 1
 MBDDC_MAT_SVK, MBDDC_MAT_NEO_HOOKEAN, MBDDC_MAT_GUCCIONE = 1, 2, 3
 MBDDC_BC_ROBIN, MBDDC_BC_PRESSURE = 1, 2
 
@@ -45,7 +46,7 @@ class mbddc_options(ctypes.Structure):
                 ("max_it", ctypes.c_int32), ("symmetric_hint", ctypes.c_int32), ("tune_table", ctypes.c_char_p),
                 ("keep_coarse_matrix", ctypes.c_int32), ("coarse_primal", ctypes.c_uint32),
                 ("graph_apply", ctypes.c_int32), ("packed_sym", ctypes.c_int32),
-                ("nonsym_coarse", ctypes.c_int32), ("nnsp", ctypes.c_int32)]
+                ("nonsym_coarse", ctypes.c_int32), ("nnsp", ctypes.c_int32), ("scaling", ctypes.c_int32)]
 
 
 class mbddc_info(ctypes.Structure):

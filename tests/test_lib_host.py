@@ -155,3 +155,19 @@ def test_nnsp_option_is_checked_on_the_host():
         with pytest.raises(mbddc.MbddcError) as e:
             mbddc.mbddc_estimate_footprint([mesh], mbddc.default_options(primal=7, **kw))
         assert e.value.status == status
+
+
+def test_deluxe_option_is_checked_on_the_host():
+    """Deluxe scaling: symmetric path with FP64 local factors; the flag is 0 or 1."""
+    m = mbddc.mesh_from_problem(problem("small_ve"))
+    base = mbddc.mbddc_estimate_footprint([m], mbddc.default_options(primal=3, symmetric_hint=1))
+    dlx = mbddc.mbddc_estimate_footprint([m], mbddc.default_options(primal=3, symmetric_hint=1,
+                                                                    scaling=mbddc.MBDDC_SCALING_DELUXE))
+    assert dlx > base          # glob blocks and the scratch of the weighted operators
+    for kw, status in ((dict(scaling=2, symmetric_hint=1), mbddc.MBDDC_ERR_ARG),
+                       (dict(scaling=1, symmetric_hint=0), mbddc.MBDDC_ERR_UNSUPPORTED),
+                       (dict(scaling=1, symmetric_hint=1, precision=mbddc.MBDDC_MIXED_F32FACT),
+                        mbddc.MBDDC_ERR_UNSUPPORTED)):
+        with pytest.raises(mbddc.MbddcError) as e:
+            mbddc.mbddc_estimate_footprint([m], mbddc.default_options(primal=3, **kw))
+        assert e.value.status == status
