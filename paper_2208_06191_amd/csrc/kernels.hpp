@@ -122,6 +122,24 @@ struct DlxGlob {
   int32_t n, first, count, pad;
 };
 
+// Sparse products of the symmetric factorisation: up to kCgW consecutive interface columns
+// [h0, h0 + nh) of one subdomain with the union of their K_IG patterns (nu interior rows, ascending,
+// at row_off of the row array).
+constexpr int kCgW = 16;
+constexpr int kCgMaxRows = 768;
+struct ColGroup {
+  int64_t row_off;
+  int32_t sub, h0, nh, nu;
+};
+
+// Workgroups are handed to the 8 XCDs round-robin; renumbering them so that each XCD takes one
+// contiguous range of work items keeps the data those items share (a GEMM's panels, a sweep's
+// panels, a SpMV row range's neighbourhood of x) in that XCD's L2.
+__device__ __forceinline__ unsigned xcd_block(unsigned b, unsigned g) {
+  const unsigned x = b % 8, i = b / 8, q = g / 8, r = g % 8;
+  return x * q + min(x, r) + i;
+}
+
 // Apply work item: (subdomain or instance, first row, first column, column count).
 struct ApplyItem {
   int32_t sub, row0, col0, ncol;

@@ -318,6 +318,13 @@ struct mbddc_ctx {
   ApplyItem *d_itSA = nullptr, *d_itSC = nullptr;
   std::vector<int32_t> kig_ptr, kig_col;   // K_IG rows of the packed path's phase H (SubDev::kig_*)
   int32_t *d_kig_ptr = nullptr, *d_kig_col = nullptr;
+  // symmetric path: interface column groups of the sparse products G^T = K_II^-1 K_IG and
+  // S = K_GG - K_GI G^T (ColGroup), their union rows, and the products' dynamic LDS
+  std::vector<ColGroup> cgroups;
+  std::vector<int32_t> cg_rows;
+  ColGroup* d_cgroups = nullptr;
+  int32_t* d_cg_rows = nullptr;
+  size_t cg_lds = 16;
   // deluxe scaling: blocks per (subdomain, glob) and shared globs (DlxBlock / DlxGlob), each
   // interface slot's block and position in it, per-subdomain scratch offsets, the sweep set of
   // the summed blocks and the GEMM items of D = (sum S)^-1 S
@@ -628,7 +635,7 @@ void clear_pointers(mbddc_ctx* c) {
   cl(c->d_coords); cl(c->d_u); cl(c->d_frames); cl(c->d_fe); cl(c->d_fint); cl(c->d_elem_nodes);
   cl(c->d_elem_node_off); cl(c->d_elem_mat); cl(c->d_mats); cl(c->d_el_list[0]); cl(c->d_el_list[1]);
   cl(c->d_fe_off); cl(c->d_ne_ptr); cl(c->d_ne_ent);
-  cl(c->d_itSA); cl(c->d_itSC); cl(c->d_np); cl(c->d_tp); cl(c->d_kig_ptr); cl(c->d_kig_col);
+  cl(c->d_itSA); cl(c->d_itSC); cl(c->d_np); cl(c->d_tp); cl(c->d_kig_ptr); cl(c->d_kig_col); cl(c->d_cgroups); cl(c->d_cg_rows);
   cl(c->d_dlx_blk); cl(c->d_dlx_glob); cl(c->d_dlx_idx); cl(c->d_dlx_gblk); cl(c->d_dlx_ent_blk);
   cl(c->d_dlx_ent_pos); cl(c->d_dlx_tmp_off); cl(c->d_dlx_S); cl(c->d_dlx_D); cl(c->d_dlx_T); cl(c->d_dlx_tmp);
   cl(c->d_ones); cl(c->d_gemm_dlx);
@@ -774,6 +781,47 @@ int64_t kig_pattern(const Plan& P, const SubLayout& L, std::vector<int32_t>& ptr
   return n;
 }
 
+// Column groups of the sparse condensation for subdomain s: kCgW consecutive interface columns
+// (fewer where the union of their K_IG rows would pass kCgMaxRows) with that union.
+void col_groups(const Plan& P, const SubLayout& L, int32_t s, std::vector<ColGroup>& groups,
+                std::vector<int32_t>& rows_out) {
+  std::vector<std::vector<int32_t>> cols(L.nG);   // interior rows coupled to each interface column
+  std::vector<int32_t> in, ifc;
+  for (int32_t k = 0; k < L.n_elems; ++k) {
+    const int64_t e = L.elem_off + k;
+    const int32_t npe = P.elem_npe[P.sub_elems[e]];
+    const int32_t* ld = P.elem_ldof.data() + P.elem_ldof_off[e];
+    in.clear();
+    ifc.clear();
+    for (int32_t a = 0; a < 3 * npe; ++a) {
+      if (ld[a] < 0) continue;
+      (ld[a] < L.nI ? in : ifc).push_back(ld[a]);
+    }
+    for (int32_t g : ifc) cols[g - L.nI].insert(cols[g - L.nI].end(), in.begin(), in.end());
+  }
+  for (auto& c : cols) {
+    std::sort(c.begin(), c.end());
+    c.erase(std::unique(c.begin(), c.end()), c.end());
+  }
+  std::vector<int32_t> u;
+  for (int32_t h0 = 0; h0 < L.nG;) {
+    int32_t nh = std::min<int32_t>(kCgW, L.nG - h0);
+    for (;;) {
+      u.clear();
+      for (int32_t j = 0; j < nh; ++j) u.insert(u.end(), cols[h0 + j].begin(), cols[h0 + j].end());
+      std::sort(u.begin(), u.end());
+      u.erase(std::unique(u.begin(), u.end()), u.end());
+      if ((int32_t)u.size() <= kCgMaxRows || nh == 1) break;
+      nh = (nh + 1) / 2;
+    }
+    ColGroup g{};
+    g.row_off = (int64_t)rows_out.size(); g.sub = s; g.h0 = h0; g.nh = nh; g.nu = (int32_t)u.size();
+    rows_out.insert(rows_out.end(), u.begin(), u.end());
+    groups.push_back(g);
+    h0 += nh;
+  }
+}
+
 // Row blocks of the local apply phases: at most 64, 128 or 256 rows per workgroup per phase, from
 // the tuning table, or (0) the one of 128 and 256 that pads the phase's row counts least (256 on ties).
 void build_apply_items(mbddc_ctx* c) {
@@ -893,7 +941,7 @@ int build_layout(mbddc_ctx* c) {
   c->gj_t.clear();
   c->itA.clear(); c->itC.clear(); c->itE.clear(); c->itF.clear(); c->itH.clear();
   c->itSA.clear(); c->itSC.clear();
-  c->kig_ptr.clear(); c->kig_col.clear();
+  c->kig_ptr.clear(); c->kig_col.clear(); c->cgroups.clear(); c->cg_rows.clear(); c->cg_lds = 16;
   c->np_total = c->tp_total = 0;
   // packed symmetric blocks: forced (2), or (1) when they cut the operator bytes by a tenth or more
   // (blocks spanning several panels; a single panel holds the whole block anyway)
@@ -933,6 +981,7 @@ int build_layout(mbddc_ctx* c) {
     d.ld4 = (int32_t)round_up(nI, 4);
     for (int q = 0; q < 2; ++q) d.oS[q] = d.oNP[q] = d.oTP[q] = -1;
     d.oKig = d.kig_ptr = d.kig_col = -1;
+    if (c->sym) col_groups(P, L, (int32_t)s, c->cgroups, c->cg_rows);
     if (c->packed) {   // symmetric blocks stored once (SymPack), with their partial-product buffers
       d.ld1 = (int32_t)round_up(nG, 4);   // G alone (column-major) for phase A
       d.oB1 = op; op += round_up((int64_t)d.ld1 * nI, 64);
@@ -1126,6 +1175,9 @@ int build_layout(mbddc_ctx* c) {
   c->inst_chunk_off[P.n_inst] = (int32_t)c->chunk_inst.size();
   c->chunk_begin.push_back(P.n_dofs);
   c->nblocks = (int64_t)P.bsr_col.size();
+  for (const ColGroup& g : c->cgroups)
+    c->cg_lds = std::max(c->cg_lds, (size_t)g.nu * (kCgW * sizeof(double) + sizeof(int32_t)));
+  if (c->cg_lds > 159 * 1024) return MBDDC_ERR_UNSUPPORTED;   // an interface DOF coupled to > 1200 interior DOFs
   // algorithmic bytes (operators once) and flops of each launch family
   for (int f = 0; f < F_COUNT; ++f) c->op_bytes[f] = c->vec_words[f] = c->fam_flops[f] = 0.0;
   const double eo = (double)elem_size(c->mixed), ef = (double)elem_size(c->fact32);
@@ -1160,9 +1212,15 @@ int build_layout(mbddc_ctx* c) {
     c->vec_words[F_APPLY_F] += nc + 2 * nG;
     c->fam_flops[F_GJ_KII] += 2.0 * nI * nI * nI;
     c->fam_flops[F_GJ_P] += 2.0 * m * m * m;
-    c->fam_flops[F_GEMM_GH] += 4.0 * nG * nI * nI;
-    c->fam_flops[F_GEMM_S] += 2.0 * nG * nG * nI;
+    if (!c->sym) {   // dense G, H and S (symmetric path: the sparse products, below)
+      c->fam_flops[F_GEMM_GH] += 4.0 * nG * nI * nI;
+      c->fam_flops[F_GEMM_S] += 2.0 * nG * nG * nI;
+    }
     c->op_bytes[F_ASSEMBLE_LOCAL] += ef * (nI + nG) * (nI + nG);
+  }
+  for (const ColGroup& g : c->cgroups) {   // flops of the products as run (the group's full width)
+    c->fam_flops[F_GEMM_GH] += 2.0 * g.nu * kCgW * c->subs[g.sub].nI;
+    c->fam_flops[F_GEMM_S] += 2.0 * g.nu * kCgW * c->subs[g.sub].nG;
   }
   for (int32_t ii = 0; ii < P.n_inst; ++ii) {
     const double nc = c->inst_nc[ii];
@@ -1249,6 +1307,8 @@ int upload_plan(mbddc_ctx* c) {
     CHK(upload(c, &c->d_kig_ptr, c->kig_ptr));
     CHK(upload(c, &c->d_kig_col, c->kig_col));
   }
+  CHK(upload(c, &c->d_cgroups, c->cgroups));
+  CHK(upload(c, &c->d_cg_rows, c->cg_rows));
   if (c->deluxe) {
     CHK(upload(c, &c->d_dlx_blk, c->dlx_blk));
     CHK(upload(c, &c->d_dlx_glob, c->dlx_glob));
@@ -1440,7 +1500,8 @@ double device_bytes_estimate(const mbddc_ctx* c, bool krylov, int nrhs) {
        c->gemm_items_ssym.size() + c->gemm_items_phi.size() + c->gemm_items_stil.size());
   b += 16.0 * (c->itA.size() + c->itC.size() + c->itE.size() + c->itF.size() + c->itH.size() + c->itSA.size() +
                c->itSC.size());
-  b += 8.0 * R * (c->np_total + c->tp_total) + 4.0 * (c->kig_ptr.size() + c->kig_col.size());
+  b += 8.0 * R * (c->np_total + c->tp_total) + 4.0 * (c->kig_ptr.size() + c->kig_col.size()) +
+       24.0 * c->cgroups.size() + 4.0 * c->cg_rows.size();
   if (c->deluxe)
     b += 8.0 * (2.0 * c->dlx_s_elems + c->dlx_t_elems + c->dlx_tmp_elems + c->dlx_tmp_off.size() + P.n_slots) +
          4.0 * (c->dlx_idx.size() + c->dlx_gblk.size() + 2.0 * P.n_slots) + 32.0 * c->dlx_blk.size() +
@@ -1889,18 +1950,33 @@ int factor_impl(mbddc_ctx* c) {
     return st;
   }
   if (!c->sym) CHK(run_gj_large<T>(c, W, c->gj_kii_large, F_GJ_KII, false));
-  // G = K_GI K_II^-1 (and H = K_II^-1 K_IG on the general path), S = K_GG - G K_IG
-  const std::vector<GemmItem>& igh = c->sym ? c->gemm_items_g : c->gemm_items_gh;
-  const std::vector<GemmItem>& is = c->sym ? c->gemm_items_ssym : c->gemm_items_s;
-  if (!igh.empty()) {
-    ProfScope ps(c, F_GEMM_GH, 0.0, c->fam_flops[F_GEMM_GH] * (c->sym ? 0.5 : 1.0));
-    launch_gemm<T>(c, (unsigned)igh.size(), c->stream, c->d_gemm_desc,
-                       c->sym ? c->d_gemm_g : c->d_gemm_gh, W, W, W, W);
-  }
-  if (!is.empty()) {
-    ProfScope ps(c, F_GEMM_S, 0.0, c->fam_flops[F_GEMM_S]);
-    launch_gemm<T>(c, (unsigned)is.size(), c->stream, c->d_gemm_desc,
-                       c->sym ? c->d_gemm_ssym : c->d_gemm_s, W, W, W, W);
+  // G = K_GI K_II^-1 and H = K_II^-1 K_IG, S = K_GG - G K_IG: dense GEMMs on the general path;
+  // on the symmetric path G^T = H and S = K_GG - K_GI G^T as sparse products over K_IG's pattern
+  if (c->sym) {
+    const unsigned ng = (unsigned)c->cgroups.size();
+    if (ng > 0) {
+      CHK(set_lds(k_kig_product<T, 0>, c->cg_lds));
+      CHK(set_lds(k_kig_product<T, 1>, c->cg_lds));
+      {
+        ProfScope ps(c, F_GEMM_GH, 0.0, c->fam_flops[F_GEMM_GH]);
+        hipLaunchKernelGGL((k_kig_product<T, 0>), dim3(ng), dim3(kBlock), c->cg_lds, c->stream, c->d_subs,
+                           c->d_cgroups, c->d_cg_rows, W);
+      }
+      {
+        ProfScope ps(c, F_GEMM_S, 0.0, c->fam_flops[F_GEMM_S]);
+        hipLaunchKernelGGL((k_kig_product<T, 1>), dim3(ng), dim3(kBlock), c->cg_lds, c->stream, c->d_subs,
+                           c->d_cgroups, c->d_cg_rows, W);
+      }
+    }
+  } else {
+    if (!c->gemm_items_gh.empty()) {
+      ProfScope ps(c, F_GEMM_GH, 0.0, c->fam_flops[F_GEMM_GH]);
+      launch_gemm<T>(c, (unsigned)c->gemm_items_gh.size(), c->stream, c->d_gemm_desc, c->d_gemm_gh, W, W, W, W);
+    }
+    if (!c->gemm_items_s.empty()) {
+      ProfScope ps(c, F_GEMM_S, 0.0, c->fam_flops[F_GEMM_S]);
+      launch_gemm<T>(c, (unsigned)c->gemm_items_s.size(), c->stream, c->d_gemm_desc, c->d_gemm_s, W, W, W, W);
+    }
   }
   HIPCHK(hipGetLastError());
   if (c->sym) {
