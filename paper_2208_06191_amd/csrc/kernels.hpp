@@ -42,6 +42,9 @@ struct SubDev {
   // array, interface-local columns at kig_col of the column array, values at oKig of the operator
   // buffer (-1 otherwise).
   int64_t oKig, kig_ptr, kig_col;
+  // Packed path, phase A: G (column-major, ld1 rows, ld1 a multiple of 32) applied by 256 x 256
+  // tiles; their partial products per column panel at oNPA (panels(nI) x nG R-vectors).
+  int64_t oNPA;
 };
 
 // Panel-packed symmetric operator: rows [0, n) = [S; X] with S (nS x nS) symmetric, columns

@@ -314,8 +314,8 @@ struct mbddc_ctx {
   // packed symmetric phases A and C: tiles (sub, first row of the tile, first column of the panel,
   // rows), partial-product sizes (R-vectors) and buffers
   bool packed = false;
-  std::vector<ApplyItem> itSA, itSC;
-  ApplyItem *d_itSA = nullptr, *d_itSC = nullptr;
+  std::vector<ApplyItem> itSA, itSC, itRA;   // itRA: phase A's tiles of G on the packed path
+  ApplyItem *d_itSA = nullptr, *d_itSC = nullptr, *d_itRA = nullptr;
   std::vector<int32_t> kig_ptr, kig_col;   // K_IG rows of the packed path's phase H (SubDev::kig_*)
   int32_t *d_kig_ptr = nullptr, *d_kig_col = nullptr;
   // symmetric path: interface column groups of the sparse products G^T = K_II^-1 K_IG and
@@ -635,7 +635,7 @@ void clear_pointers(mbddc_ctx* c) {
   cl(c->d_coords); cl(c->d_u); cl(c->d_frames); cl(c->d_fe); cl(c->d_fint); cl(c->d_elem_nodes);
   cl(c->d_elem_node_off); cl(c->d_elem_mat); cl(c->d_mats); cl(c->d_el_list[0]); cl(c->d_el_list[1]);
   cl(c->d_fe_off); cl(c->d_ne_ptr); cl(c->d_ne_ent);
-  cl(c->d_itSA); cl(c->d_itSC); cl(c->d_np); cl(c->d_tp); cl(c->d_kig_ptr); cl(c->d_kig_col); cl(c->d_cgroups); cl(c->d_cg_rows);
+  cl(c->d_itSA); cl(c->d_itSC); cl(c->d_itRA); cl(c->d_np); cl(c->d_tp); cl(c->d_kig_ptr); cl(c->d_kig_col); cl(c->d_cgroups); cl(c->d_cg_rows);
   cl(c->d_dlx_blk); cl(c->d_dlx_glob); cl(c->d_dlx_idx); cl(c->d_dlx_gblk); cl(c->d_dlx_ent_blk);
   cl(c->d_dlx_ent_pos); cl(c->d_dlx_tmp_off); cl(c->d_dlx_S); cl(c->d_dlx_D); cl(c->d_dlx_T); cl(c->d_dlx_tmp);
   cl(c->d_ones); cl(c->d_gemm_dlx);
@@ -940,7 +940,7 @@ int build_layout(mbddc_ctx* c) {
   c->gj_x.clear();
   c->gj_t.clear();
   c->itA.clear(); c->itC.clear(); c->itE.clear(); c->itF.clear(); c->itH.clear();
-  c->itSA.clear(); c->itSC.clear();
+  c->itSA.clear(); c->itSC.clear(); c->itRA.clear();
   c->kig_ptr.clear(); c->kig_col.clear(); c->cgroups.clear(); c->cg_rows.clear(); c->cg_lds = 16;
   c->np_total = c->tp_total = 0;
   // packed symmetric blocks: forced (2), or (1) when they cut the operator bytes by a tenth or more
@@ -980,11 +980,18 @@ int build_layout(mbddc_ctx* c) {
     d.ld3 = (int32_t)round_up(nG, 4);
     d.ld4 = (int32_t)round_up(nI, 4);
     for (int q = 0; q < 2; ++q) d.oS[q] = d.oNP[q] = d.oTP[q] = -1;
+    d.oNPA = -1;
     d.oKig = d.kig_ptr = d.kig_col = -1;
     if (c->sym) col_groups(P, L, (int32_t)s, c->cgroups, c->cg_rows);
     if (c->packed) {   // symmetric blocks stored once (SymPack), with their partial-product buffers
-      d.ld1 = (int32_t)round_up(nG, 4);   // G alone (column-major) for phase A
+      d.ld1 = (int32_t)round_up(nG, 32);   // G alone (column-major, 128-byte aligned columns) for phase A
       d.oB1 = op; op += round_up((int64_t)d.ld1 * nI, 64);
+      d.oNPA = c->np_total;
+      c->np_total += (int64_t)nG * SymPack::panels((int32_t)nI);
+      for (int32_t pp = 0; pp < SymPack::panels((int32_t)nI); ++pp)
+        for (int32_t k = 0; k * kSymPanel < nG; ++k)
+          c->itRA.push_back({(int32_t)s, k * kSymPanel, pp * kSymPanel,
+                             std::min<int32_t>(kSymPanel, (int32_t)nG - k * kSymPanel)});
       d.oB2 = -1;
       const int32_t nS[2] = {(int32_t)nI, (int32_t)nG}, nr[2] = {(int32_t)nI, (int32_t)(nG + nc)};
       for (int q = 0; q < 2; ++q) {
@@ -1303,6 +1310,7 @@ int upload_plan(mbddc_ctx* c) {
   CHK(upload(c, &c->d_itH, c->itH));
   CHK(upload(c, &c->d_itSA, c->itSA));
   CHK(upload(c, &c->d_itSC, c->itSC));
+  CHK(upload(c, &c->d_itRA, c->itRA));
   if (c->packed) {
     CHK(upload(c, &c->d_kig_ptr, c->kig_ptr));
     CHK(upload(c, &c->d_kig_col, c->kig_col));
@@ -1499,7 +1507,7 @@ double device_bytes_estimate(const mbddc_ctx* c, bool krylov, int nrhs) {
   b += 48.0 * (c->gemm_desc.size()) + 16.0 * (c->gemm_items_gh.size() + c->gemm_items_s.size() +
        c->gemm_items_ssym.size() + c->gemm_items_phi.size() + c->gemm_items_stil.size());
   b += 16.0 * (c->itA.size() + c->itC.size() + c->itE.size() + c->itF.size() + c->itH.size() + c->itSA.size() +
-               c->itSC.size());
+               c->itSC.size() + c->itRA.size());
   b += 8.0 * R * (c->np_total + c->tp_total) + 4.0 * (c->kig_ptr.size() + c->kig_col.size()) +
        24.0 * c->cgroups.size() + 4.0 * c->cg_rows.size();
   if (c->deluxe)
@@ -2147,6 +2155,8 @@ int apply_attrs();
 // dynamic LDS of the packed tile kernel per right-hand side: cross-wave sums, the panel's and
 // the row tile's inputs
 constexpr size_t kSymLds = (4 * 256 + 2 * kSymPanel) * sizeof(double);
+// of the rectangular tile kernel (phase A, packed path): cross-wave sums and the panel's inputs
+constexpr size_t kRectLds = (4 * 256 + kSymPanel) * sizeof(double);
 
 // Phase PH of the local apply (row-block list k of A, C, F, H) with that list's rows per
 // workgroup: 256 (four rows per lane), 128 (two) or 64 (one).
@@ -2195,9 +2205,20 @@ int apply_impl(mbddc_ctx* c, const double* r, double* z, mbddc_ctx* parent = nul
   a.n_slots = P.n_slots;
   {
     ProfScope ps(c, F_APPLY_A, c->op_bytes[F_APPLY_A] + 8.0 * R * c->vec_words[F_APPLY_A], 2.0 * R * c->fam_flops[F_APPLY_A]);
+    if (c->packed) {   // G r_I alone: 256 x 256 tiles, then their panel sums
+      a.items = c->d_itRA;
+      if (!c->itRA.empty())
+        hipLaunchKernelGGL((k_apply_rect<To, R>), dim3((unsigned)c->itRA.size()), dim3(kBlock), kRectLds * R,
+                           c->stream, a);
+    } else {
+      a.items = c->d_itA;
+      launch_local<To, R, 0>(c, a, 0, c->itA.size());
+    }
+  }
+  if (c->packed) {
+    ProfScope ps(c, F_APPLY_SYMRED, 0.0, 0.0);
     a.items = c->d_itA;
-    if (c->packed) launch_local<To, R, 5>(c, a, 0, c->itA.size());   // G r_I alone
-    else launch_local<To, R, 0>(c, a, 0, c->itA.size());
+    hipLaunchKernelGGL((k_apply_rect_reduce<R>), dim3((unsigned)c->itA.size()), dim3(kBlock), 0, c->stream, a);
   }
   {
     ProfScope ps(c, F_APPLY_C, c->op_bytes[F_APPLY_C] + 8.0 * R * c->vec_words[F_APPLY_C], 2.0 * R * c->fam_flops[F_APPLY_C]);
@@ -2316,13 +2337,9 @@ int apply_attrs() {
     if (!e) e = set_lds(k_apply_local<To, R, 1, 1, false>, mx);
     if (!e) e = set_lds(k_apply_local<To, R, 3, 1, false>, mx);
     if (!e) e = set_lds(k_apply_local<To, R, 4, 1, false>, mx);
-    if (!e) e = set_lds(k_apply_local<To, R, 5, 4, false>, mx);
-    if (!e) e = set_lds(k_apply_local<To, R, 5, 2, false>, mx);
-    if (!e) e = set_lds(k_apply_local<To, R, 5, 4, true>, mx);
-    if (!e) e = set_lds(k_apply_local<To, R, 5, 2, true>, mx);
-    if (!e) e = set_lds(k_apply_local<To, R, 5, 1, false>, mx);
     if (!e) e = set_lds(k_apply_sym<To, R, 1>, mx);
     if (!e) e = set_lds(k_apply_sym<To, R, 2>, mx);
+    if (!e) e = set_lds(k_apply_rect<To, R>, mx);
     st = e;
   });
   return st;
