@@ -948,11 +948,11 @@ int build_layout(mbddc_ctx* c) {
   c->packed = false;
   if (c->sym && c->opt.packed_sym != 0) {
     double full = 0.0, pk = 0.0;
-    for (const SubLayout& L : P.subs) {   // full: [K_II^-1; G], [D S~ D; (D Phi)^T], H; packed: G, K_II^-1, S~
-      full += (double)round_up(L.nI + L.nG, 4) * L.nI + (double)round_up(L.nG + L.nc, 4) * L.nG +
-              (double)round_up(L.nI, 4) * L.nG;
-      pk += (double)round_up(L.nG, 4) * L.nI + (double)SymPack::elems(L.nI, L.nI) +
-            (double)SymPack::elems(L.nG, L.nG + L.nc);
+    // the saving of storing the symmetric blocks once (several panels per block; with one panel the
+    // tile kernels have too little parallelism for what the packing saves)
+    for (const SubLayout& L : P.subs) {
+      full += (double)round_up(L.nI + L.nG, 4) * L.nI + (double)round_up(L.nG + L.nc, 4) * L.nG;
+      pk += (double)SymPack::elems(L.nI, L.nI + L.nG) + (double)SymPack::elems(L.nG, L.nG + L.nc);
     }
     c->packed = c->opt.packed_sym == 2 || pk <= 0.9 * full;
   }
