@@ -56,9 +56,12 @@ enum { MBDDC_PRIMAL_V = 1, MBDDC_PRIMAL_E = 2, MBDDC_PRIMAL_F = 4 }; /* §6.2 pr
  * per-iteration local operators in FP64. MBDDC_MIXED: local factorisations in
  * FP64; the local operators are stored in FP32 (half the bytes each apply reads)
  * and every product with them accumulates in FP64. MBDDC_MIXED_F32FACT: local
- * factorisations in FP32 too (local blocks up to 1197 rows); this mode costs
- * GMRES iterations (the FP32 local inverses are less accurate) and is outside
- * the oracle + 2 iteration contract of MBDDC_MIXED. */
+ * factorisations in FP32 too (symmetric path: blocks of any size, the large ones
+ * swept on the FP32 matrix cores with FP32 accumulation; general path: blocks up
+ * to 512 rows). The FP32 local inverses are less accurate: the outer FP64 GMRES
+ * absorbs the difference at the cost of iterations that depend on the problem
+ * (none on the ventricle-like shell, 3 to 5 on small Q1 boxes), so this mode is
+ * not held to MBDDC_MIXED's oracle + 2 iteration contract. */
 enum { MBDDC_FP64 = 0, MBDDC_MIXED = 1, MBDDC_MIXED_F32FACT = 2 };
 /* interface scaling of the averaging operator (mbddc_options.scaling) */
 enum { MBDDC_SCALING_COUNTING = 0, MBDDC_SCALING_DELUXE = 1 };

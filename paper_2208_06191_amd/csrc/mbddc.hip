@@ -134,14 +134,14 @@ struct Tuning {
   int32_t xchunk;
   int32_t apply_rows[4];            // rows per workgroup of apply phases A, C, F, H (64, 128, 256; 0 = by size)
   int32_t apply_rows2[4];           // the same for the level-2 instance of three-level handles
-  int32_t gemm_mfma;                // FP64 batched GEMMs on the matrix cores (1) or the vector units (0)
+  int32_t gemm_mfma;                // batched GEMMs on the matrix cores (1) or the vector units (0)
   int32_t apply_big;                // apply column groups: 1 large first, 0 small only, -1 by size
   Tuning() {
     gemm_mfma = 0;
     apply_big = -1;
     for (int k = 0; k < 4; ++k) apply_rows[k] = apply_rows2[k] = 0;
     const int d64[kSymBuckets] = {SV_REG, SV_REG, SV_BLOCKED, SV_BLOCKED};
-    const int d32[kSymBuckets] = {SV_BP32, SV_BP32, SV_BP16, SV_BP16};
+    const int d32[kSymBuckets] = {SV_BP32, SV_BP32, SV_BP16, SV_BLOCKED};
     for (int b = 0; b < kSymBuckets; ++b) {
       sym[0][b] = d64[b];
       sym[1][b] = d32[b];
@@ -156,7 +156,7 @@ inline bool sym_variant_ok(int v, int n, bool fp32) {
     case SV_REG: return !fp32 && n <= kSymRegMax;
     case SV_BP16: return n <= (fp32 ? sym_onewg_max<float>(16) : sym_onewg_max<double>(16));
     case SV_BP32: return n <= (fp32 ? sym_onewg_max<float>(32) : sym_onewg_max<double>(32));
-    case SV_BLOCKED: return !fp32;
+    case SV_BLOCKED: return true;
     default: return false;
   }
 }
@@ -965,10 +965,9 @@ int build_layout(mbddc_ctx* c) {
     d.n_elems = L.n_elems; d.ldK = L.ni();
     d.dof_off = L.dof_off; d.if_off = L.if_off; d.c_off = L.c_off; d.elem_off = L.elem_off; d.cons_off = L.cons_off;
     const int64_t ni = L.ni(), nI = L.nI, nG = L.nG, nc = L.nc, m = L.mP();
-    // the pivoting path inverts in one workgroup; the symmetric path sweeps larger FP64
-    // matrices with the batched blocked kernels, larger FP32 ones not at all
-    // the general path inverts blocks up to kGjMax rows in one workgroup, larger ones (FP64
-    // factorisations only) by the multi-workgroup pivoted Gauss-Jordan
+    // the symmetric path sweeps matrices beyond the one-workgroup kernels with the batched
+    // blocked kernels (FP64 or FP32); the general path inverts blocks up to kGjMax rows in one
+    // workgroup, larger ones (FP64 factorisations only) by the multi-workgroup pivoted Gauss-Jordan
     if (!c->sym && c->fact32 && std::max<int64_t>(nI, m) > kGjMax) return MBDDC_ERR_UNSUPPORTED;
     d.oK = w; w += round_up(ni * ni, 64);
     d.oG = w; w += round_up(nG * nI, 64);
@@ -1217,8 +1216,9 @@ int build_layout(mbddc_ctx* c) {
     c->fam_flops[F_APPLY_F] += nG * nc;
     c->vec_words[F_APPLY_C] += 2 * nG + nG + nc;
     c->vec_words[F_APPLY_F] += nc + 2 * nG;
-    c->fam_flops[F_GJ_KII] += 2.0 * nI * nI * nI;
-    c->fam_flops[F_GJ_P] += 2.0 * m * m * m;
+    // a symmetric sweep updates one triangle (n^3 flops per inverse), Gauss-Jordan the whole matrix (2 n^3)
+    c->fam_flops[F_GJ_KII] += (c->sym ? 1.0 : 2.0) * nI * nI * nI;
+    c->fam_flops[F_GJ_P] += c->sym ? (double)nG * nG * nG : 2.0 * m * m * m;
     if (!c->sym) {   // dense G, H and S (symmetric path: the sparse products, below)
       c->fam_flops[F_GEMM_GH] += 4.0 * nG * nI * nI;
       c->fam_flops[F_GEMM_S] += 2.0 * nG * nG * nI;
@@ -1578,11 +1578,9 @@ template <typename T>
 void launch_gemm(mbddc_ctx* c, unsigned n_items, hipStream_t st, const GemmDesc* d, const GemmItem* it, const T* A,
                  const T* B, T* C, const T* Ci) {
   if (n_items == 0) return;
-  if constexpr (sizeof(T) == 8) {
-    if (c->tune.gemm_mfma) {
-      hipLaunchKernelGGL(k_gemm_batched_f64, dim3(n_items), dim3(kBlock), 0, st, d, it, A, B, C, Ci);
-      return;
-    }
+  if (c->tune.gemm_mfma) {
+    hipLaunchKernelGGL((k_gemm_batched_mfma<T>), dim3(n_items), dim3(kBlock), 0, st, d, it, A, B, C, Ci);
+    return;
   }
   hipLaunchKernelGGL((k_gemm_batched<T>), dim3(n_items), dim3(kBlock), 0, st, d, it, A, B, C, Ci);
 }
@@ -1648,26 +1646,27 @@ int run_symset(mbddc_ctx* c, T* base, const SymSet& S) {
     }
   }
   if (S.big.empty()) return MBDDC_OK;
-  if (sizeof(T) != 8) return MBDDC_ERR_UNSUPPORTED;
-  double* A = reinterpret_cast<double*>(base);
+  // the panel and diagonal-inverse buffers are sized in doubles and hold T
+  T* pbuf = reinterpret_cast<T*>(c->d_bpanel);
+  T* dbuf = reinterpret_cast<T*>(c->d_bdinv);
+  T* A = base;
   const unsigned nb = (unsigned)S.big.size();
-  hipLaunchKernelGGL(k_bsym_prep, dim3(nb), dim3(kBlock), 0, c->stream, S.d_big, A, c->d_bthr, c->d_status);
-  CHK(set_lds(k_bsym_diag, kDiagLds));
+  hipLaunchKernelGGL(k_bsym_prep<T>, dim3(nb), dim3(kBlock), 0, c->stream, S.d_big, A, c->d_bthr, c->d_status);
+  CHK(set_lds(k_bsym_diag<T>, diag_lds<T>()));
   const int nmax = S.big[0].n;
   const unsigned gx = std::min<unsigned>(64, nblk((int64_t)nmax * kSymCB));
   unsigned active = nb;
   for (int k0 = 0; k0 < nmax; k0 += kSymCB) {
     while (active > 0 && S.big[active - 1].n <= k0) --active;
-    hipLaunchKernelGGL(k_bsym_diag, dim3(active), dim3(kBlock), kDiagLds, c->stream, S.d_big, A, c->d_bdinv,
+    hipLaunchKernelGGL(k_bsym_diag<T>, dim3(active), dim3(kBlock), diag_lds<T>(), c->stream, S.d_big, A, dbuf,
                        c->d_bthr, c->d_status, k0);
-    hipLaunchKernelGGL(k_bsym_gather, dim3(gx, active), dim3(kBlock), 0, c->stream, S.d_big, A, c->d_bpanel, k0);
-    launch_gemm<double>(c, (unsigned)S.gitem_off[active], c->stream,
-                       S.d_gd, S.d_gitems, c->d_bpanel, c->d_bdinv, c->d_bpanel, c->d_bpanel);
-    hipLaunchKernelGGL(k_bsym_update, dim3((unsigned)S.item_off[active]), dim3(kBlock), 0, c->stream, S.d_big,
-                       S.d_items, A, c->d_bpanel, c->d_bdinv, k0);
+    hipLaunchKernelGGL(k_bsym_gather<T>, dim3(gx, active), dim3(kBlock), 0, c->stream, S.d_big, A, pbuf, k0);
+    launch_gemm<T>(c, (unsigned)S.gitem_off[active], c->stream, S.d_gd, S.d_gitems, pbuf, dbuf, pbuf, pbuf);
+    hipLaunchKernelGGL(k_bsym_update<T>, dim3((unsigned)S.item_off[active]), dim3(kBlock), 0, c->stream, S.d_big,
+                       S.d_items, A, pbuf, dbuf, k0);
   }
-  hipLaunchKernelGGL(k_bsym_finish, dim3((unsigned)S.item_off[nb]), dim3(kBlock), 0, c->stream, S.d_big, S.d_items,
-                     A);
+  hipLaunchKernelGGL(k_bsym_finish<T>, dim3((unsigned)S.item_off[nb]), dim3(kBlock), 0, c->stream, S.d_big,
+                     S.d_items, A);
   HIPCHK(hipGetLastError());
   return MBDDC_OK;
 }
@@ -3221,7 +3220,7 @@ int autotune_impl(mbddc_ctx* c) {
       CHK(rebuild_symsets(c));
     }
   }
-  if (!c->fact32) {   // FP64 GEMMs: vector units or matrix cores
+  {   // batched GEMMs: vector units or matrix cores
     int best_g = c->tune.gemm_mfma;
     double best_t = 1e300;
     for (int g = 0; g < 2; ++g) {

@@ -41,5 +41,6 @@ def test_no_packed_fp32_in_device_code(tmp_path):
                     f"--input={fat}", f"--output={co}"], check=True)
     dis = subprocess.run([objdump, "-d", str(co)], check=True, capture_output=True, text=True).stdout
     assert "k_apply_sym" in dis and "v_mfma_f64" in dis      # the kernels are there
+    assert "v_mfma_f32_16x16x4" in dis                      # the FP32 factorisation's matrix-core products
     found = sorted(set(re.findall(r"\bv_pk_\w*f32\b", dis)))
     assert not found, found

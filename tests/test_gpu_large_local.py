@@ -6,9 +6,11 @@ their apply stages the input vector in LDS a chunk of 1024 columns at a time. Th
 checkpoints and bounds are those of the small cases (paper §3.2 objects): coarse
 matrix, one preconditioner application, GMRES iterations and solution against the
 FP64 oracle, on a Q1 box, a box whose subdomains straddle the one-workgroup limit
-(both kernels in one factorisation) and the Q2 ventricle-like shell.
+(both kernels in one factorisation) and the Q2 ventricle-like shell. The FP32 local
+factorisation (MBDDC_MIXED_F32FACT) sweeps the same blocks in FP32 on the matrix cores.
 """
 import functools
+import json
 
 import numpy as np
 import pytest
@@ -207,3 +209,56 @@ def test_floating_large_subdomains_without_primals_are_singular():
     bad = s.last_bad_subdomain()
     elems = np.nonzero(P.elem_part == bad)[0]
     assert not np.any(P.mesh.node_tags[P.mesh.elem_nodes[elems]] & 1)   # a floating subdomain
+
+
+# ------------------------------------------------------------------- FP32 local factorisations
+EPS32_OVER_EPS64 = 1.1920929e-07 / 2.220446049250313e-16
+
+
+@pytest.mark.parametrize("gemm", [1, 0])
+@pytest.mark.parametrize("name,primal", CASES)
+def test_fp32_blocked_sweep_on_the_matrix_cores(name, primal, gemm, tmp_path):
+    """MBDDC_MIXED_F32FACT with every symmetric inversion forced onto the blocked sweep in FP32
+    (panel products and trailing update on the FP32 matrix cores, FP32 accumulation) and the
+    condensation GEMMs on the matrix cores (gemm 1) or the vector units (gemm 0). One application
+    is held to the FP32 analogue of the FP64 bound: 100 x the oracle's change under a relative
+    FP32-epsilon perturbation of K_e (first order in the epsilon, so the FP64 floor scaled by
+    eps32 / eps64), at least 1e-2; the solve reaches the FP64 true residual within the mode's
+    allowance of oracle + 6 iterations."""
+    P = problem(name)
+    dec, B = oracle_of(name, primal)
+    path = tmp_path / "fp32.json"
+    path.write_text(json.dumps({"mbddc_tune": 1, "sym_fp64": [0, 0, 3, 3], "sym_fp32": [3, 3, 3, 3],
+                                "apply_xchunk": 256, "apply_rows": [128, 128, 128, 128], "gemm_mfma": gemm}))
+    s = solver_for(P, mbddc.MBDDC_MIXED_F32FACT, primal, tune_table=str(path))
+    assert s.mbddc_get_tuning()["sym_fp32"] == [3, 3, 3, 3]
+    r = np.random.default_rng(7).standard_normal((2, P.n_dofs))
+    r[:, P.dirichlet] = 0.0
+    z = s.mbddc_apply(r)
+    err = max(rel(z[k][dec.free], B.apply(r[k][dec.free])) for k in range(2))
+    bound = max(1e-2, 100.0 * EPS32_OVER_EPS64 * apply_noise_floor(name, primal))
+    b = P.rhs[0][dec.free]
+    ref = gmres.gmres(lambda v: B.A @ v, B.apply, b, 1e-8, 30, 1000)
+    x, info = s.mbddc_solve(P.rhs[0])
+    print(f"{name} gemm {gemm}: FP32 blocked sweep apply {err:.2e} (bound {bound:.1e}), its {info.iterations} "
+          f"(oracle {ref.iterations})")
+    assert err <= bound
+    assert info.rel_res_true <= 1e-8
+    assert np.linalg.norm(b - B.A @ x[dec.free]) <= 1e-8 * np.linalg.norm(b)
+    assert info.iterations <= ref.iterations + 6
+    s.close()
+
+
+def test_fp32_default_table_takes_the_blocked_sweep_for_large_blocks():
+    """With the default table, FP32 blocks beyond 598 rows take the blocked sweep and the shell
+    with full-size parts (interiors up to 4.4k rows, beyond every one-workgroup FP32 kernel)
+    factorises and solves."""
+    P = problem("vent_parts6k")
+    dec, B = oracle_of("vent_parts6k", 7)
+    s = solver_for(P, mbddc.MBDDC_MIXED_F32FACT, 7)
+    assert s.mbddc_get_tuning()["sym_fp32"][3] == 3
+    x, info = s.mbddc_solve(P.rhs[0])
+    b = P.rhs[0][dec.free]
+    assert info.rel_res_true <= 1e-8
+    assert np.linalg.norm(b - B.A @ x[dec.free]) <= 1e-8 * np.linalg.norm(b)
+    s.close()
