@@ -343,7 +343,7 @@ struct mbddc_ctx {
   double *d_dlx_S = nullptr, *d_dlx_D = nullptr, *d_dlx_T = nullptr, *d_dlx_tmp = nullptr, *d_ones = nullptr;
   GemmItem* d_gemm_dlx = nullptr;
   int64_t np_total = 0, tp_total = 0;
-  double *d_np = nullptr, *d_tp = nullptr;
+  double *d_np = nullptr, *d_tp = nullptr, *d_cin = nullptr;
   int32_t *d_chunk_inst = nullptr, *d_inst_chunk_off = nullptr;
   int64_t* d_chunk_begin = nullptr;
 
@@ -635,7 +635,7 @@ void clear_pointers(mbddc_ctx* c) {
   cl(c->d_coords); cl(c->d_u); cl(c->d_frames); cl(c->d_fe); cl(c->d_fint); cl(c->d_elem_nodes);
   cl(c->d_elem_node_off); cl(c->d_elem_mat); cl(c->d_mats); cl(c->d_el_list[0]); cl(c->d_el_list[1]);
   cl(c->d_fe_off); cl(c->d_ne_ptr); cl(c->d_ne_ent);
-  cl(c->d_itSA); cl(c->d_itSC); cl(c->d_itRA); cl(c->d_np); cl(c->d_tp); cl(c->d_kig_ptr); cl(c->d_kig_col); cl(c->d_cgroups); cl(c->d_cg_rows);
+  cl(c->d_itSA); cl(c->d_itSC); cl(c->d_itRA); cl(c->d_np); cl(c->d_tp); cl(c->d_cin); cl(c->d_kig_ptr); cl(c->d_kig_col); cl(c->d_cgroups); cl(c->d_cg_rows);
   cl(c->d_dlx_blk); cl(c->d_dlx_glob); cl(c->d_dlx_idx); cl(c->d_dlx_gblk); cl(c->d_dlx_ent_blk);
   cl(c->d_dlx_ent_pos); cl(c->d_dlx_tmp_off); cl(c->d_dlx_S); cl(c->d_dlx_D); cl(c->d_dlx_T); cl(c->d_dlx_tmp);
   cl(c->d_ones); cl(c->d_gemm_dlx);
@@ -1544,10 +1544,11 @@ int ensure_apply_buffers(mbddc_ctx* c, int R) {
   const Plan& P = c->plan;
   dfree(c, c->d_tb); dfree(c, c->d_wb); dfree(c, c->d_cc); dfree(c, c->d_ep);
   dfree(c, c->d_X); dfree(c, c->d_Y); dfree(c, c->d_io);
-  dfree(c, c->d_np); dfree(c, c->d_tp);
+  dfree(c, c->d_np); dfree(c, c->d_tp); dfree(c, c->d_cin);
   if (c->packed) {
     CHK(dalloc(c, &c->d_np, std::max<int64_t>(c->np_total, 1) * R));
     CHK(dalloc(c, &c->d_tp, std::max<int64_t>(c->tp_total, 1) * R));
+    CHK(dalloc(c, &c->d_cin, std::max<int64_t>(P.n_ifx, 1) * R));
   }
   CHK(dalloc(c, &c->d_tb, P.n_slots * R));
   CHK(dalloc(c, &c->d_wb, P.n_slots * R));
@@ -2199,6 +2200,8 @@ int apply_impl(mbddc_ctx* c, const double* r, double* z, mbddc_ctx* parent = nul
   if ((4 * 256 * R + (size_t)a.xchunk * R) * sizeof(double) > 160 * 1024) return MBDDC_ERR_UNSUPPORTED;
   a.np = c->d_np;
   a.tp = c->d_tp;
+  a.cin = c->d_cin;
+  a.n_ifx = P.n_ifx;
   a.kig_ptr = c->d_kig_ptr;
   a.kig_col = c->d_kig_col;
   a.n_slots = P.n_slots;
@@ -2218,6 +2221,7 @@ int apply_impl(mbddc_ctx* c, const double* r, double* z, mbddc_ctx* parent = nul
     ProfScope ps(c, F_APPLY_SYMRED, 0.0, 0.0);
     a.items = c->d_itA;
     hipLaunchKernelGGL((k_apply_rect_reduce<R>), dim3((unsigned)c->itA.size()), dim3(kBlock), 0, c->stream, a);
+    if (P.n_ifx > 0) hipLaunchKernelGGL((k_c_prep<R>), dim3(nblk(P.n_ifx)), dim3(kBlock), 0, c->stream, a);
   }
   {
     ProfScope ps(c, F_APPLY_C, c->op_bytes[F_APPLY_C] + 8.0 * R * c->vec_words[F_APPLY_C], 2.0 * R * c->fam_flops[F_APPLY_C]);
