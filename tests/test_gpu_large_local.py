@@ -223,8 +223,10 @@ def test_fp32_blocked_sweep_on_the_matrix_cores(name, primal, gemm, tmp_path):
     condensation GEMMs on the matrix cores (gemm 1) or the vector units (gemm 0). One application
     is held to the FP32 analogue of the FP64 bound: 100 x the oracle's change under a relative
     FP32-epsilon perturbation of K_e (first order in the epsilon, so the FP64 floor scaled by
-    eps32 / eps64), at least 1e-2; the solve reaches the FP64 true residual within the mode's
-    allowance of oracle + 6 iterations."""
+    eps32 / eps64), at least 1e-2; the local coarse matrices, formed in FP32 as T^-1 - rho I, to the
+    FP64 coarse bound scaled the same way (1e-12 eps32 / eps64, about 5e-4: the cancellation against
+    rho costs no more than FP32 rounding); the solve reaches the FP64 true residual within the
+    mode's allowance of oracle + 6 iterations."""
     P = problem(name)
     dec, B = oracle_of(name, primal)
     path = tmp_path / "fp32.json"
@@ -232,6 +234,8 @@ def test_fp32_blocked_sweep_on_the_matrix_cores(name, primal, gemm, tmp_path):
                                 "apply_xchunk": 256, "apply_rows": [128, 128, 128, 128], "gemm_mfma": gemm}))
     s = solver_for(P, mbddc.MBDDC_MIXED_F32FACT, primal, tune_table=str(path))
     assert s.mbddc_get_tuning()["sym_fp32"] == [3, 3, 3, 3]
+    err_c = rel(s.mbddc_get_coarse_matrix(0, dec.n_coarse), B.Kc)
+    assert err_c <= TOL_COARSE * EPS32_OVER_EPS64, err_c
     r = np.random.default_rng(7).standard_normal((2, P.n_dofs))
     r[:, P.dirichlet] = 0.0
     z = s.mbddc_apply(r)
@@ -240,8 +244,8 @@ def test_fp32_blocked_sweep_on_the_matrix_cores(name, primal, gemm, tmp_path):
     b = P.rhs[0][dec.free]
     ref = gmres.gmres(lambda v: B.A @ v, B.apply, b, 1e-8, 30, 1000)
     x, info = s.mbddc_solve(P.rhs[0])
-    print(f"{name} gemm {gemm}: FP32 blocked sweep apply {err:.2e} (bound {bound:.1e}), its {info.iterations} "
-          f"(oracle {ref.iterations})")
+    print(f"{name} gemm {gemm}: FP32 blocked sweep coarse {err_c:.2e}, apply {err:.2e} (bound {bound:.1e}), "
+          f"its {info.iterations} (oracle {ref.iterations})")
     assert err <= bound
     assert info.rel_res_true <= 1e-8
     assert np.linalg.norm(b - B.A @ x[dec.free]) <= 1e-8 * np.linalg.norm(b)
