@@ -182,7 +182,8 @@ struct SymSet {
   GemmDesc* d_gd = nullptr;
   GemmItem* d_gitems = nullptr;
 
-  // Returns false when some matrix has no usable variant (FP32 beyond the LDS kernels).
+  // Returns false when some matrix has no usable variant (cannot happen while the blocked
+  // sweep, the last fallback, takes any size in either precision).
   bool build(const std::vector<GjDesc>& src, bool fp32, const Tuning& tune) {
     all.clear(); big.clear(); items.clear(); gd.clear(); gitems.clear();
     item_off.assign(1, 0);
